@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of one full TV-model EM iteration on one MI355X.
+
+A step is one pass of the whole hot path over the workload: frame posteriors
+against the full-covariance UBM over all C components, Baum-Welch n, f and S,
+the E-step, the M-step accumulators, the FP64 M-step solve (T and Sigma),
+minimum divergence and the UBM-mean realignment.
+
+Workload (default): D=60 features, C=2048 full-covariance components, R=400,
+4000 synthetic utterances of 500-1500 frames (~4M frames), seeded generator
+(``synth``).  ``value`` is utterances per second of whole EM iterations with
+the features resident in HBM; frame posteriors per second and the split of
+the step time are reported beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n-utts U] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TV EM utts/s + frame posteriors/s at C=2048,D=60,R=400 vs FP32 plain"
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--shape", type=int, default=2, help="workload shape id (synth.SHAPES)")
+    ap.add_argument("--n-utts", type=int, default=None, help="first U utterances only")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-utts", type=int, default=6)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, n_sample):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload.
+
+    Per-utterance work (posteriors over all C, n/f/S, E-step, accumulation)
+    is timed on the first ``n_sample`` utterances; the per-iteration fixed
+    work (V_c / U_c precompute, M-step solve, minimum divergence) is timed
+    once and spread over the workload's U utterances.  Returns utts/s of a
+    whole EM iteration at the workload's U.
+    """
+    import numpy as np
+    import oracle
+    from threadpoolctl import threadpool_info
+
+    a, b = 0, n_sample
+    off = wl.utt_off[: b + 1]
+    F = int(off[-1])
+    X = wl.X[:F]
+    tv = oracle.init_tv(wl.mu, wl.cov, wl.T_init)
+    t0 = time.perf_counter()
+    gamma, lse = oracle.posteriors(oracle.frame_loglik(X, wl.w, wl.mu, wl.cov))
+    n, f, S = oracle.bw_stats(X, off, gamma)
+    t_frame = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    V, Uc = oracle.tv_precompute(*tv[:2])
+    t_pre = time.perf_counter() - t0
+    del V, Uc
+    t0 = time.perf_counter()
+    e = oracle.estep(n, f, *tv)
+    acc = oracle.accumulate(n, f, e["phi"], e["Phi"])
+    t_utt = time.perf_counter() - t0 - t_pre  # estep() repeats the precompute
+    t0 = time.perf_counter()
+    T1, S1, _ = oracle.mstep(acc, S, tv[0], tv[1])
+    h, H = acc["hsum"] / acc["count"], acc["Hsum"] / acc["count"]
+    oracle.mindiv(h, H, T1)
+    t_fixed_m = time.perf_counter() - t0
+    U = wl.U
+    per_utt = (t_frame + max(t_utt, 0.0)) / n_sample
+    fixed = t_pre + t_fixed_m
+    total = per_utt * U + fixed
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    return {
+        "value": U / total,
+        "unit": "utts/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"first {n_sample} utterances ({F} frames) for posteriors, n/f/S, E-step and "
+                   f"accumulation; one V/U precompute, M-step solve and min-div; scaled to U={U} "
+                   f"(frame part {t_frame:.1f}s, E-step part {max(t_utt, 0):.1f}s, fixed "
+                   f"{fixed:.1f}s)"),
+        "frames_per_s": F / t_frame,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout "
+              "is described in DESIGN.md and not measured here.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1906_08556_amd import ivx
+
+    t0 = time.time()
+    wl = synth.make(args.shape, seed=args.seed, n_utts=args.n_utts)
+    sh = wl.shape
+    log(f"[bench] workload shape {args.shape}: U={wl.U} F={wl.F} D={sh.D} C={sh.C} R={sh.R} "
+        f"(generated in {time.time() - t0:.1f}s)")
+    C, D, R, U, F = sh.C, sh.D, sh.R, wl.U, wl.F
+    dev = torch.device("cuda", 0)
+    ctx = ivx.Context(C, D, R, U, F)
+    X = torch.from_numpy(wl.X).to(dev)
+    off = torch.from_numpy(wl.utt_off).to(dev)
+    ctx.set_ubm(torch.from_numpy(wl.w).to(dev), torch.from_numpy(wl.mu).to(dev),
+                torch.from_numpy(wl.cov).to(dev))
+    ctx.init_tv(torch.from_numpy(wl.T_init).to(dev), 100.0)
+    n = torch.empty((U, C), dtype=torch.float32, device=dev)
+    f = torch.empty((U, C, D), dtype=torch.float32, device=dev)
+    S = torch.zeros((C, D * (D + 1) // 2), dtype=torch.float64, device=dev)
+    ll_frames = torch.zeros(1, dtype=torch.float64, device=dev)
+    phi = torch.empty((U, R), dtype=torch.float32, device=dev)
+    Phi = torch.empty((U, R * (R + 1) // 2), dtype=torch.float32, device=dev)
+    ll_utt = torch.zeros(1, dtype=torch.float64, device=dev)
+    obj = torch.zeros(1, dtype=torch.float64, device=dev)
+    acc = ctx.new_accum()
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    phase = {"frame": 0.0, "em": 0.0}
+
+    def step(timed):
+        S.zero_()
+        ll_frames.zero_()
+        ll_utt.zero_()
+        acc.zero_()
+        if timed:
+            ev[0].record()
+        ctx.bw_stats(X, off, n, f, S_acc=S, ll_acc=ll_frames)
+        if timed:
+            ev[1].record()
+        ctx.tv_estep(n, f, phi, Phi=Phi, ll_acc=ll_utt)
+        ctx.tv_mstep_accumulate(n, f, phi, Phi, acc)
+        ctx.tv_mstep_solve(acc, S, update_sigma=True, ll_sum=ll_utt, objective=obj)
+        ctx.tv_mindiv(acc)
+        ctx.ubm_update_means()
+        if timed:
+            ev[2].record()
+
+    for _ in range(args.warmup):
+        step(False)
+    ctx.sync_status()
+    ctx.profile_enable(4096)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()  # phase events of this step complete
+        phase["frame"] += ev[0].elapsed_time(ev[1])
+        phase["em"] += ev[1].elapsed_time(ev[2])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = ctx.profile_read()
+    ctx.profile_enable(0)
+    ctx.sync_status()
+    K = args.steps
+    ms_step = elapsed * 1e3 / K
+    value = U * K / elapsed
+    frames_per_s = F * K / (phase["frame"] / 1e3)
+    em_utts_per_s = U * K / (phase["em"] / 1e3)
+
+    # roofline of the dominant kernel: the expanded-feature frame GEMM
+    Kexp = (D + 1) * (D + 2) // 2
+    flop_per_frame = 2.0 * Kexp * C
+    fs_ms, fs_calls = prof["frame_select"]
+    fs_avg_s = fs_ms / max(fs_calls, 1) / 1e3
+    achieved = flop_per_frame * F / fs_avg_s / 1e12
+    roof = {"kernel": "k_frame_select", "bound": "mfma", "achieved": round(achieved, 2),
+            "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+            "avg_launch_ms": round(fs_avg_s * 1e3, 3), "flop_per_frame": flop_per_frame}
+    log("[bench] kernel groups (ms per step): " + ", ".join(
+        f"{k}={v[0] / K:.2f}" for k, v in prof.items() if v[1]))
+    log(f"[bench] objective after last step: {obj.item():.6e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a bounded sample ...")
+        cpu = cpu_baseline(wl, min(args.cpu_sample_utts, U))
+        log(f"[bench] cpu baseline: {cpu['value']:.3f} utts/s, {cpu['frames_per_s']:.0f} frames/s "
+            f"({cpu['cores']} threads)")
+        cpu.pop("frames_per_s")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "utts/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"shape{args.shape}:{sh.name}", "D": D, "C": C, "R": R,
+                   "utterances": U, "frames": F,
+                   "step": "posteriors+n/f/S+E-step+accumulate+M-step(T,Sigma)+min-div+realign"},
+        "frame_posteriors_per_s": round(frames_per_s, 1),
+        "tv_em_utts_per_s": round(em_utts_per_s, 3),
+        "phase_ms_per_step": {"frame_stage": round(phase["frame"] / K, 3),
+                              "em_stage": round(phase["em"] / K, 3)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

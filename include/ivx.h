@@ -1,0 +1,236 @@
+/*
+ * ivx.h -- C ABI of the MI355X (gfx950) TV-model EM hot path.
+ *
+ * The operations follow Vestman, Lee, Kinnunen, Koshinaka, "Unleashing the
+ * Unused Potential of I-Vectors Enabled by GPU Acceleration" (Interspeech
+ * 2019), augmented formulation (Sec. 2.2): frame posteriors against a
+ * full-covariance UBM, Baum-Welch statistics (Sec. 2), the E-step of
+ * eqs. (3)-(4), the M-step of the factor-analysis EM cited in Sec. 2.1 and
+ * Sec. 3.2 step 3, minimum-divergence re-estimation of eqs. (6)-(12), and the
+ * UBM-mean realignment of Sec. 3.2.
+ *
+ * Conventions (every call):
+ *  - Pointers named as device pointers must point to memory on the context's
+ *    device; pointers named as host pointers to host memory.  The caller owns
+ *    every pointer argument and keeps it valid until the work queued on
+ *    `stream` has completed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Hot-path calls are asynchronous on `stream`: they never synchronise and
+ *    never allocate, so they can be captured in a HIP graph.
+ *  - Arrays are row-major, C-contiguous.  Sizes are in elements.
+ *  - "packed" symmetric R x R storage is the upper triangle row by row:
+ *    element (i, j), i <= j, at i*R - i*(i-1)/2 + (j - i); R(R+1)/2 entries.
+ *  - "tile-packed" symmetric R x R storage (ivx_tp_size(R) entries) splits
+ *    the matrix into 16 x 16 tiles (R padded up to a multiple of 16 with
+ *    zeros) and stores the tiles (bi, bj) with bi >= bj in the order
+ *    bi = 0..nb-1, bj = 0..bi, each tile as 16 x 16 row-major (rows of block
+ *    row bi, columns of block column bj).  Diagonal tiles are stored in full.
+ *  - The latent dimension R includes the prior-offset dimension, which is
+ *    index 0 (the paper's element 1).
+ *  - Argument errors are detected on the host before anything is queued and
+ *    return IVX_EINVAL (nothing is launched).  Problems found by kernels
+ *    (non-positive-definite matrices, non-finite values, malformed utterance
+ *    offsets, candidate-list overflow) set a flag in the context that
+ *    ivx_sync_status() reports; ivx_last_error() gives a message.
+ *  - One host thread at a time per context.  Separate contexts are
+ *    independent.
+ */
+#ifndef IVX_H
+#define IVX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ivx_ctx ivx_ctx;
+
+typedef enum {
+  IVX_OK = 0,
+  IVX_EINVAL = -1,     /* bad argument or dimension */
+  IVX_ENOMEM = -2,     /* device allocation failed (only in ivx_create) */
+  IVX_ENOTPD = -3,     /* a covariance / precision matrix is not positive definite */
+  IVX_EDEVICE = -4,    /* HIP runtime error */
+  IVX_ENUMERIC = -5,   /* non-finite value met by a kernel */
+  IVX_ECAPACITY = -6   /* more components within the posterior margin than the list holds */
+} ivx_status;
+
+typedef enum { IVX_FP32 = 0, IVX_BF16 = 1 } ivx_precision;
+typedef enum { IVX_SEL_ALL = 0, IVX_SEL_LEARNED = 1 } ivx_selection;
+
+/* Problem dimensions, fixed for the life of a context.
+ *   C  UBM components (>= 1), D feature dimension (1..63), R latent
+ *   dimension including the offset dimension (2..480).
+ *   max_batch_utts    largest U accepted by the utterance-batch calls.
+ *   max_batch_frames  largest F accepted by the frame-batch calls. */
+typedef struct {
+  int32_t C, D, R;
+  int32_t max_batch_utts;
+  int64_t max_batch_frames;
+} ivx_dims;
+
+/* M-step accumulators (all device pointers, FP64, caller-allocated and
+ * caller-zeroed; tv_mstep_accumulate adds to them).
+ *   A     [C][ivx_tp_size(R)]  A_c = sum_u n_c(u) (Phi(u) + phi(u) phi(u)^T), tile-packed
+ *   Cc    [C][D][R]            Cc_c = sum_u f_c(u) phi(u)^T
+ *   N     [C]                  N_c = sum_u n_c(u)
+ *   h     [R]                  sum_u phi(u)                (U * eq. (6))
+ *   H     [ivx_tp_size(R)]     sum_u Phi(u) + phi(u) phi(u)^T (U * eq. (7)), tile-packed
+ *   count [1]                  number of utterances accumulated (double) */
+typedef struct {
+  double* A;
+  double* Cc;
+  double* N;
+  double* h;
+  double* H;
+  double* count;
+} ivx_accum;
+
+/* ---------------------------------------------------------------- lifecycle */
+
+/* Creates a context on HIP device `device` and allocates all model storage
+ * and workspace for `dims` (the only call besides ivx_set_* that allocates).
+ * Returns IVX_EINVAL for bad dims, IVX_ENOMEM if allocation fails. */
+ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out);
+
+/* Frees everything the context owns.  NULL is ignored. */
+void ivx_destroy(ivx_ctx* ctx);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* ivx_last_error(void);
+
+/* Synchronises `stream`, then returns and clears the first error recorded by
+ * a kernel since the last call (IVX_OK if none). */
+ivx_status ivx_sync_status(ivx_ctx* ctx, void* stream);
+
+/* Number of doubles/floats in a tile-packed symmetric R x R matrix. */
+int64_t ivx_tp_size(int32_t R);
+
+/* ------------------------------------------------------------------- model */
+
+/* Loads the full-covariance UBM (Sec. 4.1): weights w [C], means mu [C][D],
+ * covariances cov [C][D][D] (device pointers, FP64) and derives the per-
+ * component Cholesky factors, log-determinants and the expanded
+ * quadratic-form coefficients used for the frame log-likelihoods.
+ * Synchronises `stream`; returns IVX_ENOTPD if a covariance is not positive
+ * definite. */
+ivx_status ivx_set_ubm(ivx_ctx* ctx, const double* w, const double* mu, const double* cov,
+                       void* stream);
+
+/* Augmented initialisation (Sec. 2.1-2.2): T_c <- T_rand_c (device, FP64
+ * [C][D][R], N(0,1) draws supplied by the caller) with column 0 replaced by
+ * mu_c / p0, Sigma_c <- UBM covariance, p <- p0 e_1.  Requires ivx_set_ubm. */
+ivx_status ivx_init_tv(ivx_ctx* ctx, const double* T_rand, double p0, void* stream);
+
+/* Sets / reads the TV model: T [C][D][R], Sigma [C][D][D], p [R] (device,
+ * FP64).  ivx_get_tv also returns the current UBM means mu [C][D]; any output
+ * pointer may be NULL. */
+ivx_status ivx_set_tv(ivx_ctx* ctx, const double* T, const double* Sigma, const double* p,
+                      void* stream);
+ivx_status ivx_get_tv(ivx_ctx* ctx, double* T, double* Sigma, double* p, double* mu,
+                      void* stream);
+
+/* ---------------------------------------------------------------- hot path */
+
+/* Frame posteriors gamma_tc = w_c N(x_t; mu_c, cov_c) / sum_c' (...)
+ * (frame alignment, Sec. 3.2 step 1 and Sec. 4.2) over ALL C components.
+ *   X         [F][D] FP32 device frames.
+ *   gamma     [F][C] FP32 dense posteriors, or NULL.
+ *   post_idx  [F][K] int32 / post_val [F][K] FP32: the components within the
+ *             candidate margin of each frame's best one and their posteriors
+ *             (unused slots: index -1, value 0), or NULL.  K must be 16.
+ *   frame_ll  [F] FP64 log sum_c w_c N(x_t; ...), or NULL.
+ * Components further than the margin (40 nats) below the best one carry a
+ * posterior below e^-40 relative to it and are reported as 0. */
+ivx_status ubm_posteriors(ivx_ctx* ctx, const float* X, int64_t F, ivx_precision prec,
+                          ivx_selection sel, float* gamma, int32_t* post_idx, float* post_val,
+                          int32_t K, double* frame_ll, void* stream);
+
+/* Uncentred Baum-Welch statistics of U utterances (Sec. 2):
+ *   X        [F][D] FP32 device frames, utterances concatenated.
+ *   utt_off  [U+1] int64 device offsets: utt_off[0] = 0, non-decreasing,
+ *            utt_off[U] = F (checked by a kernel).
+ *   n        [U][C] FP32  n_c(u) = sum_t gamma_tc
+ *   f        [U][C][D] FP32  f_c(u) = sum_t gamma_tc x_t
+ *   S_acc    [C][D(D+1)/2] FP64, packed: S_c += sum_t gamma_tc x_t x_t^T, or NULL
+ *   ll_acc   [1] FP64: += sum_t log p(x_t | UBM), or NULL */
+ivx_status bw_stats(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_t U, int64_t F,
+                    ivx_precision prec, ivx_selection sel, float* n, float* f, double* S_acc,
+                    double* ll_acc, void* stream);
+
+/* E-step, eqs. (3)-(4), for U utterances (U <= max_batch_utts):
+ *   L(u) = I + sum_c n_c(u) T_c^T Sigma_c^{-1} T_c,  b(u) = p + sum_c T_c^T Sigma_c^{-1} f_c(u)
+ *   phi  [U][R] FP32  phi(u) = L(u)^{-1} b(u)
+ *   Phi  [U][R(R+1)/2] FP32 packed Phi(u) = L(u)^{-1}, or NULL
+ *   ll_acc [1] FP64 += sum_u (-1/2 log|L(u)| + 1/2 b(u)^T phi(u) - 1/2 p^T p), or NULL
+ *   info [U] int32: 0, or k > 0 if the Cholesky factorisation of L(u) met a
+ *        non-positive pivot at row k-1 (that utterance's outputs are then
+ *        undefined), or NULL.
+ * n, f are the device arrays produced by bw_stats. */
+ivx_status tv_estep(ivx_ctx* ctx, const float* n, const float* f, int64_t U,
+                    ivx_precision prec, float* phi, float* Phi, double* ll_acc, int32_t* info,
+                    void* stream);
+
+/* Adds the M-step sufficient statistics of U utterances to `acc` (see
+ * ivx_accum): n [U][C], f [U][C][D], phi [U][R], Phi [U][R(R+1)/2] packed
+ * (device, FP32, as produced by bw_stats / tv_estep).  `acc` itself is a
+ * host struct of device pointers. */
+ivx_status tv_mstep_accumulate(ivx_ctx* ctx, const float* n, const float* f, const float* phi,
+                               const float* Phi, int64_t U, const ivx_accum* acc, void* stream);
+
+/* i-vector extraction (Sec. 3.2, last paragraph): posteriors against the
+ * current (possibly realigned) UBM, n and f, then eq. (4).
+ *   phi [U][R] FP32.  X, utt_off as in bw_stats. */
+ivx_status extract_ivectors(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_t U,
+                            int64_t F, ivx_precision prec, ivx_selection sel, float* phi,
+                            void* stream);
+
+/* ------------------------------------------------------ iteration finalise */
+
+/* M-step (Sec. 3.2 step 3), FP64: for every component with N_c >= 1,
+ *   T_c <- Cc_c A_c^{-1};  if update_sigma: Sigma_c <- sym((S_c - T_c Cc_c^T) / N_c)
+ * S [C][D(D+1)/2] FP64 packed (from bw_stats).  acc->A is overwritten by the
+ * Cholesky factors of A_c.  A new Sigma_c that is not positive definite is
+ * rejected (old one kept) and flagged in `status`.
+ *   objective [1] FP64 or NULL: receives the EM objective at the incoming
+ *     parameters, sum_c N_c(-D/2 log 2pi - 1/2 log|Sigma_c|)
+ *     - 1/2 sum_c tr(Sigma_c^{-1} S_c) + ll_sum, where ll_sum is read from
+ *     ll_sum_dev [1] (the tv_estep ll_acc of the same pass).
+ *   status [C] int32 or NULL: 0 updated, 1 skipped (N_c < 1), 2 Sigma not PD
+ *     (T updated, Sigma kept), 3 A_c not PD (nothing updated). */
+ivx_status tv_mstep_solve(ivx_ctx* ctx, const ivx_accum* acc, const double* S, int update_sigma,
+                          const double* ll_sum_dev, double* objective, int32_t* status,
+                          void* stream);
+
+/* Minimum-divergence re-estimation, augmented formulation (eqs. (6)-(12)),
+ * from acc->h, acc->H, acc->count: G = H/U - (h/U)(h/U)^T, P1 = L_G^{-1}
+ * (Cholesky whitening, method 0; other methods return IVX_EINVAL),
+ * Householder P2, T_c <- T_c P1^{-1} P2^{-1}, p <- P2 P1 h. */
+ivx_status tv_mindiv(ivx_ctx* ctx, const ivx_accum* acc, int method, void* stream);
+
+/* Realignment (Sec. 3.2 step 5): mu_c <- p[0] * T_c[:, 0], then re-derives
+ * the UBM quantities used by ubm_posteriors. */
+ivx_status ubm_update_means(ivx_ctx* ctx, void* stream);
+
+/* ----------------------------------------------------------------- tracing */
+
+/* Opt-in kernel timing with HIP events recorded on the stream each kernel
+ * group is launched on.  ivx_profile_enable(ctx, capacity) creates
+ * `capacity` event pairs (capacity 0 disables and frees them; it
+ * synchronises the device).  ivx_profile_read() synchronises the device, adds
+ * the elapsed milliseconds of every completed pair to ms[k] and its count to
+ * calls[k] for the kernel groups k = 0..n-1 (host arrays of length n, n <= the
+ * number of groups), then resets the pairs.  Groups: 0 frame-select GEMM,
+ * 1 rescoring, 2 n/f statistics, 3 second-order statistics, 4 TV precompute,
+ * 5 E-step GEMMs, 6 E-step Cholesky/solve/inverse, 7 accumulators, 8 M-step
+ * solve, 9 minimum divergence, 10 UBM preparation.  Pairs beyond the capacity
+ * are not recorded. */
+ivx_status ivx_profile_enable(ivx_ctx* ctx, int32_t capacity);
+ivx_status ivx_profile_read(ivx_ctx* ctx, double* ms, int64_t* calls, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IVX_H */

@@ -1,0 +1,255 @@
+// C ABI entry points of the E-step, the M-step and extraction.
+#include <cstdio>
+
+#include "ivx_internal.h"
+#include "ivx_tv.h"
+#include "k_gemm.h"
+
+using namespace ivx;
+
+#define IVX_CHECK(cond, ...)  \
+  do {                        \
+    if (!(cond)) {            \
+      set_error(__VA_ARGS__); \
+      return IVX_EINVAL;      \
+    }                         \
+  } while (0)
+
+namespace {
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+ivx_status after_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("%s: kernel launch failed: %s", what, hipGetErrorString(e));
+    return IVX_EDEVICE;
+  }
+  return IVX_OK;
+}
+
+ivx_status gemm(const GemmArgs& g, bool ta, bool tb, int epi, int batches, hipStream_t s,
+                const char* what) {
+  if (!gemm_f32(g, ta, tb, epi, batches, s)) {
+    set_error("%s: GEMM variant not available", what);
+    return IVX_EDEVICE;
+  }
+  return IVX_OK;
+}
+
+// Recomputes V_c, U_c (and Sigma_c^{-1}, log|Sigma_c|) after the TV model changed.
+ivx_status ensure_tv(ivx_ctx* ctx, hipStream_t s) {
+  if (!ctx->tv_dirty) return IVX_OK;
+  ProfScope ps(ctx, PK_TV_PREP, s);
+  launch_tv_prep(ctx, s);
+  GemmArgs g;
+  g.A = ctx->Y32;
+  g.B = ctx->Y32;
+  g.C = ctx->Utp;
+  g.lda = ctx->R;
+  g.ldb = ctx->R;
+  g.ldc = 0;
+  g.M = ctx->R;
+  g.N = ctx->R;
+  g.K = ctx->D;
+  g.sA = (int64_t)ctx->D * ctx->R;
+  g.sB = g.sA;
+  g.sC = ctx->TP;
+  ivx_status st = gemm(g, true, false, GEMM_STORE_TP, ctx->C, s, "tv precompute");
+  if (st != IVX_OK) return st;
+  ctx->tv_dirty = false;
+  return IVX_OK;
+}
+
+ivx_status estep_impl(ivx_ctx* ctx, const float* n, const float* f, int64_t U, float* phi,
+                      float* Phi, double* ll_acc, int32_t* info, hipStream_t s) {
+  ivx_status st = ensure_tv(ctx, s);
+  if (st != IVX_OK) return st;
+  const int C = ctx->C, D = ctx->D, R = ctx->R;
+  int slot = prof_begin(ctx, PK_ESTEP_GEMM, s);
+  // L(u) = I + sum_c n_c(u) U_c
+  GemmArgs gl;
+  gl.A = n;
+  gl.lda = C;
+  gl.B = ctx->Utp;
+  gl.ldb = ctx->TP;
+  gl.C = ctx->Lbuf;
+  gl.ldc = ctx->TP;
+  gl.M = (int)U;
+  gl.N = (int)ctx->TP;
+  gl.K = C;
+  if ((st = gemm(gl, false, false, GEMM_STORE, 1, s, "tv_estep")) != IVX_OK) return st;
+  launch_add_identity(ctx, ctx->Lbuf, U, s);
+  // b(u) = p + sum_c V_c^T f_c(u), split over K = C*D
+  const int64_t K = (int64_t)C * D;
+  const int64_t tiles = ((U + 127) / 128) * ((R + 127) / 128);
+  int64_t ns = (1024 + tiles - 1) / tiles;
+  if (ns > ctx->nsplit_max) ns = ctx->nsplit_max;
+  if (ns < 1) ns = 1;
+  int64_t kchunk = (K + ns - 1) / ns;
+  kchunk = (kchunk + 15) / 16 * 16;
+  ns = (K + kchunk - 1) / kchunk;
+  GemmArgs gb;
+  gb.A = f;
+  gb.lda = K;
+  gb.B = ctx->V32;
+  gb.ldb = R;
+  gb.C = ctx->bpart;
+  gb.ldc = R;
+  gb.sS = U * R;
+  gb.M = (int)U;
+  gb.N = R;
+  gb.K = (int)K;
+  gb.ksplit = (int)ns;
+  gb.kchunk = (int)kchunk;
+  if ((st = gemm(gb, false, false, GEMM_STORE, 1, s, "tv_estep")) != IVX_OK) return st;
+  launch_reduce_b(ctx, ctx->bpart, (int)ns, U * R, U, ctx->bvec, s);
+  prof_end(ctx, slot, s);
+  {
+    ProfScope ps(ctx, PK_ESTEP_CHOL, s);
+    launch_estep_chol(ctx, U, ctx->Lbuf, ctx->Wbuf, ctx->bvec, phi, ctx->llu, info, Phi != nullptr, s);
+  }
+  if (ll_acc) launch_sum_f64(ctx, ctx->llu, U, ll_acc, s);
+  if (Phi) launch_tp_to_packed(ctx, ctx->Lbuf, U, Phi, s);
+  return after_launch("tv_estep");
+}
+
+}  // namespace
+
+extern "C" {
+
+ivx_status tv_estep(ivx_ctx* ctx, const float* n, const float* f, int64_t U, ivx_precision prec,
+                    float* phi, float* Phi, double* ll_acc, int32_t* info, void* stream) {
+  IVX_CHECK(ctx, "tv_estep: null context");
+  IVX_CHECK(ctx->tv_set, "tv_estep: no TV model (ivx_init_tv / ivx_set_tv)");
+  IVX_CHECK(U >= 0 && U <= ctx->maxU, "tv_estep: U=%lld outside [0, max_batch_utts=%d]",
+            (long long)U, ctx->maxU);
+  IVX_CHECK(U == 0 || (n && f && phi), "tv_estep: null n / f / phi");
+  IVX_CHECK(prec == IVX_FP32, "tv_estep: precision %d not available in this build", (int)prec);
+  if (U == 0) return IVX_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    set_error("tv_estep: hipSetDevice failed");
+    return IVX_EDEVICE;
+  }
+  return estep_impl(ctx, n, f, U, phi, Phi, ll_acc, info, as_stream(stream));
+}
+
+ivx_status tv_mstep_accumulate(ivx_ctx* ctx, const float* n, const float* f, const float* phi,
+                               const float* Phi, int64_t U, const ivx_accum* acc, void* stream) {
+  IVX_CHECK(ctx && acc, "tv_mstep_accumulate: null argument");
+  IVX_CHECK(U >= 0 && U <= ctx->maxU, "tv_mstep_accumulate: U=%lld outside [0, %d]",
+            (long long)U, ctx->maxU);
+  IVX_CHECK(U == 0 || (n && f && phi && Phi), "tv_mstep_accumulate: null input");
+  IVX_CHECK(acc->A && acc->Cc && acc->N && acc->h && acc->H && acc->count,
+            "tv_mstep_accumulate: null accumulator");
+  if (U == 0) return IVX_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    set_error("tv_mstep_accumulate: hipSetDevice failed");
+    return IVX_EDEVICE;
+  }
+  hipStream_t s = as_stream(stream);
+  const int C = ctx->C, D = ctx->D, R = ctx->R;
+  ProfScope ps(ctx, PK_ACCUM, s);
+  launch_packed_to_psi(ctx, Phi, phi, U, ctx->Wbuf, s);
+  // A_c += sum_u n_c(u) Psi(u)
+  GemmArgs ga;
+  ga.A = n;
+  ga.lda = C;
+  ga.B = ctx->Wbuf;
+  ga.ldb = ctx->TP;
+  ga.C = acc->A;
+  ga.ldc = ctx->TP;
+  ga.M = C;
+  ga.N = (int)ctx->TP;
+  ga.K = (int)U;
+  ivx_status st = gemm(ga, true, false, GEMM_ADD_F64, 1, s, "tv_mstep_accumulate");
+  if (st != IVX_OK) return st;
+  // Cc_c += sum_u f_c(u) phi(u)^T
+  GemmArgs gc;
+  gc.A = f;
+  gc.lda = (int64_t)C * D;
+  gc.B = phi;
+  gc.ldb = R;
+  gc.C = acc->Cc;
+  gc.ldc = R;
+  gc.M = C * D;
+  gc.N = R;
+  gc.K = (int)U;
+  if ((st = gemm(gc, true, false, GEMM_ADD_F64, 1, s, "tv_mstep_accumulate")) != IVX_OK) return st;
+  launch_colsums(ctx, n, phi, ctx->Wbuf, U, acc, s);
+  return after_launch("tv_mstep_accumulate");
+}
+
+ivx_status extract_ivectors(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_t U,
+                            int64_t F, ivx_precision prec, ivx_selection sel, float* phi,
+                            void* stream) {
+  IVX_CHECK(ctx, "extract_ivectors: null context");
+  IVX_CHECK(ctx->ubm_set && ctx->tv_set, "extract_ivectors: UBM and TV model required");
+  IVX_CHECK(U >= 1 && U <= ctx->maxU, "extract_ivectors: U=%lld outside [1, %d]", (long long)U,
+            ctx->maxU);
+  IVX_CHECK(F >= 0 && F <= ctx->maxF, "extract_ivectors: F=%lld outside [0, %lld]", (long long)F,
+            (long long)ctx->maxF);
+  IVX_CHECK(utt_off && phi && (F == 0 || X), "extract_ivectors: null argument");
+  IVX_CHECK(prec == IVX_FP32 && sel == IVX_SEL_ALL, "extract_ivectors: mode not available");
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    set_error("extract_ivectors: hipSetDevice failed");
+    return IVX_EDEVICE;
+  }
+  hipStream_t s = as_stream(stream);
+  {
+    ProfScope ps(ctx, PK_FRAME_SELECT, s);
+    launch_frame_select(ctx, X, F, s);
+  }
+  {
+    ProfScope ps(ctx, PK_RESCORE, s);
+    launch_rescore(ctx, X, F, ctx->post_idx, ctx->post_val, ctx->frame_ll, s);
+  }
+  {
+    ProfScope ps(ctx, PK_STATS_NF, s);
+    launch_stats_nf(ctx, X, utt_off, U, F, ctx->n_ws, ctx->f_ws, s);
+  }
+  ivx_status st = after_launch("extract_ivectors");
+  if (st != IVX_OK) return st;
+  return estep_impl(ctx, ctx->n_ws, ctx->f_ws, U, phi, nullptr, nullptr, nullptr, s);
+}
+
+ivx_status tv_mstep_solve(ivx_ctx* ctx, const ivx_accum* acc, const double* S, int update_sigma,
+                          const double* ll_sum_dev, double* objective, int32_t* status,
+                          void* stream) {
+  IVX_CHECK(ctx && acc && S, "tv_mstep_solve: null argument");
+  IVX_CHECK(ctx->tv_set, "tv_mstep_solve: no TV model");
+  IVX_CHECK(acc->A && acc->Cc && acc->N, "tv_mstep_solve: null accumulator");
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    set_error("tv_mstep_solve: hipSetDevice failed");
+    return IVX_EDEVICE;
+  }
+  hipStream_t s = as_stream(stream);
+  ivx_status st = ensure_tv(ctx, s);
+  if (st != IVX_OK) return st;
+  {
+    ProfScope ps(ctx, PK_MSTEP, s);
+    if (objective) launch_objective(ctx, acc->N, S, ll_sum_dev, objective, s);
+    launch_mstep_solve(ctx, acc, S, update_sigma, status ? status : ctx->mstat, s);
+  }
+  ctx->tv_dirty = true;
+  return after_launch("tv_mstep_solve");
+}
+
+ivx_status tv_mindiv(ivx_ctx* ctx, const ivx_accum* acc, int method, void* stream) {
+  IVX_CHECK(ctx && acc, "tv_mindiv: null argument");
+  IVX_CHECK(ctx->tv_set, "tv_mindiv: no TV model");
+  IVX_CHECK(acc->h && acc->H && acc->count, "tv_mindiv: null accumulator");
+  IVX_CHECK(method == 0, "tv_mindiv: method %d not available (0 = Cholesky whitening)", method);
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    set_error("tv_mindiv: hipSetDevice failed");
+    return IVX_EDEVICE;
+  }
+  {
+    ProfScope ps(ctx, PK_MINDIV, as_stream(stream));
+    launch_mindiv(ctx, acc, as_stream(stream));
+  }
+  ctx->tv_dirty = true;
+  return after_launch("tv_mindiv");
+}
+
+}  // extern "C"

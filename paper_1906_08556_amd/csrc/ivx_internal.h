@@ -1,0 +1,162 @@
+// Internal declarations shared by the host API and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/ivx.h"
+
+namespace ivx {
+
+// Posterior list capacity per frame (entries of post_idx / post_val).
+constexpr int KP = 16;
+// Candidate margin in nats: components whose expanded-form log-likelihood is
+// more than this below the frame's best are dropped (their posterior is below
+// e^-40 relative to the best one).  The FP32 expanded form is accurate to far
+// better than 1 nat on the working range, so the margin also absorbs its error.
+constexpr float kMargin = 40.0f;
+// Tile size of the tile-packed symmetric layout.
+constexpr int TB = 16;
+
+// Kernel groups timed by the opt-in event profiler (ivx_profile_*).
+enum ProfKernel {
+  PK_FRAME_SELECT = 0,  // expanded-feature MFMA GEMM + running max + candidates
+  PK_RESCORE,           // FP64 candidate rescoring and posteriors
+  PK_STATS_NF,          // n, f
+  PK_STATS_S,           // second-order statistics
+  PK_TV_PREP,           // V_c, U_c
+  PK_ESTEP_GEMM,        // precision assembly + linear term GEMMs
+  PK_ESTEP_CHOL,        // per-utterance Cholesky, solve, inverse
+  PK_ACCUM,             // M-step accumulator GEMMs and sums
+  PK_MSTEP,             // FP64 M-step solve and objective
+  PK_MINDIV,            // minimum divergence
+  PK_UBM,               // UBM preparation / realignment
+  PK_COUNT
+};
+
+inline int64_t tp_size(int R) {
+  int64_t nb = (R + TB - 1) / TB;
+  return nb * (nb + 1) / 2 * TB * TB;
+}
+
+// Records a message for ivx_last_error() (printf-style).
+void set_error(const char* fmt, ...);
+
+// Device-side error codes written (first one wins) into ctx->dev_err.
+__device__ inline void raise_error(int* err, int code) {
+  if (err) atomicCAS(err, 0, code);
+}
+
+}  // namespace ivx
+
+struct ivx_ctx {
+  int device = 0;
+  int C = 0, D = 0, R = 0;
+  int maxU = 0;
+  int64_t maxF = 0;
+  int K = 0;       // expanded features (D+1)(D+2)/2
+  int Kpad = 0;    // K rounded up to a multiple of 8
+  int Cpad = 0;    // C rounded up to a multiple of 256 (frame GEMM tile)
+  int Dp = 0;      // D(D+1)/2
+  int64_t TP = 0;  // tile-packed size for R
+  bool ubm_set = false;
+  bool tv_set = false;
+
+  // UBM, FP64 master copy
+  double* w = nullptr;      // [C]
+  double* mu = nullptr;     // [C][D]
+  double* cov = nullptr;    // [C][D][D]
+  // UBM-derived
+  float* shift = nullptr;     // [D] global mean shift applied before expansion
+  float* Wexp = nullptr;      // [Cpad][Kpad] expanded quadratic-form coefficients
+  double* linv = nullptr;     // [C][Dp] L_c^{-1}, lower triangle column by column
+  double* cst = nullptr;      // [C] log w_c - D/2 log 2pi - sum_i log L_c[i,i]
+  uint16_t* pairs = nullptr;  // [Kpad] expanded-feature index pairs (a | b << 8)
+
+  // TV model, FP64 master copy
+  double* T = nullptr;      // [C][D][R]
+  double* Sigma = nullptr;  // [C][D][D]
+  double* p = nullptr;      // [R]
+
+  // frame-stage workspace
+  int* cand = nullptr;        // [maxF][KP]
+  int* cflag = nullptr;       // [maxF]
+  int* post_idx = nullptr;    // [maxF][KP]
+  float* post_val = nullptr;  // [maxF][KP]
+  double* frame_ll = nullptr; // [maxF]
+  int* hist = nullptr;        // [nhist][C]
+  int* coff = nullptr;        // [C+1]
+  int2* ent = nullptr;        // [maxF*KP] component-sorted (frame, gamma bits)
+  double* partial = nullptr;  // [1024] reduction partials
+  int nhist = 0;
+
+  // TV-derived quantities (recomputed when the TV model changes)
+  bool tv_dirty = true;
+  float* Y32 = nullptr;       // [C][D][R] L_c^{-1} T_c
+  float* V32 = nullptr;       // [C][D][R] Sigma_c^{-1} T_c
+  float* Utp = nullptr;       // [C][TP]   T_c^T Sigma_c^{-1} T_c, tile-packed
+  double* Psig = nullptr;     // [C][D][D] Sigma_c^{-1}
+  double* sig_logdet = nullptr;  // [C]   log|Sigma_c|
+
+  // utterance-batch workspace
+  int nsplit_max = 64;
+  float* Lbuf = nullptr;      // [maxU][TP] L(u) -> G -> Phi(u)
+  float* Wbuf = nullptr;      // [maxU][TP] G^{-1}, or Psi(u) in the accumulate call
+  float* bpart = nullptr;     // [nsplit_max][maxU][R]
+  float* bvec = nullptr;      // [maxU][R]
+  double* llu = nullptr;      // [maxU]
+  float* n_ws = nullptr;      // [maxU][C]   (extract_ivectors)
+  float* f_ws = nullptr;      // [maxU][C][D]
+
+  // M-step / minimum-divergence workspace
+  double* Tnew = nullptr;     // [C][D][R]
+  double* obj_part = nullptr; // [C]
+  double* Gmat = nullptr;     // [R][R]
+  double* Mmat = nullptr;     // [R][R]
+  double* mvec = nullptr;     // [4][R]
+  int* mstat = nullptr;       // [C]
+
+  int* dev_err = nullptr;     // [2]: first error code, smallest failing index
+
+  // event profiler (off unless ivx_profile_enable)
+  bool prof_on = false;
+  int prof_cap = 0, prof_used = 0;
+  hipEvent_t* prof_ev = nullptr;  // [2 * prof_cap]
+  int* prof_kind = nullptr;       // [prof_cap]
+};
+
+namespace ivx {
+// Records a start event for kernel group k on stream s; returns a slot or -1.
+int prof_begin(ivx_ctx* ctx, int k, hipStream_t s);
+void prof_end(ivx_ctx* ctx, int slot, hipStream_t s);
+struct ProfScope {
+  ivx_ctx* ctx;
+  hipStream_t s;
+  int slot;
+  ProfScope(ivx_ctx* c, int k, hipStream_t st) : ctx(c), s(st), slot(prof_begin(c, k, st)) {}
+  ~ProfScope() { prof_end(ctx, slot, s); }
+};
+}  // namespace ivx
+
+namespace ivx {
+
+// ---- k_ubm.hip
+void launch_ubm_prepare(ivx_ctx* ctx, hipStream_t s);
+void launch_init_tv(ivx_ctx* ctx, const double* T_rand, double p0, hipStream_t s);
+void launch_update_means(ivx_ctx* ctx, hipStream_t s);
+
+// ---- k_frame.hip
+void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, hipStream_t s);
+void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int* post_idx, float* post_val,
+                    double* frame_ll, hipStream_t s);
+void launch_dense_gamma(ivx_ctx* ctx, int64_t F, const int* post_idx, const float* post_val,
+                        float* gamma, hipStream_t s);
+
+// ---- k_stats.hip
+void launch_stats_nf(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_t U, int64_t F,
+                     float* n, float* f, hipStream_t s);
+void launch_stats_S(ivx_ctx* ctx, const float* X, int64_t F, double* S_acc, hipStream_t s);
+void launch_sum_f64(ivx_ctx* ctx, const double* x, int64_t n, double* acc, hipStream_t s);
+
+}  // namespace ivx

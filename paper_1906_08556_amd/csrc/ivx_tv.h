@@ -1,0 +1,28 @@
+// Launchers of the E-step / M-step kernels (k_tv.hip, k_mstep.hip).
+#pragma once
+
+#include "ivx_internal.h"
+
+namespace ivx {
+
+// ---- k_tv.hip
+void launch_tv_prep(ivx_ctx* ctx, hipStream_t s);
+void launch_add_identity(ivx_ctx* ctx, float* L, int64_t U, hipStream_t s);
+void launch_reduce_b(ivx_ctx* ctx, const float* part, int nsplit, int64_t sstride, int64_t U,
+                     float* b, hipStream_t s);
+void launch_estep_chol(ivx_ctx* ctx, int64_t U, float* Lb, float* Wb, const float* b, float* phi,
+                       double* llu, int* info, bool want_cov, hipStream_t s);
+void launch_tp_to_packed(ivx_ctx* ctx, const float* Ptp, int64_t U, float* out, hipStream_t s);
+void launch_packed_to_psi(ivx_ctx* ctx, const float* Phi, const float* phi, int64_t U, float* Psi,
+                          hipStream_t s);
+void launch_colsums(ivx_ctx* ctx, const float* n, const float* phi, const float* Psi, int64_t U,
+                    const ivx_accum* acc, hipStream_t s);
+
+// ---- k_mstep.hip
+void launch_objective(ivx_ctx* ctx, const double* N, const double* S, const double* ll_sum,
+                      double* objective, hipStream_t s);
+void launch_mstep_solve(ivx_ctx* ctx, const ivx_accum* acc, const double* S, int update_sigma,
+                        int* status, hipStream_t s);
+void launch_mindiv(ivx_ctx* ctx, const ivx_accum* acc, hipStream_t s);
+
+}  // namespace ivx

@@ -1,0 +1,296 @@
+// Frame posteriors against the full-covariance UBM over all C components.
+//
+// Stage 1 (k_frame_select): the log-likelihood of every (frame, component)
+// pair is one dot product of the expanded feature vector vech(x~ x~^T),
+// x~ = [1, x - s], with the component's coefficient row (see k_ubm.hip).  The
+// product runs on MFMA (v_mfma_f32_32x32x2_f32) with components on the M side
+// and frames on the N side, so each lane ends a component tile holding 128
+// log-likelihoods of one frame.  A running per-frame maximum and a short list
+// of components within kMargin nats of it are kept across component tiles:
+// the [F x C] log-likelihood matrix never leaves registers.
+//
+// Stage 2 (k_rescore): every surviving candidate is rescored exactly in FP64,
+// l = const_c - 1/2 || L_c^{-1} (x - mu_c) ||^2, and the posteriors follow
+// from a log-sum-exp over the candidates.  Frames whose candidate list
+// overflowed are rescored over all C components.
+#include <cmath>
+
+#include "ivx_internal.h"
+
+namespace ivx {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int FR = 32;        // frames per wave (one 32-frame MFMA block)
+constexpr int NW = 4;         // waves per workgroup
+constexpr int FT = FR * NW;   // frames per workgroup
+constexpr int NCB = 8;        // 32-component MFMA blocks per tile
+constexpr int CT = 32 * NCB;  // components per tile
+constexpr int CAPL = KP / 2;  // candidate slots per lane-half per frame
+
+__device__ inline void append_cand(int2* list, int& cnt, bool& ovf, int comp, float val,
+                                   float thr) {
+  if (cnt == CAPL) {  // drop entries that fell below the running threshold
+    int w = 0;
+    for (int s = 0; s < CAPL; ++s) {
+      const int2 e = list[s * 64];
+      if (__int_as_float(e.y) >= thr) list[(w++) * 64] = e;
+    }
+    cnt = w;
+  }
+  if (cnt < CAPL) {
+    list[cnt * 64] = make_int2(comp, __float_as_int(val));
+    ++cnt;
+  } else {
+    ovf = true;
+  }
+}
+
+__global__ void __launch_bounds__(256, 2)
+k_frame_select(const float* __restrict__ X, int64_t F, int D, const float* __restrict__ shift,
+               const float* __restrict__ W, int C, int Cpad, int Kpad,
+               const uint16_t* __restrict__ pairs, float margin, int* __restrict__ cand,
+               int* __restrict__ cflag) {
+  extern __shared__ float smem[];
+  const int DS = D + 1;
+  float* xs = smem;                                                  // [FT][DS]
+  int2* cl = reinterpret_cast<int2*>(smem + ((FT * DS + 1) & ~1));  // [NW][CAPL][64]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t f0 = (int64_t)blockIdx.x * FT;
+
+  for (int i = tid; i < FT * DS; i += 256) {
+    const int fr = i / DS, a = i - fr * DS;
+    const int64_t g = f0 + fr;
+    float v = (a == 0) ? 1.0f : 0.0f;
+    if (a > 0 && g < F) v = X[g * D + (a - 1)] - shift[a - 1];
+    xs[i] = v;
+  }
+  __syncthreads();
+
+  const int h = lane >> 5, l32 = lane & 31;
+  const float* xw = xs + (wave * FR + l32) * DS;
+  int2* lst = cl + wave * CAPL * 64 + lane;
+  float M = -INFINITY;
+  int cnt = 0;
+  bool ov = false;
+  const int nq = Kpad / 8;
+
+  for (int c0 = 0; c0 < Cpad; c0 += CT) {
+    floatx16 acc[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = floatx16{0};
+    const float* wp = W + (size_t)(c0 + l32) * Kpad + 4 * h;
+    float4 wn[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      wn[cb] = *reinterpret_cast<const float4*>(wp + (size_t)cb * 32 * Kpad);
+    uint2 pn = *reinterpret_cast<const uint2*>(pairs + 4 * h);
+    for (int q = 0; q < nq; ++q) {
+      float4 wc[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) wc[cb] = wn[cb];
+      const uint2 pc = pn;
+      const int qn = (q + 1 < nq) ? (q + 1) : q;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        wn[cb] = *reinterpret_cast<const float4*>(wp + (size_t)cb * 32 * Kpad + 8 * qn);
+      pn = *reinterpret_cast<const uint2*>(pairs + 8 * qn + 4 * h);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const uint32_t pr = ((s < 2) ? pc.x : pc.y) >> ((s & 1) * 16);
+        const int a = pr & 0xff, b = (pr >> 8) & 0xff;
+        const float bv = xw[a] * xw[b];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const float av = (s == 0) ? wc[cb].x : (s == 1) ? wc[cb].y : (s == 2) ? wc[cb].z : wc[cb].w;
+          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[cb], 0, 0, 0);
+        }
+      }
+    }
+    // epilogue: lane holds frame l32 and rows 8*(r/4) + 4*h + r%4 of each
+    // 32-component block; its partner lane (lane ^ 32) holds the other rows
+    float vmax = -INFINITY;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) vmax = fmaxf(vmax, acc[cb][r]);
+    const float lmax = vmax;
+    vmax = fmaxf(vmax, __shfl_xor(vmax, 32));
+    M = fmaxf(M, vmax);
+    const float thr = M - margin;
+    if (lmax >= thr) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float v = acc[cb][r];
+          const int comp = c0 + cb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+          if (v >= thr && comp < C) append_cand(lst, cnt, ov, comp, v, thr);
+        }
+    }
+  }
+  // final candidate list: half h writes slots h*CAPL .. h*CAPL + CAPL-1
+  const float thr = M - margin;
+  const int ovi = ov ? 1 : 0;
+  const int ovp = __shfl_xor(ovi, 32);
+  const int64_t g = f0 + wave * FR + l32;
+  if (g < F) {
+#pragma unroll
+    for (int s = 0; s < CAPL; ++s) {
+      int v = -1;
+      if (s < cnt) {
+        const int2 e = lst[s * 64];
+        if (__int_as_float(e.y) >= thr) v = e.x;
+      }
+      cand[g * KP + h * CAPL + s] = v;
+    }
+    if (h == 0) cflag[g] = ovi | ovp;
+  }
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Exact FP64 log w_c N(x; mu_c, Sigma_c) for the wave's frame; every lane
+// returns the same value.  xd: lane's feature (0 for lanes >= D); dsh: 64
+// doubles of wave-private LDS.
+__device__ inline double exact_ll(int c, double xd, int lane, int D, int Dp,
+                                  const double* __restrict__ mu, const double* __restrict__ linv,
+                                  const double* __restrict__ cst, double* dsh) {
+  const double d = (lane < D) ? (xd - mu[(size_t)c * D + lane]) : 0.0;
+  dsh[lane] = d;
+  __builtin_amdgcn_wave_barrier();
+  const double* Lc = linv + (size_t)c * Dp;
+  double y = 0.0;
+  int col = 0;
+  for (int j = 0; j < D; ++j) {
+    const double dj = dsh[j];
+    if (lane >= j && lane < D) y += Lc[col + (lane - j)] * dj;
+    col += D - j;
+  }
+  __builtin_amdgcn_wave_barrier();
+  return cst[c] - 0.5 * wave_sum(y * y);
+}
+
+__global__ void __launch_bounds__(256)
+k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __restrict__ mu,
+          const double* __restrict__ linv, const double* __restrict__ cst,
+          const int* __restrict__ cand, const int* __restrict__ cflag, double margin,
+          int* __restrict__ post_idx, float* __restrict__ post_val, double* __restrict__ frame_ll,
+          int* __restrict__ err) {
+  __shared__ double dsh[4][64];
+  __shared__ double lsh[4][KP];
+  __shared__ int ish[4][KP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t g = (int64_t)blockIdx.x * 4 + wave;
+  if (g >= F) return;  // wave-uniform; no workgroup barriers below
+  const int Dp = D * (D + 1) / 2;
+  const double xd = (lane < D) ? (double)X[g * D + lane] : 0.0;
+  int m = 0;
+  if (cflag[g] == 0) {
+    const int ci = (lane < KP) ? cand[g * KP + lane] : -1;
+    for (int s = 0; s < KP; ++s) {
+      const int c = __shfl(ci, s);
+      if (c < 0 || c >= C) continue;
+      const double l = exact_ll(c, xd, lane, D, Dp, mu, linv, cst, dsh[wave]);
+      if (lane == 0) {
+        lsh[wave][m] = l;
+        ish[wave][m] = c;
+      }
+      ++m;
+    }
+  } else {
+    // overflowed candidate list: exact scores over all components, two passes
+    double mx = -INFINITY;
+    for (int c = 0; c < C; ++c) mx = fmax(mx, exact_ll(c, xd, lane, D, Dp, mu, linv, cst, dsh[wave]));
+    int cnt = 0;
+    for (int c = 0; c < C; ++c) {
+      const double l = exact_ll(c, xd, lane, D, Dp, mu, linv, cst, dsh[wave]);
+      if (l >= mx - margin) {
+        if (cnt < KP && lane == 0) {
+          lsh[wave][cnt] = l;
+          ish[wave][cnt] = c;
+        }
+        ++cnt;
+      }
+    }
+    if (cnt > KP && lane == 0) raise_error(err, IVX_ECAPACITY);
+    m = cnt < KP ? cnt : KP;
+  }
+  __builtin_amdgcn_wave_barrier();
+  double mx = -INFINITY;
+  for (int s = 0; s < m; ++s) mx = fmax(mx, lsh[wave][s]);
+  double se = 0.0;
+  for (int s = 0; s < m; ++s) se += exp(lsh[wave][s] - mx);
+  const double lse = mx + log(se);
+  if (!isfinite(lse) && lane == 0) raise_error(err, IVX_ENUMERIC);
+  if (lane < KP) {
+    int id = -1;
+    float v = 0.0f;
+    if (lane < m) {
+      id = ish[wave][lane];
+      v = (float)exp(lsh[wave][lane] - lse);
+    }
+    if (post_idx) post_idx[g * KP + lane] = id;
+    if (post_val) post_val[g * KP + lane] = v;
+  }
+  if (lane == 0 && frame_ll) frame_ll[g] = lse;
+}
+
+__global__ void k_dense_gamma(int64_t F, int C, const int* __restrict__ post_idx,
+                              const float* __restrict__ post_val, float* __restrict__ gamma) {
+  const int64_t n = F * C;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    gamma[i] = 0.0f;
+}
+
+__global__ void k_scatter_gamma(int64_t F, int C, const int* __restrict__ post_idx,
+                                const float* __restrict__ post_val, float* __restrict__ gamma) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= F * KP) return;
+  const int c = post_idx[i];
+  if (c >= 0) gamma[(i / KP) * C + c] = post_val[i];
+}
+
+}  // namespace
+
+void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, hipStream_t s) {
+  if (F <= 0) return;
+  const int DS = ctx->D + 1;
+  const size_t lds = sizeof(float) * (((size_t)FT * DS + 1) & ~(size_t)1) +
+                     sizeof(int2) * NW * CAPL * 64;
+  const unsigned nblk = (unsigned)((F + FT - 1) / FT);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_frame_select),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  k_frame_select<<<nblk, 256, lds, s>>>(X, F, ctx->D, ctx->shift, ctx->Wexp, ctx->C, ctx->Cpad, ctx->Kpad,
+                                        ctx->pairs, kMargin, ctx->cand, ctx->cflag);
+}
+
+void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int* post_idx, float* post_val,
+                    double* frame_ll, hipStream_t s) {
+  if (F <= 0) return;
+  const unsigned nblk = (unsigned)((F + 3) / 4);
+  k_rescore<<<nblk, 256, 0, s>>>(X, F, ctx->D, ctx->C, ctx->mu, ctx->linv, ctx->cst, ctx->cand,
+                                 ctx->cflag, (double)kMargin, post_idx, post_val, frame_ll,
+                                 ctx->dev_err);
+}
+
+void launch_dense_gamma(ivx_ctx* ctx, int64_t F, const int* post_idx, const float* post_val,
+                        float* gamma, hipStream_t s) {
+  if (F <= 0) return;
+  k_dense_gamma<<<2048, 256, 0, s>>>(F, ctx->C, post_idx, post_val, gamma);
+  const int64_t n = F * KP;
+  k_scatter_gamma<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(F, ctx->C, post_idx, post_val, gamma);
+}
+
+}  // namespace ivx

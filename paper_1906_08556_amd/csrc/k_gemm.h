@@ -1,0 +1,29 @@
+// FP32 MFMA GEMM launcher shared by the E-step and M-step host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ivx {
+
+enum { GEMM_STORE = 0, GEMM_ADD_F64 = 1, GEMM_STORE_TP = 2 };
+
+struct GemmArgs {
+  const float* A = nullptr;
+  const float* B = nullptr;
+  void* C = nullptr;
+  int64_t lda = 0, ldb = 0, ldc = 0;
+  int M = 0, N = 0, K = 0;
+  int64_t sA = 0, sB = 0, sC = 0;  // per-batch strides (elements)
+  int64_t sS = 0;                  // per-split stride of the FP32 store epilogue
+  int ksplit = 1;
+  int kchunk = 0;                  // K per split (multiple of 16); ignored when ksplit == 1
+};
+
+// C = op(A) op(B).  ta / tb select the transposed addressing of A / B, epi one
+// of GEMM_STORE, GEMM_ADD_F64, GEMM_STORE_TP.  Returns false (and launches
+// nothing) for a combination that is not instantiated.
+bool gemm_f32(const GemmArgs& g, bool ta, bool tb, int epi, int batches, hipStream_t s);
+
+}  // namespace ivx

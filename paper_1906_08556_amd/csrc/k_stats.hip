@@ -1,0 +1,244 @@
+// Baum-Welch statistics (Sec. 2) from the sparse per-frame posterior lists.
+//
+//  n_c(u), f_c(u): one workgroup per (utterance, block of 256 components)
+//    accumulates [n | f] rows in LDS with LDS float atomics and writes the
+//    block's rows once (zeros included), coalesced.
+//  S_c = sum_t gamma_tc x_t x_t^T (FP64 totals): the (frame, component)
+//    posterior entries are bucketed by component with a counting sort
+//    (per-block histograms, a scan, a scatter); one workgroup per component
+//    then accumulates the packed upper triangle in FP64 registers.
+#include "ivx_internal.h"
+
+namespace ivx {
+namespace {
+
+constexpr int NFB = 256;       // components per n/f workgroup
+constexpr int HB = 8192;       // frames per histogram block
+
+__global__ void __launch_bounds__(256)
+k_stats_nf(const float* __restrict__ X, const int64_t* __restrict__ utt_off, int64_t U, int64_t F,
+           int D, int C, const int* __restrict__ post_idx, const float* __restrict__ post_val,
+           float* __restrict__ n, float* __restrict__ f, int* __restrict__ err) {
+  extern __shared__ float acc[];  // [NFB][D+1]: n at column 0, f at 1..D
+  const int DS = D + 1;
+  const int64_t u = blockIdx.x;
+  const int c0 = blockIdx.y * NFB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int64_t t0 = utt_off[u], t1 = utt_off[u + 1];
+  const bool bad = (t0 > t1) || (t0 < 0) || (t1 > F) || (u == 0 && t0 != 0) ||
+                   (u == U - 1 && t1 != F);
+  if (bad) {
+    if (tid == 0 && blockIdx.y == 0) raise_error(err, IVX_EINVAL);
+    t0 = t1 = 0;
+  }
+  for (int i = tid; i < NFB * DS; i += 256) acc[i] = 0.0f;
+  __syncthreads();
+  for (int64_t t = t0 + wave; t < t1; t += 4) {
+    const int id = (lane < KP) ? post_idx[t * KP + lane] : -1;
+    const float gv = (lane < KP) ? post_val[t * KP + lane] : 0.0f;
+    const bool mine = id >= c0 && id < c0 + NFB;
+    uint64_t mask = __ballot(mine);
+    if (mask == 0) continue;
+    const float xv = (lane == 0) ? 1.0f : ((lane <= D) ? X[t * D + (lane - 1)] : 0.0f);
+    while (mask) {
+      const int s = __ffsll((unsigned long long)mask) - 1;
+      mask &= mask - 1;
+      const int c = __shfl(id, s);
+      const float gm = __shfl(gv, s);
+      if (lane <= D) atomicAdd(&acc[(c - c0) * DS + lane], gm * xv);
+    }
+  }
+  __syncthreads();
+  const int nc = (C - c0) < NFB ? (C - c0) : NFB;
+  float* fo = f + ((size_t)u * C + c0) * D;
+  for (int i = tid; i < nc * D; i += 256) {
+    const int c = i / D, d = i - c * D;
+    fo[i] = acc[c * DS + 1 + d];
+  }
+  for (int c = tid; c < nc; c += 256) n[(size_t)u * C + c0 + c] = acc[c * DS];
+}
+
+// hist[b][c] = number of posterior entries of component c in frame block b
+__global__ void __launch_bounds__(256)
+k_hist(int64_t F, int C, const int* __restrict__ post_idx, int* __restrict__ hist) {
+  extern __shared__ int hl[];
+  const int b = blockIdx.x;
+  for (int c = threadIdx.x; c < C; c += 256) hl[c] = 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)b * HB * KP;
+  const int64_t e1 = min(F * KP, e0 + (int64_t)HB * KP);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int c = post_idx[e];
+    if (c >= 0) atomicAdd(&hl[c], 1);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < C; c += 256) hist[(size_t)b * C + c] = hl[c];
+}
+
+// Turns hist into exclusive offsets in (component, block) order and writes
+// coff[c] = first entry of component c (coff[C] = total).  One workgroup.
+__global__ void __launch_bounds__(1024) k_hist_scan(int nb, int C, int* __restrict__ hist,
+                                                     int* __restrict__ coff) {
+  __shared__ int tot[1024];
+  __shared__ int wsum[16];
+  // per-component totals; each thread owns components c = tid, tid+1024, ...
+  int carry = 0;
+  for (int cbase = 0; cbase < C; cbase += 1024) {
+    const int c = cbase + threadIdx.x;
+    int s = 0;
+    if (c < C)
+      for (int b = 0; b < nb; ++b) s += hist[(size_t)b * C + c];
+    tot[threadIdx.x] = s;
+    __syncthreads();
+    // inclusive scan of tot (Hillis-Steele)
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int v = (threadIdx.x >= o) ? tot[threadIdx.x - o] : 0;
+      __syncthreads();
+      tot[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const int excl = carry + ((threadIdx.x > 0) ? tot[threadIdx.x - 1] : 0);
+    if (c < C) {
+      coff[c] = excl;
+      int run = excl;
+      for (int b = 0; b < nb; ++b) {
+        const int v = hist[(size_t)b * C + c];
+        hist[(size_t)b * C + c] = run;
+        run += v;
+      }
+    }
+    const int last = tot[1023];
+    __syncthreads();
+    carry += last;
+  }
+  if (threadIdx.x == 0) coff[C] = carry;
+  (void)wsum;
+}
+
+__global__ void __launch_bounds__(256)
+k_scatter(int64_t F, int C, const int* __restrict__ post_idx, const float* __restrict__ post_val,
+          const int* __restrict__ base, int2* __restrict__ ent) {
+  extern __shared__ int cur[];
+  const int b = blockIdx.x;
+  for (int c = threadIdx.x; c < C; c += 256) cur[c] = base[(size_t)b * C + c];
+  __syncthreads();
+  const int64_t e0 = (int64_t)b * HB * KP;
+  const int64_t e1 = min(F * KP, e0 + (int64_t)HB * KP);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int c = post_idx[e];
+    if (c >= 0) {
+      const int pos = atomicAdd(&cur[c], 1);
+      ent[pos] = make_int2((int)(e / KP), __float_as_int(post_val[e]));
+    }
+  }
+}
+
+// S_c += sum over the component's entries of gamma x x^T, packed upper
+// triangle (i <= j, row by row), FP64.
+constexpr int SB = 32;  // entries staged per step
+__global__ void __launch_bounds__(256)
+k_S_accum(const float* __restrict__ X, int D, const int* __restrict__ coff,
+          const int2* __restrict__ ent, double* __restrict__ S_acc) {
+  extern __shared__ float xsm[];  // [SB][D]
+  __shared__ float gsm[SB];
+  const int c = blockIdx.x;
+  const int Dp = D * (D + 1) / 2;
+  const int tid = threadIdx.x;
+  constexpr int MAXM = 8;  // Dp <= 2016 for D <= 63
+  int ii[MAXM], jj[MAXM];
+  double acc[MAXM];
+#pragma unroll
+  for (int m = 0; m < MAXM; ++m) {
+    acc[m] = 0.0;
+    const int k = tid + m * 256;
+    int i = 0, rem = k;
+    while (i < D && rem >= D - i) {
+      rem -= D - i;
+      ++i;
+    }
+    ii[m] = (k < Dp) ? i : 0;
+    jj[m] = (k < Dp) ? i + rem : 0;
+  }
+  const int e0 = coff[c], e1 = coff[c + 1];
+  for (int eb = e0; eb < e1; eb += SB) {
+    const int ne = min(SB, e1 - eb);
+    __syncthreads();
+    for (int i = tid; i < ne * D; i += 256) {
+      const int e = i / D, d = i - e * D;
+      xsm[i] = X[(int64_t)ent[eb + e].x * D + d];
+    }
+    if (tid < ne) gsm[tid] = __int_as_float(ent[eb + tid].y);
+    __syncthreads();
+    for (int e = 0; e < ne; ++e) {
+      const double g = (double)gsm[e];
+      const float* xe = xsm + e * D;
+#pragma unroll
+      for (int m = 0; m < MAXM; ++m)
+        acc[m] += g * ((double)xe[ii[m]] * (double)xe[jj[m]]);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < MAXM; ++m) {
+    const int k = tid + m * 256;
+    if (k < Dp) S_acc[(size_t)c * Dp + k] += acc[m];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sum_partial(const double* __restrict__ x, int64_t n,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += x[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ part, int np,
+                                                   double* __restrict__ acc) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) acc[0] += sh[0];
+}
+
+}  // namespace
+
+void launch_stats_nf(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_t U, int64_t F,
+                     float* n, float* f, hipStream_t s) {
+  if (U <= 0) return;
+  dim3 grid((unsigned)U, (unsigned)((ctx->C + NFB - 1) / NFB));
+  const size_t lds = sizeof(float) * NFB * (ctx->D + 1);
+  k_stats_nf<<<grid, 256, lds, s>>>(X, utt_off, U, F, ctx->D, ctx->C, ctx->post_idx,
+                                    ctx->post_val, n, f, ctx->dev_err);
+}
+
+void launch_stats_S(ivx_ctx* ctx, const float* X, int64_t F, double* S_acc, hipStream_t s) {
+  if (F <= 0) return;
+  const int nb = (int)((F + HB - 1) / HB);
+  const size_t ldsc = sizeof(int) * ctx->C;
+  k_hist<<<nb, 256, ldsc, s>>>(F, ctx->C, ctx->post_idx, ctx->hist);
+  k_hist_scan<<<1, 1024, 0, s>>>(nb, ctx->C, ctx->hist, ctx->coff);
+  k_scatter<<<nb, 256, ldsc, s>>>(F, ctx->C, ctx->post_idx, ctx->post_val, ctx->hist, ctx->ent);
+  k_S_accum<<<ctx->C, 256, sizeof(float) * SB * ctx->D, s>>>(X, ctx->D, ctx->coff, ctx->ent, S_acc);
+}
+
+void launch_sum_f64(ivx_ctx* ctx, const double* x, int64_t n, double* acc, hipStream_t s) {
+  if (n <= 0) return;
+  int nb = (int)((n + 255) / 256);
+  if (nb > 1024) nb = 1024;
+  k_sum_partial<<<nb, 256, 0, s>>>(x, n, ctx->partial);
+  k_sum_final<<<1, 256, 0, s>>>(ctx->partial, nb, acc);
+}
+
+}  // namespace ivx

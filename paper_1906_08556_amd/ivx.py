@@ -1,0 +1,264 @@
+"""ctypes binding of libivx.so (argument marshalling only).
+
+Every entry point of include/ivx.h has a method of the same name here.
+Tensors are torch tensors on the context's device; the binding checks dtype,
+device and contiguity, passes raw pointers and the current HIP stream, and
+raises IvxError on a non-zero status.  No arithmetic of the method happens
+here: if libivx.so is missing, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libivx.so")
+
+IVX_FP32, IVX_BF16 = 0, 1
+IVX_SEL_ALL, IVX_SEL_LEARNED = 0, 1
+KP = 16  # posterior list capacity per frame
+
+STATUS = {0: "IVX_OK", -1: "IVX_EINVAL", -2: "IVX_ENOMEM", -3: "IVX_ENOTPD", -4: "IVX_EDEVICE",
+          -5: "IVX_ENUMERIC", -6: "IVX_ECAPACITY"}
+
+
+class IvxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_int32), ("D", ctypes.c_int32), ("R", ctypes.c_int32),
+                ("max_batch_utts", ctypes.c_int32), ("max_batch_frames", ctypes.c_int64)]
+
+
+class Accum(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("Cc", ctypes.c_void_p), ("N", ctypes.c_void_p),
+                ("h", ctypes.c_void_p), ("H", ctypes.c_void_p), ("count", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_I32, _I64, _F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+# name -> (restype, argtypes)
+PROTOTYPES = {
+    "ivx_create": (_I32, [ctypes.POINTER(Dims), ctypes.c_int, ctypes.POINTER(_P)]),
+    "ivx_destroy": (None, [_P]),
+    "ivx_last_error": (ctypes.c_char_p, []),
+    "ivx_sync_status": (_I32, [_P, _P]),
+    "ivx_tp_size": (_I64, [_I32]),
+    "ivx_set_ubm": (_I32, [_P, _P, _P, _P, _P]),
+    "ivx_init_tv": (_I32, [_P, _P, _F64, _P]),
+    "ivx_set_tv": (_I32, [_P, _P, _P, _P, _P]),
+    "ivx_get_tv": (_I32, [_P, _P, _P, _P, _P, _P]),
+    "ubm_posteriors": (_I32, [_P, _P, _I64, _I32, _I32, _P, _P, _P, _I32, _P, _P]),
+    "bw_stats": (_I32, [_P, _P, _P, _I64, _I64, _I32, _I32, _P, _P, _P, _P, _P]),
+    "tv_estep": (_I32, [_P, _P, _P, _I64, _I32, _P, _P, _P, _P, _P]),
+    "tv_mstep_accumulate": (_I32, [_P, _P, _P, _P, _P, _I64, ctypes.POINTER(Accum), _P]),
+    "extract_ivectors": (_I32, [_P, _P, _P, _I64, _I64, _I32, _I32, _P, _P]),
+    "tv_mstep_solve": (_I32, [_P, ctypes.POINTER(Accum), _P, ctypes.c_int, _P, _P, _P, _P]),
+    "tv_mindiv": (_I32, [_P, ctypes.POINTER(Accum), ctypes.c_int, _P]),
+    "ubm_update_means": (_I32, [_P, _P]),
+    "ivx_profile_enable": (_I32, [_P, _I32]),
+    "ivx_profile_read": (_I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
+}
+
+PROFILE_GROUPS = ["frame_select", "rescore", "stats_nf", "stats_S", "tv_prep", "estep_gemm",
+                  "estep_chol", "accumulate", "mstep_solve", "mindiv", "ubm_prepare"]
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads libivx.so and binds every prototype; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1906_08556_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in PROTOTYPES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t: Optional[torch.Tensor], dtype: torch.dtype, name: str, device=None):
+    if t is None:
+        return None
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name}: expected device {device}, got {t.device}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """One ivx_ctx: model storage and workspace for fixed (C, D, R) and batch limits."""
+
+    def __init__(self, C: int, D: int, R: int, max_batch_utts: int, max_batch_frames: int,
+                 device: int = 0):
+        self.lib = load()
+        self.C, self.D, self.R = C, D, R
+        self.max_batch_utts, self.max_batch_frames = max_batch_utts, max_batch_frames
+        self.device = torch.device("cuda", device)
+        dims = Dims(C, D, R, max_batch_utts, max_batch_frames)
+        h = ctypes.c_void_p()
+        self._check(self.lib.ivx_create(ctypes.byref(dims), device, ctypes.byref(h)))
+        self.h = h
+        self.TP = int(self.lib.ivx_tp_size(R))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ivx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, status: int):
+        if status != 0:
+            msg = self.lib.ivx_last_error().decode(errors="replace")
+            raise IvxError(status, msg)
+
+    def _p(self, t, dtype, name):
+        return _ptr(t, dtype, name, self.device)
+
+    # ------------------------------------------------------------------ model
+    def sync_status(self, stream=None):
+        self._check(self.lib.ivx_sync_status(self.h, _stream(stream)))
+
+    def set_ubm(self, w, mu, cov, stream=None):
+        f = torch.float64
+        self._check(self.lib.ivx_set_ubm(self.h, self._p(w, f, "w"), self._p(mu, f, "mu"),
+                                         self._p(cov, f, "cov"), _stream(stream)))
+
+    def init_tv(self, T_rand, p0=100.0, stream=None):
+        self._check(self.lib.ivx_init_tv(self.h, self._p(T_rand, torch.float64, "T_rand"),
+                                         float(p0), _stream(stream)))
+
+    def set_tv(self, T, Sigma, p, stream=None):
+        f = torch.float64
+        self._check(self.lib.ivx_set_tv(self.h, self._p(T, f, "T"), self._p(Sigma, f, "Sigma"),
+                                        self._p(p, f, "p"), _stream(stream)))
+
+    def get_tv(self, stream=None):
+        f = torch.float64
+        dev = self.device
+        T = torch.empty((self.C, self.D, self.R), dtype=f, device=dev)
+        Sigma = torch.empty((self.C, self.D, self.D), dtype=f, device=dev)
+        p = torch.empty(self.R, dtype=f, device=dev)
+        mu = torch.empty((self.C, self.D), dtype=f, device=dev)
+        self._check(self.lib.ivx_get_tv(self.h, self._p(T, f, "T"), self._p(Sigma, f, "Sigma"),
+                                        self._p(p, f, "p"), self._p(mu, f, "mu"), _stream(stream)))
+        return T, Sigma, p, mu
+
+    # --------------------------------------------------------------- hot path
+    def ubm_posteriors(self, X, gamma=None, post_idx=None, post_val=None, frame_ll=None,
+                       prec=IVX_FP32, sel=IVX_SEL_ALL, stream=None):
+        F = X.shape[0]
+        self._check(self.lib.ubm_posteriors(
+            self.h, self._p(X, torch.float32, "X"), F, prec, sel,
+            self._p(gamma, torch.float32, "gamma"), self._p(post_idx, torch.int32, "post_idx"),
+            self._p(post_val, torch.float32, "post_val"), KP,
+            self._p(frame_ll, torch.float64, "frame_ll"), _stream(stream)))
+
+    def bw_stats(self, X, utt_off, n, f, S_acc=None, ll_acc=None, prec=IVX_FP32,
+                 sel=IVX_SEL_ALL, stream=None):
+        U = utt_off.shape[0] - 1
+        self._check(self.lib.bw_stats(
+            self.h, self._p(X, torch.float32, "X"), self._p(utt_off, torch.int64, "utt_off"), U,
+            X.shape[0], prec, sel, self._p(n, torch.float32, "n"), self._p(f, torch.float32, "f"),
+            self._p(S_acc, torch.float64, "S_acc"), self._p(ll_acc, torch.float64, "ll_acc"),
+            _stream(stream)))
+
+    def tv_estep(self, n, f, phi, Phi=None, ll_acc=None, info=None, prec=IVX_FP32, stream=None):
+        U = n.shape[0]
+        self._check(self.lib.tv_estep(
+            self.h, self._p(n, torch.float32, "n"), self._p(f, torch.float32, "f"), U, prec,
+            self._p(phi, torch.float32, "phi"), self._p(Phi, torch.float32, "Phi"),
+            self._p(ll_acc, torch.float64, "ll_acc"), self._p(info, torch.int32, "info"),
+            _stream(stream)))
+
+    def new_accum(self) -> "Accumulators":
+        return Accumulators(self)
+
+    def tv_mstep_accumulate(self, n, f, phi, Phi, acc: "Accumulators", stream=None):
+        U = n.shape[0]
+        s = acc.struct()
+        self._check(self.lib.tv_mstep_accumulate(
+            self.h, self._p(n, torch.float32, "n"), self._p(f, torch.float32, "f"),
+            self._p(phi, torch.float32, "phi"), self._p(Phi, torch.float32, "Phi"), U,
+            ctypes.byref(s), _stream(stream)))
+
+    def extract_ivectors(self, X, utt_off, phi, prec=IVX_FP32, sel=IVX_SEL_ALL, stream=None):
+        U = utt_off.shape[0] - 1
+        self._check(self.lib.extract_ivectors(
+            self.h, self._p(X, torch.float32, "X"), self._p(utt_off, torch.int64, "utt_off"), U,
+            X.shape[0], prec, sel, self._p(phi, torch.float32, "phi"), _stream(stream)))
+
+    def tv_mstep_solve(self, acc: "Accumulators", S, update_sigma=True, ll_sum=None,
+                       objective=None, status=None, stream=None):
+        s = acc.struct()
+        self._check(self.lib.tv_mstep_solve(
+            self.h, ctypes.byref(s), self._p(S, torch.float64, "S"), int(bool(update_sigma)),
+            self._p(ll_sum, torch.float64, "ll_sum"), self._p(objective, torch.float64, "objective"),
+            self._p(status, torch.int32, "status"), _stream(stream)))
+
+    def tv_mindiv(self, acc: "Accumulators", method=0, stream=None):
+        s = acc.struct()
+        self._check(self.lib.tv_mindiv(self.h, ctypes.byref(s), int(method), _stream(stream)))
+
+    def ubm_update_means(self, stream=None):
+        self._check(self.lib.ubm_update_means(self.h, _stream(stream)))
+
+    # ---------------------------------------------------------------- tracing
+    def profile_enable(self, capacity=4096):
+        self._check(self.lib.ivx_profile_enable(self.h, int(capacity)))
+
+    def profile_read(self):
+        """{group: (total ms, calls)} of the event pairs recorded since the last read."""
+        n = len(PROFILE_GROUPS)
+        ms = (ctypes.c_double * n)()
+        calls = (ctypes.c_int64 * n)()
+        self._check(self.lib.ivx_profile_read(self.h, ms, calls, n))
+        return {g: (ms[i], calls[i]) for i, g in enumerate(PROFILE_GROUPS)}
+
+
+class Accumulators:
+    """Device FP64 accumulator buffers for tv_mstep_accumulate (zeroed)."""
+
+    def __init__(self, ctx: Context):
+        f, dev = torch.float64, ctx.device
+        self.A = torch.zeros((ctx.C, ctx.TP), dtype=f, device=dev)
+        self.Cc = torch.zeros((ctx.C, ctx.D, ctx.R), dtype=f, device=dev)
+        self.N = torch.zeros(ctx.C, dtype=f, device=dev)
+        self.h = torch.zeros(ctx.R, dtype=f, device=dev)
+        self.H = torch.zeros(ctx.TP, dtype=f, device=dev)
+        self.count = torch.zeros(1, dtype=f, device=dev)
+
+    def zero_(self):
+        for t in (self.A, self.Cc, self.N, self.h, self.H, self.count):
+            t.zero_()
+        return self
+
+    def struct(self) -> Accum:
+        return Accum(self.A.data_ptr(), self.Cc.data_ptr(), self.N.data_ptr(), self.h.data_ptr(),
+                     self.H.data_ptr(), self.count.data_ptr())

@@ -1,0 +1,152 @@
+"""GPU parity of the frame stage (posteriors, n/f/S statistics) against the FP64 oracle.
+
+Tolerances: posteriors <= 1e-4 absolute (the target accuracy of the method's
+GPU form); frame log-likelihood 1e-8 absolute (both sides score the kept
+components exactly in FP64); n, f accumulate FP32 posteriors in FP32:
+|err| <= 1e-5 + 1e-5 |ref|; S accumulates FP32-rounded posteriors (relative
+rounding <= 6e-8 each) in FP64, so an entry's error is bounded by the rounding
+times sum_t gamma_tc |x_ti x_tj|, not by |S_ij| (mixed signs cancel):
+|err| <= 2e-7 sum_t gamma_tc |x_ti x_tj| + 1e-9.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from _gpu_helpers import dev, make_ctx, packed_upper
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_frame(wl):
+    ll = oracle.frame_loglik(wl.X, wl.w, wl.mu, wl.cov)
+    gamma, lse = oracle.posteriors(ll)
+    return gamma, lse
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    wl = synth.make(1)
+    gamma, lse = _oracle_frame(wl)
+    n, f, S = oracle.bw_stats(wl.X, wl.utt_off, gamma)
+    return wl, gamma, lse, n, f, S
+
+
+@pytest.fixture(scope="module")
+def cfg2_sub():
+    wl = synth.make(2, n_utts=3)
+    gamma, lse = _oracle_frame(wl)
+    n, f, S = oracle.bw_stats(wl.X, wl.utt_off, gamma)
+    return wl, gamma, lse, n, f, S
+
+
+def _run_posteriors(wl):
+    ctx = make_ctx(wl)
+    X = dev(wl.X)
+    F, C = wl.F, wl.shape.C
+    gamma = torch.empty((F, C), dtype=torch.float32, device="cuda")
+    pidx = torch.empty((F, 16), dtype=torch.int32, device="cuda")
+    pval = torch.empty((F, 16), dtype=torch.float32, device="cuda")
+    fll = torch.empty(F, dtype=torch.float64, device="cuda")
+    ctx.ubm_posteriors(X, gamma=gamma, post_idx=pidx, post_val=pval, frame_ll=fll)
+    ctx.sync_status()
+    return gamma.cpu().numpy(), pidx.cpu().numpy(), pval.cpu().numpy(), fll.cpu().numpy()
+
+
+@pytest.mark.parametrize("which", ["cfg1", "cfg2_sub"])
+def test_posteriors_match_oracle(which, request):
+    wl, g_ref, lse_ref, *_ = request.getfixturevalue(which)
+    gamma, pidx, pval, fll = _run_posteriors(wl)
+    err = np.abs(gamma - g_ref)
+    print(which, "max |dgamma|", err.max(), "candidates/frame", (pidx >= 0).sum(1).mean())
+    assert err.max() <= 1e-4
+    np.testing.assert_allclose(gamma.sum(1), 1.0, atol=1e-5)
+    np.testing.assert_allclose(fll, lse_ref, rtol=0, atol=1e-8)
+    # the list and the dense output agree, and every listed index is valid
+    assert np.all((pidx >= -1) & (pidx < wl.shape.C))
+    rows = np.repeat(np.arange(wl.F)[:, None], 16, 1)
+    ok = pidx >= 0
+    np.testing.assert_array_equal(gamma[rows[ok], pidx[ok]], pval[ok])
+
+
+def _run_stats(wl, with_S=True):
+    ctx = make_ctx(wl)
+    X = dev(wl.X)
+    off = dev(wl.utt_off)
+    U, C, D = wl.U, wl.shape.C, wl.shape.D
+    n = torch.empty((U, C), dtype=torch.float32, device="cuda")
+    f = torch.empty((U, C, D), dtype=torch.float32, device="cuda")
+    S = torch.zeros((C, D * (D + 1) // 2), dtype=torch.float64, device="cuda") if with_S else None
+    ll = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.bw_stats(X, off, n, f, S_acc=S, ll_acc=ll)
+    ctx.sync_status()
+    return n.cpu().numpy(), f.cpu().numpy(), (S.cpu().numpy() if with_S else None), ll.item()
+
+
+@pytest.mark.parametrize("which", ["cfg1", "cfg2_sub"])
+def test_bw_stats_match_oracle(which, request):
+    wl, g_ref, lse_ref, n_ref, f_ref, S_ref = request.getfixturevalue(which)
+    n, f, S, ll = _run_stats(wl)
+    np.testing.assert_allclose(n, n_ref, rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(f, f_ref, rtol=1e-5, atol=1e-4)
+    Sp = packed_upper(S_ref)
+    Xa = np.abs(wl.X.astype(np.float64))
+    S_abs = packed_upper(np.stack([(g_ref[:, c:c + 1] * Xa).T @ Xa for c in range(wl.shape.C)]))
+    ratio = np.max(np.abs(S - Sp) / (2e-7 * S_abs + 1e-9))
+    print(which, "S error / bound", ratio)
+    assert ratio <= 1.0
+    assert abs(ll - lse_ref.sum()) <= 1e-9 * abs(lse_ref.sum())
+
+
+def test_ragged_shapes_and_empty_utterance():
+    wl = synth.make(1, D=7, C=200, R=8, U=12, lengths="uniform:0:40")
+    assert np.any(np.diff(wl.utt_off) == 0), "want an empty utterance in this case"
+    gamma, lse = _oracle_frame(wl)
+    n_ref, f_ref, S_ref = oracle.bw_stats(wl.X, wl.utt_off, gamma)
+    g, *_ = _run_posteriors(wl)
+    assert np.abs(g - gamma).max() <= 1e-4
+    n, f, S, ll = _run_stats(wl)
+    np.testing.assert_allclose(n, n_ref, rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(f, f_ref, rtol=1e-5, atol=1e-4)
+    empty = np.diff(wl.utt_off) == 0
+    assert np.all(n[empty] == 0) and np.all(f[empty] == 0)
+
+
+def test_single_component_ubm():
+    wl = synth.make(1, D=5, C=1, R=4, U=3, lengths="uniform:10:20")
+    g, pidx, pval, fll = _run_posteriors(wl)
+    np.testing.assert_array_equal(g, 1.0)
+
+
+def test_zero_frames_is_a_no_op():
+    wl = synth.make(1, D=5, C=10, R=4, U=3, lengths="uniform:10:20")
+    ctx = make_ctx(wl)
+    X = torch.empty((0, 5), dtype=torch.float32, device="cuda")
+    ctx.ubm_posteriors(X)
+    ctx.sync_status()
+
+
+def test_bad_offsets_are_reported():
+    from paper_1906_08556_amd import ivx
+    wl = synth.make(1, D=5, C=10, R=4, U=3, lengths="uniform:10:20")
+    ctx = make_ctx(wl)
+    off = wl.utt_off.copy()
+    off[1], off[2] = off[2], off[1]  # decreasing
+    n = torch.empty((3, 10), dtype=torch.float32, device="cuda")
+    f = torch.empty((3, 10, 5), dtype=torch.float32, device="cuda")
+    ctx.bw_stats(dev(wl.X), dev(off), n, f)
+    with pytest.raises(ivx.IvxError) as e:
+        ctx.sync_status()
+    assert e.value.status == -1
+
+
+def test_non_pd_covariance_is_rejected():
+    from paper_1906_08556_amd import ivx
+    wl = synth.make(1, D=5, C=10, R=4, U=3, lengths="uniform:10:20")
+    cov = wl.cov.copy()
+    cov[7] = -np.eye(5)
+    ctx = ivx.Context(10, 5, 4, 3, wl.F)
+    with pytest.raises(ivx.IvxError) as e:
+        ctx.set_ubm(dev(wl.w), dev(wl.mu), dev(cov))
+    assert e.value.status == -3 and "7" in str(e.value)
