@@ -53,7 +53,7 @@ typedef enum {
   IVX_ENOTPD = -3,     /* a covariance / precision matrix is not positive definite */
   IVX_EDEVICE = -4,    /* HIP runtime error */
   IVX_ENUMERIC = -5,   /* non-finite value met by a kernel */
-  IVX_ECAPACITY = -6   /* more components within the posterior margin than the list holds */
+  IVX_ECAPACITY = -6   /* a frame's posterior does not fit the 16-entry list (see ubm_posteriors) */
 } ivx_status;
 
 typedef enum { IVX_FP32 = 0, IVX_BF16 = 1 } ivx_precision;
@@ -141,8 +141,11 @@ ivx_status ivx_get_tv(ivx_ctx* ctx, double* T, double* Sigma, double* p, double*
  *             candidate margin of each frame's best one and their posteriors
  *             (unused slots: index -1, value 0), or NULL.  K must be 16.
  *   frame_ll  [F] FP64 log sum_c w_c N(x_t; ...), or NULL.
- * Components further than the margin (40 nats) below the best one carry a
- * posterior below e^-40 relative to it and are reported as 0. */
+ * Components more than ln C + 18.64 nats below the frame's best carry a
+ * total mass below 2^-24 e^-2 and are reported as 0.  If more than 16
+ * components lie within that margin, the 16 with the highest exact scores
+ * are kept, and IVX_ECAPACITY is recorded when the others carry more than
+ * 1e-6 of the frame's mass (very flat posteriors, e.g. small D). */
 ivx_status ubm_posteriors(ivx_ctx* ctx, const float* X, int64_t F, ivx_precision prec,
                           ivx_selection sel, float* gamma, int32_t* post_idx, float* post_val,
                           int32_t K, double* frame_ll, void* stream);

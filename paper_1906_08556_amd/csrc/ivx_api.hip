@@ -153,6 +153,7 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   c->Cpad = (c->C + 255) / 256 * 256;  // multiple of the frame GEMM component tile
   c->Dp = c->D * (c->D + 1) / 2;
   c->TP = tp_size(c->R);
+  c->margin = candidate_margin(c->C);
   c->nhist = (int)((c->maxF + 8191) / 8192);
 
   const size_t C = c->C, D = c->D, R = c->R, F = c->maxF;
@@ -244,7 +245,8 @@ ivx_status ivx_sync_status(ivx_ctx* ctx, void* stream) {
       set_error("device: non-finite value");
       break;
     case IVX_ECAPACITY:
-      set_error("device: more than %d components within the posterior margin of a frame", KP);
+      set_error("device: a frame has more than %d components within the posterior margin and "
+                "the components beyond them carry more than %g of its mass", KP, kMaxDroppedMass);
       break;
     default:
       set_error("device: error %d", e[0]);

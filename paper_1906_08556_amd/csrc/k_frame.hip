@@ -6,13 +6,13 @@
 // product runs on MFMA (v_mfma_f32_32x32x2_f32) with components on the M side
 // and frames on the N side, so each lane ends a component tile holding 128
 // log-likelihoods of one frame.  A running per-frame maximum and a short list
-// of components within kMargin nats of it are kept across component tiles:
+// of components within the candidate margin of it are kept across component tiles:
 // the [F x C] log-likelihood matrix never leaves registers.
 //
 // Stage 2 (k_rescore): every surviving candidate is rescored exactly in FP64,
 // l = const_c - 1/2 || L_c^{-1} (x - mu_c) ||^2, and the posteriors follow
 // from a log-sum-exp over the candidates.  Frames whose candidate list
-// overflowed are rescored over all C components.
+// overflowed are rescored over all C components and keep the KP best.
 #include <cmath>
 
 #include "ivx_internal.h"
@@ -180,7 +180,7 @@ __device__ inline double exact_ll(int c, double xd, int lane, int D, int Dp,
 __global__ void __launch_bounds__(256)
 k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __restrict__ mu,
           const double* __restrict__ linv, const double* __restrict__ cst,
-          const int* __restrict__ cand, const int* __restrict__ cflag, double margin,
+          const int* __restrict__ cand, const int* __restrict__ cflag,
           int* __restrict__ post_idx, float* __restrict__ post_val, double* __restrict__ frame_ll,
           int* __restrict__ err) {
   __shared__ double dsh[4][64];
@@ -192,6 +192,7 @@ k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __
   const int Dp = D * (D + 1) / 2;
   const double xd = (lane < D) ? (double)X[g * D + lane] : 0.0;
   int m = 0;
+  double full_lse = NAN;  // set when all components were scored
   if (cflag[g] == 0) {
     const int ci = (lane < KP) ? cand[g * KP + lane] : -1;
     for (int s = 0; s < KP; ++s) {
@@ -205,30 +206,44 @@ k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __
       ++m;
     }
   } else {
-    // overflowed candidate list: exact scores over all components, two passes
-    double mx = -INFINITY;
-    for (int c = 0; c < C; ++c) mx = fmax(mx, exact_ll(c, xd, lane, D, Dp, mu, linv, cst, dsh[wave]));
+    // overflowed candidate list: exact scores over all components; keep the
+    // KP best (sorted, lane 0) and the full log-sum-exp
+    double run_m = -INFINITY, run_s = 0.0;
     int cnt = 0;
     for (int c = 0; c < C; ++c) {
       const double l = exact_ll(c, xd, lane, D, Dp, mu, linv, cst, dsh[wave]);
-      if (l >= mx - margin) {
-        if (cnt < KP && lane == 0) {
-          lsh[wave][cnt] = l;
-          ish[wave][cnt] = c;
-        }
-        ++cnt;
+      if (l > run_m) {
+        run_s = run_s * exp(run_m - l) + 1.0;
+        run_m = l;
+      } else {
+        run_s += exp(l - run_m);
       }
+      if (lane == 0 && (cnt < KP || l > lsh[wave][KP - 1])) {
+        int pos = cnt < KP ? cnt : KP - 1;
+        while (pos > 0 && lsh[wave][pos - 1] < l) {
+          lsh[wave][pos] = lsh[wave][pos - 1];
+          ish[wave][pos] = ish[wave][pos - 1];
+          --pos;
+        }
+        lsh[wave][pos] = l;
+        ish[wave][pos] = c;
+      }
+      if (cnt < KP) ++cnt;
     }
-    if (cnt > KP && lane == 0) raise_error(err, IVX_ECAPACITY);
-    m = cnt < KP ? cnt : KP;
+    __builtin_amdgcn_wave_barrier();
+    m = cnt;
+    full_lse = run_m + log(run_s);
   }
   __builtin_amdgcn_wave_barrier();
   double mx = -INFINITY;
   for (int s = 0; s < m; ++s) mx = fmax(mx, lsh[wave][s]);
   double se = 0.0;
   for (int s = 0; s < m; ++s) se += exp(lsh[wave][s] - mx);
-  const double lse = mx + log(se);
+  const double kept = mx + log(se);
+  const double lse = isnan(full_lse) ? kept : full_lse;
   if (!isfinite(lse) && lane == 0) raise_error(err, IVX_ENUMERIC);
+  if (!isnan(full_lse) && lane == 0 && 1.0 - exp(kept - full_lse) > kMaxDroppedMass)
+    raise_error(err, IVX_ECAPACITY);
   if (lane < KP) {
     int id = -1;
     float v = 0.0f;
@@ -273,7 +288,7 @@ void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, hipStream_t s)
     attr_set = true;
   }
   k_frame_select<<<nblk, 256, lds, s>>>(X, F, ctx->D, ctx->shift, ctx->Wexp, ctx->C, ctx->Cpad, ctx->Kpad,
-                                        ctx->pairs, kMargin, ctx->cand, ctx->cflag);
+                                        ctx->pairs, ctx->margin, ctx->cand, ctx->cflag);
 }
 
 void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int* post_idx, float* post_val,
@@ -281,8 +296,7 @@ void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int* post_idx, floa
   if (F <= 0) return;
   const unsigned nblk = (unsigned)((F + 3) / 4);
   k_rescore<<<nblk, 256, 0, s>>>(X, F, ctx->D, ctx->C, ctx->mu, ctx->linv, ctx->cst, ctx->cand,
-                                 ctx->cflag, (double)kMargin, post_idx, post_val, frame_ll,
-                                 ctx->dev_err);
+                                 ctx->cflag, post_idx, post_val, frame_ll, ctx->dev_err);
 }
 
 void launch_dense_gamma(ivx_ctx* ctx, int64_t F, const int* post_idx, const float* post_val,

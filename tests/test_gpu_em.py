@@ -9,8 +9,12 @@ Tolerances (derived from the arithmetic of each GPU step):
   * Accumulators: FP32 GEMM partial sums added into FP64, relative <= 1e-5.
   * M-step solve and minimum divergence: FP64 on both sides from the same
     inputs, relative <= 1e-9.
-  * One full GPU EM iteration vs the oracle iteration: T, Sigma relative
-    Frobenius <= 1e-4; objective relative <= 1e-6.
+  * One full GPU EM iteration vs the oracle iteration from the same state:
+    T, Sigma, mu relative Frobenius <= 1e-4; objective relative <= 1e-6.
+  * Free-running trajectories (each side on its own state): FP32-level
+    differences in Sigma are amplified by cond(Sigma) (~370 at this shape) in
+    tr(Sigma^-1 S) and in the next M-step: objective relative <= 1e-3, T
+    relative Frobenius <= 1e-2 after three iterations.
 """
 import numpy as np
 import pytest
@@ -227,6 +231,34 @@ def _gpu_iteration(ctx, wl, X, off, realign=True, S_fixed=None, stats=None):
 
 
 def test_full_em_iterations_match_oracle(cfg1):
+    """Each GPU iteration starts from the oracle's state (T, Sigma, p, UBM
+    means) and is compared with the oracle's iteration from that state."""
+    wl, n, f, S, tv = cfg1
+    ctx = make_ctx(wl)
+    X, off = dev(wl.X), dev(wl.utt_off)
+    ubm = (wl.w, wl.mu, wl.cov)
+    for it in range(3):
+        ctx.set_ubm(dev(ubm[0]), dev(ubm[1]), dev(ubm[2]))
+        ctx.set_tv(dev(tv[0]), dev(tv[1]), dev(tv[2]))
+        obj, _, _ = _gpu_iteration(ctx, wl, X, off, realign=True)
+        r = oracle.em_iteration(wl.X, wl.utt_off, ubm, tv, realign=True)
+        Tg, Sg, pg, mug = [t.cpu().numpy() for t in ctx.get_tv()]
+        print(f"iter {it}: obj gpu {obj:.6f} oracle {r['objective']:.6f}  T relfro "
+              f"{relfro(Tg, r['T']):.2e}  Sigma relfro {relfro(Sg, r['Sigma']):.2e}  "
+              f"p0 {pg[0]:.6f} {r['p'][0]:.6f}  mu relfro {relfro(mug, r['mu']):.2e}")
+        assert abs(obj - r["objective"]) <= 1e-6 * abs(r["objective"])
+        assert relfro(Tg, r["T"]) <= 1e-4
+        assert relfro(Sg, r["Sigma"]) <= 1e-4
+        assert abs(pg[0] - r["p"][0]) <= 1e-4 * r["p"][0]
+        assert relfro(mug, r["mu"]) <= 1e-4
+        tv = (r["T"], r["Sigma"], r["p"])
+        ubm = (wl.w, r["mu"], wl.cov)
+
+
+def test_gpu_trajectory_stays_close_to_the_oracle(cfg1):
+    """Three iterations from the same initial model, each side on its own
+    state.  FP32-level differences in Sigma are amplified by cond(Sigma) in
+    the next iteration, so the bound is looser than the seeded comparison."""
     wl, n, f, S, tv = cfg1
     ctx = _ctx_tv(wl, tv)
     X, off = dev(wl.X), dev(wl.utt_off)
@@ -236,17 +268,11 @@ def test_full_em_iterations_match_oracle(cfg1):
         r = oracle.em_iteration(wl.X, wl.utt_off, ubm, tv, realign=True)
         tv = (r["T"], r["Sigma"], r["p"])
         ubm = (wl.w, r["mu"], wl.cov)
-        Tg, Sg, pg, mug = [t.cpu().numpy() for t in ctx.get_tv()]
-        print(f"iter {it}: obj gpu {obj:.6f} oracle {r['objective']:.6f}  T relfro "
-              f"{relfro(Tg, r['T']):.2e}  Sigma relfro {relfro(Sg, r['Sigma']):.2e}  p0 {pg[0]:.6f} {r['p'][0]:.6f}")
-        assert abs(obj - r["objective"]) <= 1e-6 * abs(r["objective"])
-        if it == 0:
-            assert relfro(Tg, r["T"]) <= 1e-4
-            assert relfro(Sg, r["Sigma"]) <= 1e-4
-            assert abs(pg[0] - r["p"][0]) <= 1e-4 * r["p"][0]
-        # continue both from their own state (the GPU path is not re-seeded)
-    # after three iterations the two runs still agree closely
-    assert relfro(Tg, r["T"]) <= 1e-3
+        print(f"iter {it}: obj gpu {obj:.6f} oracle {r['objective']:.6f}")
+        assert abs(obj - r["objective"]) <= 1e-3 * abs(r["objective"])
+    Tg = ctx.get_tv()[0].cpu().numpy()
+    print("T relfro after 3 iterations", relfro(Tg, r["T"]))
+    assert relfro(Tg, r["T"]) <= 1e-2
 
 
 def test_gpu_objective_never_decreases_at_fixed_alignments():

@@ -100,8 +100,12 @@ def test_bw_stats_match_oracle(which, request):
 
 
 def test_ragged_shapes_and_empty_utterance():
-    wl = synth.make(1, D=7, C=200, R=8, U=12, lengths="uniform:0:40")
-    assert np.any(np.diff(wl.utt_off) == 0), "want an empty utterance in this case"
+    wl = synth.make(1, D=20, C=200, R=8, U=12, lengths="uniform:1:40")
+    # empty utterances first, in the middle and last
+    off = wl.utt_off
+    off = np.concatenate([[0], off[:7], off[6:], off[-1:]]).astype(np.int64)
+    wl.utt_off = off
+    assert np.sum(np.diff(off) == 0) == 3
     gamma, lse = _oracle_frame(wl)
     n_ref, f_ref, S_ref = oracle.bw_stats(wl.X, wl.utt_off, gamma)
     g, *_ = _run_posteriors(wl)
@@ -111,6 +115,18 @@ def test_ragged_shapes_and_empty_utterance():
     np.testing.assert_allclose(f, f_ref, rtol=1e-5, atol=1e-4)
     empty = np.diff(wl.utt_off) == 0
     assert np.all(n[empty] == 0) and np.all(f[empty] == 0)
+
+
+def test_flat_posteriors_beyond_the_list_are_reported():
+    """D=7, C=200: ~32 components per frame within the margin and up to 1e-3
+    of the mass beyond the 16 best -- reported, not silently truncated."""
+    from paper_1906_08556_amd import ivx
+    wl = synth.make(1, D=7, C=200, R=8, U=12, lengths="uniform:1:40")
+    ctx = make_ctx(wl)
+    ctx.ubm_posteriors(dev(wl.X))
+    with pytest.raises(ivx.IvxError) as e:
+        ctx.sync_status()
+    assert e.value.status == -6
 
 
 def test_single_component_ubm():
