@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-utts", type=int, default=6)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="after the timed steps, copy this many MiB device-to-device once "
+                         "(reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -172,6 +175,14 @@ def main():
     prof = ctx.profile_read()
     ctx.profile_enable(0)
     ctx.sync_status()
+    if args.copy_calib_mib > 0:
+        nbytes = args.copy_calib_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nbytes} bytes read and written")
+        del src, dst
     K = args.steps
     ms_step = elapsed * 1e3 / K
     value = U * K / elapsed

@@ -191,7 +191,7 @@ ivx_status extract_ivectors(ivx_ctx* ctx, const float* X, const int64_t* utt_off
 
 /* ------------------------------------------------------ iteration finalise */
 
-/* M-step (Sec. 3.2 step 3), FP64: for every component with N_c >= 1,
+/* M-step (Sec. 3.2 step 3), FP64: for every component with N_c >= 0.5,
  *   T_c <- Cc_c A_c^{-1};  if update_sigma: Sigma_c <- sym((S_c - T_c Cc_c^T) / N_c)
  * S [C][D(D+1)/2] FP64 packed (from bw_stats).  acc->A is overwritten by the
  * Cholesky factors of A_c.  A new Sigma_c that is not positive definite is
@@ -200,7 +200,7 @@ ivx_status extract_ivectors(ivx_ctx* ctx, const float* X, const int64_t* utt_off
  *     parameters, sum_c N_c(-D/2 log 2pi - 1/2 log|Sigma_c|)
  *     - 1/2 sum_c tr(Sigma_c^{-1} S_c) + ll_sum, where ll_sum is read from
  *     ll_sum_dev [1] (the tv_estep ll_acc of the same pass).
- *   status [C] int32 or NULL: 0 updated, 1 skipped (N_c < 1), 2 Sigma not PD
+ *   status [C] int32 or NULL: 0 updated, 1 skipped (N_c < 0.5), 2 Sigma not PD
  *     (T updated, Sigma kept), 3 A_c not PD (nothing updated). */
 ivx_status tv_mstep_solve(ivx_ctx* ctx, const ivx_accum* acc, const double* S, int update_sigma,
                           const double* ll_sum_dev, double* objective, int32_t* status,

@@ -169,10 +169,13 @@ def objective(N, S, Sigma, ll_u_sum):
 # --------------------------------------------------------------------------
 # M-step (Sec. 3.2 step 3: T_c, then Sigma_c; factor-analysis EM cited there)
 # --------------------------------------------------------------------------
-def mstep(acc, S, T, Sigma, update_sigma=True, min_count=1.0):
+def mstep(acc, S, T, Sigma, update_sigma=True, min_count=0.5):
     """T_c <- Cc_c A_c^{-1};  Sigma_c <- sym((S_c - T_c^new Cc_c^T) / N_c).
 
-    A component with N_c < min_count keeps its T_c and Sigma_c.  A new Sigma_c
+    A component without data (N_c < min_count = 0.5) keeps its T_c and
+    Sigma_c.  The paper is silent on empty components; soft counts cluster at
+    integer frame counts when posteriors are near one-hot, so the threshold
+    sits between 0 and 1 frame rather than on an integer.  A new Sigma_c
     that is not positive definite is rejected (old one kept).
     Returns (T_new, Sigma_new, info) with info = dict(skipped=[...], notpd=[...]).
     """

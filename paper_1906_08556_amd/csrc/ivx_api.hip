@@ -118,7 +118,7 @@ void ivx_destroy(ivx_ctx* ctx) {
   void* ptrs[] = {ctx->w, ctx->mu, ctx->cov, ctx->shift, ctx->Wexp, ctx->linv, ctx->cst,
                   ctx->pairs, ctx->T, ctx->Sigma, ctx->p, ctx->cand, ctx->cflag, ctx->post_idx,
                   ctx->post_val, ctx->frame_ll, ctx->hist, ctx->coff, ctx->ent, ctx->partial,
-                  ctx->Y32, ctx->V32, ctx->Utp, ctx->Psig, ctx->sig_logdet, ctx->Lbuf, ctx->Wbuf,
+                  ctx->Y32, ctx->V32, ctx->Utp, ctx->Psig, ctx->sig_logdet, ctx->Lbuf, ctx->Wbuf, ctx->Psi64,
                   ctx->bpart, ctx->bvec, ctx->llu, ctx->n_ws, ctx->f_ws, ctx->Tnew, ctx->obj_part,
                   ctx->Gmat, ctx->Mmat, ctx->mvec, ctx->mstat, ctx->dev_err};
   for (void* p : ptrs)
@@ -187,6 +187,7 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   A(dalloc(&c->sig_logdet, C));
   A(dalloc(&c->Lbuf, U * TP));
   A(dalloc(&c->Wbuf, U * TP));
+  A(dalloc(&c->Psi64, U * TP));
   A(dalloc(&c->bpart, (size_t)c->nsplit_max * U * R));
   A(dalloc(&c->bvec, U * R));
   A(dalloc(&c->llu, U));

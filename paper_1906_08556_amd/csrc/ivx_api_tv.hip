@@ -150,33 +150,11 @@ ivx_status tv_mstep_accumulate(ivx_ctx* ctx, const float* n, const float* f, con
   hipStream_t s = as_stream(stream);
   const int C = ctx->C, D = ctx->D, R = ctx->R;
   ProfScope ps(ctx, PK_ACCUM, s);
-  launch_packed_to_psi(ctx, Phi, phi, U, ctx->Wbuf, s);
-  // A_c += sum_u n_c(u) Psi(u)
-  GemmArgs ga;
-  ga.A = n;
-  ga.lda = C;
-  ga.B = ctx->Wbuf;
-  ga.ldb = ctx->TP;
-  ga.C = acc->A;
-  ga.ldc = ctx->TP;
-  ga.M = C;
-  ga.N = (int)ctx->TP;
-  ga.K = (int)U;
-  ivx_status st = gemm(ga, true, false, GEMM_ADD_F64, 1, s, "tv_mstep_accumulate");
-  if (st != IVX_OK) return st;
-  // Cc_c += sum_u f_c(u) phi(u)^T
-  GemmArgs gc;
-  gc.A = f;
-  gc.lda = (int64_t)C * D;
-  gc.B = phi;
-  gc.ldb = R;
-  gc.C = acc->Cc;
-  gc.ldc = R;
-  gc.M = C * D;
-  gc.N = R;
-  gc.K = (int)U;
-  if ((st = gemm(gc, true, false, GEMM_ADD_F64, 1, s, "tv_mstep_accumulate")) != IVX_OK) return st;
-  launch_colsums(ctx, n, phi, ctx->Wbuf, U, acc, s);
+  launch_packed_to_psi(ctx, Phi, phi, U, ctx->Psi64, s);
+  // A_c += sum_u n_c(u) Psi(u), Cc_c += sum_u f_c(u) phi(u)^T: FP64 products and sums
+  gemm64_tn(n, C, ctx->Psi64, true, ctx->TP, acc->A, ctx->TP, C, (int)ctx->TP, (int)U, s);
+  gemm64_tn(f, (int64_t)C * D, phi, false, R, acc->Cc, R, C * D, R, (int)U, s);
+  launch_colsums(ctx, n, phi, ctx->Psi64, U, acc, s);
   return after_launch("tv_mstep_accumulate");
 }
 

@@ -108,7 +108,8 @@ struct ivx_ctx {
   // utterance-batch workspace
   int nsplit_max = 64;
   float* Lbuf = nullptr;      // [maxU][TP] L(u) -> G -> Phi(u)
-  float* Wbuf = nullptr;      // [maxU][TP] G^{-1}, or Psi(u) in the accumulate call
+  float* Wbuf = nullptr;      // [maxU][TP] G^{-1}
+  double* Psi64 = nullptr;    // [maxU][TP] Psi(u) = Phi(u) + phi phi^T (accumulate call)
   float* bpart = nullptr;     // [nsplit_max][maxU][R]
   float* bvec = nullptr;      // [maxU][R]
   double* llu = nullptr;      // [maxU]

@@ -13,9 +13,9 @@ void launch_reduce_b(ivx_ctx* ctx, const float* part, int nsplit, int64_t sstrid
 void launch_estep_chol(ivx_ctx* ctx, int64_t U, float* Lb, float* Wb, const float* b, float* phi,
                        double* llu, int* info, bool want_cov, hipStream_t s);
 void launch_tp_to_packed(ivx_ctx* ctx, const float* Ptp, int64_t U, float* out, hipStream_t s);
-void launch_packed_to_psi(ivx_ctx* ctx, const float* Phi, const float* phi, int64_t U, float* Psi,
+void launch_packed_to_psi(ivx_ctx* ctx, const float* Phi, const float* phi, int64_t U, double* Psi,
                           hipStream_t s);
-void launch_colsums(ivx_ctx* ctx, const float* n, const float* phi, const float* Psi, int64_t U,
+void launch_colsums(ivx_ctx* ctx, const float* n, const float* phi, const double* Psi, int64_t U,
                     const ivx_accum* acc, hipStream_t s);
 
 // ---- k_mstep.hip

@@ -21,6 +21,9 @@ namespace ivx {
 namespace {
 
 constexpr double kLog2Pi = 1.8378770664093454836;
+// Components with N_c below this (no frames: soft counts cluster at integer
+// frame counts when posteriors are near one-hot) keep T_c and Sigma_c.
+constexpr double kMinCount = 0.5;
 
 __device__ inline int64_t tile_off(int bi, int bj) { return (int64_t)(bi * (bi + 1) / 2 + bj) * 256; }
 
@@ -87,7 +90,7 @@ k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
   __shared__ int s_bad;
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double Nc = N[c];
-  if (!(Nc >= 1.0)) {  // too little data: keep T_c, Sigma_c
+  if (!(Nc >= kMinCount)) {  // no data: keep T_c, Sigma_c
     if (tid == 0) status[c] = 1;
     return;
   }

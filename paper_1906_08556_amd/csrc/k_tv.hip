@@ -418,9 +418,10 @@ __global__ void k_tp_to_packed(const float* __restrict__ Ptp, int64_t TP, int R,
   out[idx] = Ptp[u * TP + tile_off(j >> 4, i >> 4) + (j & 15) * 16 + (i & 15)];
 }
 
-// Psi(u) = Phi(u) + phi phi^T in tile-packed FP32 (padding zero)
+// Psi(u) = Phi(u) + phi phi^T in tile-packed FP64 (padding zero); the FP32
+// inputs are widened first, so the product phi phi^T is exact
 __global__ void k_packed_to_psi(const float* __restrict__ Phi, const float* __restrict__ phi,
-                                int64_t TP, int R, int64_t U, float* __restrict__ Psi) {
+                                int64_t TP, int R, int64_t U, double* __restrict__ Psi) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= U * TP) return;
   const int64_t u = idx / TP;
@@ -431,18 +432,19 @@ __global__ void k_packed_to_psi(const float* __restrict__ Phi, const float* __re
   while ((int64_t)bi * (bi + 1) / 2 > t) --bi;
   const int bj = (int)(t - (int64_t)bi * (bi + 1) / 2);
   const int r = bi * 16 + (int)((e >> 4) & 15), c = bj * 16 + (int)(e & 15);
-  float v = 0.0f;
+  double v = 0.0;
   if (r < R && c < R) {
     const int i = c < r ? c : r, j = c < r ? r : c;  // i <= j
     const int64_t k = (int64_t)i * R - (int64_t)i * (i - 1) / 2 + (j - i);
-    v = Phi[u * ((int64_t)R * (R + 1) / 2) + k] + phi[u * R + r] * phi[u * R + c];
+    v = (double)Phi[u * ((int64_t)R * (R + 1) / 2) + k] +
+        (double)phi[u * R + r] * (double)phi[u * R + c];
   }
   Psi[idx] = v;
 }
 
 // N[c] += sum_u n[u][c]; h[r] += sum_u phi[u][r]; H[e] += sum_u Psi[u][e]; count += U
 __global__ void k_colsums(const float* __restrict__ n, const float* __restrict__ phi,
-                          const float* __restrict__ Psi, int64_t U, int C, int R, int64_t TP,
+                          const double* __restrict__ Psi, int64_t U, int C, int R, int64_t TP,
                           double* __restrict__ N, double* __restrict__ h, double* __restrict__ H,
                           double* __restrict__ count) {
   const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -500,14 +502,14 @@ void launch_tp_to_packed(ivx_ctx* ctx, const float* Ptp, int64_t U, float* out, 
   k_tp_to_packed<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(Ptp, ctx->TP, ctx->R, U, out);
 }
 
-void launch_packed_to_psi(ivx_ctx* ctx, const float* Phi, const float* phi, int64_t U, float* Psi,
+void launch_packed_to_psi(ivx_ctx* ctx, const float* Phi, const float* phi, int64_t U, double* Psi,
                           hipStream_t s) {
   const int64_t n = U * ctx->TP;
   if (n <= 0) return;
   k_packed_to_psi<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(Phi, phi, ctx->TP, ctx->R, U, Psi);
 }
 
-void launch_colsums(ivx_ctx* ctx, const float* n, const float* phi, const float* Psi, int64_t U,
+void launch_colsums(ivx_ctx* ctx, const float* n, const float* phi, const double* Psi, int64_t U,
                     const ivx_accum* acc, hipStream_t s) {
   const int64_t total = ctx->C + ctx->R + ctx->TP;
   k_colsums<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(n, phi, Psi, U, ctx->C, ctx->R, ctx->TP,

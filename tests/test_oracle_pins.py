@@ -293,7 +293,7 @@ def test_mstep_is_a_stationary_point_of_the_em_auxiliary_function():
 def test_mstep_skips_components_without_data():
     wl = _tiny(D=3, C=4, R=2)
     T, Sigma, p = _random_tv(wl)
-    acc = dict(N=np.array([0.5, 2.0, 0.0, 3.0]), A=np.tile(2 * np.eye(2), (4, 1, 1)),
+    acc = dict(N=np.array([0.4, 2.0, 0.0, 3.0]), A=np.tile(2 * np.eye(2), (4, 1, 1)),
                Cc=np.ones((4, 3, 2)))
     S = np.tile(10 * np.eye(3), (4, 1, 1))
     T1, S1, info = oracle.mstep(acc, S, T, Sigma)
