@@ -199,7 +199,7 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   A(dalloc(&c->Mmat, R * R));
   A(dalloc(&c->mvec, 4 * R));
   A(dalloc(&c->mstat, C));
-  A(dalloc(&c->dev_err, 2));
+  A(dalloc(&c->dev_err, 4));
   if (!ok) {
     ivx_destroy(c);
     hipGetLastError();
@@ -213,7 +213,7 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
     return IVX_EDEVICE;
   }
   std::vector<uint16_t> pairs = make_pairs(c->D, c->Kpad);
-  int init_err[2] = {0, 0x7fffffff};
+  int init_err[4] = {0, 0x7fffffff, -1, 0};
   if (hipMemcpy(c->pairs, pairs.data(), pairs.size() * sizeof(uint16_t), hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemcpy(c->dev_err, init_err, sizeof(init_err), hipMemcpyHostToDevice) != hipSuccess) {
@@ -229,28 +229,37 @@ ivx_status ivx_sync_status(ivx_ctx* ctx, void* stream) {
   IVX_CHECK(ctx, "ivx_sync_status: null context");
   if (set_device(ctx) != IVX_OK) return IVX_EDEVICE;
   IVX_HIP(hipStreamSynchronize(as_stream(stream)));
-  int e[2];
+  int e[4];
   IVX_HIP(hipMemcpy(e, ctx->dev_err, sizeof(e), hipMemcpyDeviceToHost));
-  const int reset[2] = {0, 0x7fffffff};
+  const int reset[4] = {0, 0x7fffffff, -1, 0};
   IVX_HIP(hipMemcpy(ctx->dev_err, reset, sizeof(reset), hipMemcpyHostToDevice));
+  static const char* kSrc[PK_COUNT] = {"frame select", "rescoring", "n/f statistics",
+                                       "second-order statistics", "TV precompute (Sigma_c)",
+                                       "E-step GEMMs", "E-step Cholesky of L(u)",
+                                       "accumulators", "M-step (A_c)", "minimum divergence (G)",
+                                       "UBM preparation (covariance)"};
+  const char* src = (e[2] >= 0 && e[2] < PK_COUNT) ? kSrc[e[2]] : "?";
+  const int idx = e[1] == 0x7fffffff ? -1 : e[1];
   switch (e[0]) {
     case 0:
       return IVX_OK;
     case IVX_ENOTPD:
-      set_error("device: matrix not positive definite (first index %d)", e[1]);
+      set_error("device: matrix not positive definite in %s (first index %d, %d events)", src, idx,
+                e[3]);
       break;
     case IVX_EINVAL:
-      set_error("device: malformed utterance offsets");
+      set_error("device: malformed utterance offsets (utterance %d)", idx);
       break;
     case IVX_ENUMERIC:
-      set_error("device: non-finite value");
+      set_error("device: non-finite value in %s (index %d, %d events)", src, idx, e[3]);
       break;
     case IVX_ECAPACITY:
-      set_error("device: a frame has more than %d components within the posterior margin and "
-                "the components beyond them carry more than %g of its mass", KP, kMaxDroppedMass);
+      set_error("device: frame %d has more than %d components within the posterior margin and "
+                "the components beyond them carry more than %g of its mass (%d frames)",
+                idx, KP, kMaxDroppedMass, e[3]);
       break;
     default:
-      set_error("device: error %d", e[0]);
+      set_error("device: error %d in %s", e[0], src);
   }
   return (ivx_status)e[0];
 }

@@ -48,9 +48,14 @@ inline int64_t tp_size(int R) {
 // Records a message for ivx_last_error() (printf-style).
 void set_error(const char* fmt, ...);
 
-// Device-side error codes written (first one wins) into ctx->dev_err.
-__device__ inline void raise_error(int* err, int code) {
-  if (err) atomicCAS(err, 0, code);
+// Device-side error state ctx->dev_err[4]: [0] first error code, [1] smallest
+// failing index reported with it (component / utterance), [2] the kernel group
+// (ProfKernel) that raised the first error, [3] count of raising events.
+__device__ inline void raise_error(int* err, int code, int source, int index = -1) {
+  if (!err) return;
+  if (atomicCAS(err, 0, code) == 0) err[2] = source;
+  if (index >= 0) atomicMin(err + 1, index);
+  atomicAdd(err + 3, 1);
 }
 
 }  // namespace ivx
@@ -124,7 +129,7 @@ struct ivx_ctx {
   double* mvec = nullptr;     // [4][R]
   int* mstat = nullptr;       // [C]
 
-  int* dev_err = nullptr;     // [2]: first error code, smallest failing index
+  int* dev_err = nullptr;     // [4]: see raise_error
 
   // event profiler (off unless ivx_profile_enable)
   bool prof_on = false;

@@ -241,9 +241,9 @@ k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __
   for (int s = 0; s < m; ++s) se += exp(lsh[wave][s] - mx);
   const double kept = mx + log(se);
   const double lse = isnan(full_lse) ? kept : full_lse;
-  if (!isfinite(lse) && lane == 0) raise_error(err, IVX_ENUMERIC);
+  if (!isfinite(lse) && lane == 0) raise_error(err, IVX_ENUMERIC, PK_RESCORE, (int)g);
   if (!isnan(full_lse) && lane == 0 && 1.0 - exp(kept - full_lse) > kMaxDroppedMass)
-    raise_error(err, IVX_ECAPACITY);
+    raise_error(err, IVX_ECAPACITY, PK_RESCORE, (int)g);
   if (lane < KP) {
     int id = -1;
     float v = 0.0f;

@@ -170,8 +170,7 @@ k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
   if (s_bad) {
     if (tid == 0) {
       status[c] = 3;
-      raise_error(err, IVX_ENOTPD);
-      atomicMin(err + 1, c);
+      raise_error(err, IVX_ENOTPD, PK_MSTEP, c);
     }
     return;
   }
@@ -334,7 +333,7 @@ k_mindiv_setup(int R, int nb, const double* __restrict__ hsum, const double* __r
   }
   __syncthreads();
   if (bad) {  // leave T and p unchanged: M = I
-    if (tid == 0) raise_error(err, IVX_ENOTPD);
+    if (tid == 0) raise_error(err, IVX_ENOTPD, PK_MINDIV);
     for (int e = tid; e < R * R; e += 256) M[e] = (e / R == e % R) ? 1.0 : 0.0;
     return;
   }

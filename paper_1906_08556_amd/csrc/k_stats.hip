@@ -28,7 +28,7 @@ k_stats_nf(const float* __restrict__ X, const int64_t* __restrict__ utt_off, int
   const bool bad = (t0 > t1) || (t0 < 0) || (t1 > F) || (u == 0 && t0 != 0) ||
                    (u == U - 1 && t1 != F);
   if (bad) {
-    if (tid == 0 && blockIdx.y == 0) raise_error(err, IVX_EINVAL);
+    if (tid == 0 && blockIdx.y == 0) raise_error(err, IVX_EINVAL, PK_STATS_NF, (int)u);
     t0 = t1 = 0;
   }
   for (int i = tid; i < NFB * DS; i += 256) acc[i] = 0.0f;

@@ -59,8 +59,7 @@ k_tv_prep(const double* __restrict__ T, const double* __restrict__ Sigma, int D,
   __syncthreads();
   if (bad) {
     if (t == 0) {
-      raise_error(err, IVX_ENOTPD);
-      atomicMin(err + 1, c);
+      raise_error(err, IVX_ENOTPD, PK_TV_PREP, c);
       logdet[c] = NAN;
     }
     return;
@@ -235,7 +234,7 @@ k_estep_chol(int R, int nb, int64_t TP, float* __restrict__ Lb, float* __restric
   if (s_bad) {
     if (tid == 0) {
       if (info) info[u] = s_bad;
-      raise_error(err, IVX_ENOTPD);
+      raise_error(err, IVX_ENOTPD, PK_ESTEP_CHOL, (int)u);
       llu[u] = 0.0;
     }
     for (int i = tid; i < R; i += 256) phi[u * R + i] = NAN;

@@ -76,8 +76,7 @@ __global__ void __launch_bounds__(64) k_ubm_prepare(
   __syncthreads();
   if (bad) {
     if (t == 0) {
-      raise_error(err, IVX_ENOTPD);
-      atomicMin(err + 1, c);
+      raise_error(err, IVX_ENOTPD, PK_UBM, c);
     }
     for (int k = t; k < Kpad; k += 64) wrow[k] = (k == 0) ? -1e30f : 0.0f;
     if (t == 0) cst_out[c] = -INFINITY;

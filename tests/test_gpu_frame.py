@@ -165,4 +165,4 @@ def test_non_pd_covariance_is_rejected():
     ctx = ivx.Context(10, 5, 4, 3, wl.F)
     with pytest.raises(ivx.IvxError) as e:
         ctx.set_ubm(dev(wl.w), dev(wl.mu), dev(cov))
-    assert e.value.status == -3 and "7" in str(e.value)
+    assert e.value.status == -3 and "index 7" in str(e.value)
