@@ -173,6 +173,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     prof = ctx.profile_read()
+    K = args.steps
     ctx.profile_enable(0)
     ctx.sync_status()
     if args.copy_calib_mib > 0:
@@ -183,22 +184,24 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {nbytes} bytes read and written")
         del src, dst
-    K = args.steps
     ms_step = elapsed * 1e3 / K
     value = U * K / elapsed
     frames_per_s = F * K / (phase["frame"] / 1e3)
     em_utts_per_s = U * K / (phase["em"] / 1e3)
 
-    # roofline of the dominant kernel: the expanded-feature frame GEMM
+    # roofline of the dominant kernel: the expanded-feature frame GEMM, one
+    # launch per 256-component tile (C/256 launches per pass over the frames)
     Kexp = (D + 1) * (D + 2) // 2
-    flop_per_frame = 2.0 * Kexp * C
+    tile = 256
+    flop_per_frame_tile = 2.0 * Kexp * tile
     fs_ms, fs_calls = prof["frame_select"]
     fs_avg_s = fs_ms / max(fs_calls, 1) / 1e3
-    achieved = flop_per_frame * F / fs_avg_s / 1e12
-    roof = {"kernel": "k_frame_select", "bound": "mfma", "achieved": round(achieved, 2),
+    achieved = flop_per_frame_tile * F / fs_avg_s / 1e12
+    roof = {"kernel": "k_frame_tile", "bound": "mfma", "achieved": round(achieved, 2),
             "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
-            "avg_launch_ms": round(fs_avg_s * 1e3, 3), "flop_per_frame": flop_per_frame}
+            "avg_launch_ms": round(fs_avg_s * 1e3, 3), "launches_per_step": fs_calls // K,
+            "flop_per_frame_per_launch": flop_per_frame_tile, "frames_per_launch": F}
     log("[bench] kernel groups (ms per step): " + ", ".join(
         f"{k}={v[0] / K:.2f}" for k, v in prof.items() if v[1]))
     log(f"[bench] objective after last step: {obj.item():.6e}")

@@ -116,7 +116,7 @@ void ivx_destroy(ivx_ctx* ctx) {
     prof_free(ctx);
   }
   void* ptrs[] = {ctx->w, ctx->mu, ctx->cov, ctx->shift, ctx->Wexp, ctx->linv, ctx->cst,
-                  ctx->pairs, ctx->T, ctx->Sigma, ctx->p, ctx->cand, ctx->cflag, ctx->post_idx,
+                  ctx->pairs, ctx->T, ctx->Sigma, ctx->p, ctx->cand, ctx->cM, ctx->cflag, ctx->post_idx,
                   ctx->post_val, ctx->frame_ll, ctx->hist, ctx->coff, ctx->ent, ctx->partial,
                   ctx->Y32, ctx->V32, ctx->Utp, ctx->Psig, ctx->sig_logdet, ctx->Lbuf, ctx->Wbuf, ctx->Psi64,
                   ctx->bpart, ctx->bvec, ctx->llu, ctx->n_ws, ctx->f_ws, ctx->Tnew, ctx->obj_part,
@@ -171,6 +171,7 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   A(dalloc(&c->Sigma, C * D * D));
   A(dalloc(&c->p, R));
   A(dalloc(&c->cand, F * KP));
+  A(dalloc(&c->cM, F));
   A(dalloc(&c->cflag, F));
   A(dalloc(&c->post_idx, F * KP));
   A(dalloc(&c->post_val, F * KP));
@@ -348,10 +349,7 @@ ivx_status ubm_posteriors(ivx_ctx* ctx, const float* X, int64_t F, ivx_precision
   hipStream_t s = as_stream(stream);
   int* pi = post_idx ? post_idx : ctx->post_idx;
   float* pv = post_val ? post_val : ctx->post_val;
-  {
-    ProfScope ps(ctx, PK_FRAME_SELECT, s);
-    launch_frame_select(ctx, X, F, s);
-  }
+  launch_frame_select(ctx, X, F, s);
   {
     ProfScope ps(ctx, PK_RESCORE, s);
     launch_rescore(ctx, X, F, pi, pv, frame_ll, s);
@@ -369,10 +367,7 @@ ivx_status bw_stats(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_
   IVX_CHECK(utt_off && n && f, "bw_stats: null utt_off / n / f");
   if (set_device(ctx) != IVX_OK) return IVX_EDEVICE;
   hipStream_t s = as_stream(stream);
-  {
-    ProfScope ps(ctx, PK_FRAME_SELECT, s);
-    launch_frame_select(ctx, X, F, s);
-  }
+  launch_frame_select(ctx, X, F, s);
   {
     ProfScope ps(ctx, PK_RESCORE, s);
     launch_rescore(ctx, X, F, ctx->post_idx, ctx->post_val, ctx->frame_ll, s);

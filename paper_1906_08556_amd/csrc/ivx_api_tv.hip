@@ -174,10 +174,7 @@ ivx_status extract_ivectors(ivx_ctx* ctx, const float* X, const int64_t* utt_off
     return IVX_EDEVICE;
   }
   hipStream_t s = as_stream(stream);
-  {
-    ProfScope ps(ctx, PK_FRAME_SELECT, s);
-    launch_frame_select(ctx, X, F, s);
-  }
+  launch_frame_select(ctx, X, F, s);
   {
     ProfScope ps(ctx, PK_RESCORE, s);
     launch_rescore(ctx, X, F, ctx->post_idx, ctx->post_val, ctx->frame_ll, s);

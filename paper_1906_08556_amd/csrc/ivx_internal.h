@@ -80,7 +80,7 @@ struct ivx_ctx {
   double* cov = nullptr;    // [C][D][D]
   // UBM-derived
   float* shift = nullptr;     // [D] global mean shift applied before expansion
-  float* Wexp = nullptr;      // [Cpad][Kpad] expanded quadratic-form coefficients
+  float* Wexp = nullptr;      // [Kpad/8][Cpad][8] expanded quadratic-form coefficients
   double* linv = nullptr;     // [C][Dp] L_c^{-1}, lower triangle column by column
   double* cst = nullptr;      // [C] log w_c - D/2 log 2pi - sum_i log L_c[i,i]
   uint16_t* pairs = nullptr;  // [Kpad] expanded-feature index pairs (a | b << 8)
@@ -91,8 +91,9 @@ struct ivx_ctx {
   double* p = nullptr;      // [R]
 
   // frame-stage workspace
-  int* cand = nullptr;        // [maxF][KP]
-  int* cflag = nullptr;       // [maxF]
+  int2* cand = nullptr;       // [maxF][KP] candidate (component, FP32 score bits)
+  float* cM = nullptr;        // [maxF] running maximum of the FP32 scores
+  int* cflag = nullptr;       // [maxF] candidate-list overflow
   int* post_idx = nullptr;    // [maxF][KP]
   float* post_val = nullptr;  // [maxF][KP]
   double* frame_ll = nullptr; // [maxF]

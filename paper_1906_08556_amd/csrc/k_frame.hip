@@ -1,6 +1,6 @@
 // Frame posteriors against the full-covariance UBM over all C components.
 //
-// Stage 1 (k_frame_select): the log-likelihood of every (frame, component)
+// Stage 1 (k_frame_tile): the log-likelihood of every (frame, component)
 // pair is one dot product of the expanded feature vector vech(x~ x~^T),
 // x~ = [1, x - s], with the component's coefficient row (see k_ubm.hip).  The
 // product runs on MFMA (v_mfma_f32_32x32x2_f32) with components on the M side
@@ -26,40 +26,47 @@ constexpr int FR = 32;        // frames per wave (one 32-frame MFMA block)
 constexpr int NW = 4;         // waves per workgroup
 constexpr int FT = FR * NW;   // frames per workgroup
 constexpr int NCB = 8;        // 32-component MFMA blocks per tile
-constexpr int CT = 32 * NCB;  // components per tile
+constexpr int CT = 32 * NCB;  // components per launch (one tile)
 constexpr int CAPL = KP / 2;  // candidate slots per lane-half per frame
+constexpr int WLD = 12;       // LDS row stride (floats) of a staged [CT][8] W chunk
 
-__device__ inline void append_cand(int2* list, int& cnt, bool& ovf, int comp, float val,
-                                   float thr) {
-  if (cnt == CAPL) {  // drop entries that fell below the running threshold
-    int w = 0;
-    for (int s = 0; s < CAPL; ++s) {
-      const int2 e = list[s * 64];
-      if (__int_as_float(e.y) >= thr) list[(w++) * 64] = e;
-    }
-    cnt = w;
+// Drops the entries of a lane-half's candidate list (global, CAPL slots,
+// filled from slot 0) that fell below the running threshold.
+__device__ inline int compact_cands(int2* __restrict__ lst, float thr) {
+  int w = 0;
+  for (int s = 0; s < CAPL; ++s) {
+    const int2 e = lst[s];
+    if (e.x >= 0 && __int_as_float(e.y) >= thr) lst[w++] = e;
   }
-  if (cnt < CAPL) {
-    list[cnt * 64] = make_int2(comp, __float_as_int(val));
-    ++cnt;
-  } else {
-    ovf = true;
-  }
+  for (int s = w; s < CAPL; ++s) lst[s] = make_int2(-1, 0);
+  return w;
 }
 
+// One launch per 256-component tile [c0, c0 + 256).  All workgroups of a
+// launch stream the same 1.9 MB slice of W, so it stays resident in every
+// XCD's L2; chunks of 8 expanded features are staged through LDS (double
+// buffered) and shared by the 4 waves.  The per-frame running maximum M, the
+// candidate lists and the overflow flag persist in global memory between
+// launches.
+//
+// W layout (k_ubm_prepare): chunk-major, coefficient (c, k) at
+// ((k / 8) * Cpad + c) * 8 + k % 8, so a chunk of a tile is contiguous.
 __global__ void __launch_bounds__(256, 2)
-k_frame_select(const float* __restrict__ X, int64_t F, int D, const float* __restrict__ shift,
-               const float* __restrict__ W, int C, int Cpad, int Kpad,
-               const uint16_t* __restrict__ pairs, float margin, int* __restrict__ cand,
-               int* __restrict__ cflag) {
+k_frame_tile(const float* __restrict__ X, int64_t F, int D, const float* __restrict__ shift,
+             const float* __restrict__ W, int C, int Cpad, int Kpad,
+             const uint16_t* __restrict__ pairs, float margin, int c0, int first,
+             int2* __restrict__ cand, float* __restrict__ cM, int* __restrict__ cflag) {
   extern __shared__ float smem[];
   const int DS = D + 1;
-  float* xs = smem;                                                  // [FT][DS]
-  int2* cl = reinterpret_cast<int2*>(smem + ((FT * DS + 1) & ~1));  // [NW][CAPL][64]
+  float* Ws = smem;                                              // [2][CT][WLD]
+  float* xs = smem + 2 * CT * WLD;                               // [FT][DS]
+  uint32_t* prs = reinterpret_cast<uint32_t*>(xs + FT * DS);     // [Kpad/2] index pairs
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int64_t f0 = (int64_t)blockIdx.x * FT;
+  const int nq = Kpad / 8;
 
+  for (int i = tid; i < Kpad / 2; i += 256) prs[i] = reinterpret_cast<const uint32_t*>(pairs)[i];
   for (int i = tid; i < FT * DS; i += 256) {
     const int fr = i / DS, a = i - fr * DS;
     const int64_t g = f0 + fr;
@@ -67,86 +74,107 @@ k_frame_select(const float* __restrict__ X, int64_t F, int D, const float* __res
     if (a > 0 && g < F) v = X[g * D + (a - 1)] - shift[a - 1];
     xs[i] = v;
   }
-  __syncthreads();
+  // W chunk loader: thread t stages the 8 coefficients of component c0 + t
+  float4 r0, r1;
+  auto gload = [&](int q) {
+    const float4* p = reinterpret_cast<const float4*>(W + ((size_t)q * Cpad + c0 + tid) * 8);
+    r0 = p[0];
+    r1 = p[1];
+  };
+  auto sstore = [&](int buf) {
+    float* d = Ws + (buf * CT + tid) * WLD;
+    *reinterpret_cast<float4*>(d) = r0;
+    *reinterpret_cast<float4*>(d + 4) = r1;
+  };
+  gload(0);
+  sstore(0);
 
   const int h = lane >> 5, l32 = lane & 31;
-  const float* xw = xs + (wave * FR + l32) * DS;
-  int2* lst = cl + wave * CAPL * 64 + lane;
+  const int64_t g = f0 + wave * FR + l32;
+  const bool valid = g < F;
+  int2* lst = cand + (valid ? g : 0) * KP + h * CAPL;
   float M = -INFINITY;
   int cnt = 0;
   bool ov = false;
-  const int nq = Kpad / 8;
-
-  for (int c0 = 0; c0 < Cpad; c0 += CT) {
-    floatx16 acc[NCB];
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[cb] = floatx16{0};
-    const float* wp = W + (size_t)(c0 + l32) * Kpad + 4 * h;
-    float4 wn[NCB];
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-      wn[cb] = *reinterpret_cast<const float4*>(wp + (size_t)cb * 32 * Kpad);
-    uint2 pn = *reinterpret_cast<const uint2*>(pairs + 4 * h);
-    for (int q = 0; q < nq; ++q) {
-      float4 wc[NCB];
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) wc[cb] = wn[cb];
-      const uint2 pc = pn;
-      const int qn = (q + 1 < nq) ? (q + 1) : q;
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
-        wn[cb] = *reinterpret_cast<const float4*>(wp + (size_t)cb * 32 * Kpad + 8 * qn);
-      pn = *reinterpret_cast<const uint2*>(pairs + 8 * qn + 4 * h);
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const uint32_t pr = ((s < 2) ? pc.x : pc.y) >> ((s & 1) * 16);
-        const int a = pr & 0xff, b = (pr >> 8) & 0xff;
-        const float bv = xw[a] * xw[b];
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          const float av = (s == 0) ? wc[cb].x : (s == 1) ? wc[cb].y : (s == 2) ? wc[cb].z : wc[cb].w;
-          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[cb], 0, 0, 0);
-        }
-      }
-    }
-    // epilogue: lane holds frame l32 and rows 8*(r/4) + 4*h + r%4 of each
-    // 32-component block; its partner lane (lane ^ 32) holds the other rows
-    float vmax = -INFINITY;
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) vmax = fmaxf(vmax, acc[cb][r]);
-    const float lmax = vmax;
-    vmax = fmaxf(vmax, __shfl_xor(vmax, 32));
-    M = fmaxf(M, vmax);
-    const float thr = M - margin;
-    if (lmax >= thr) {
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const float v = acc[cb][r];
-          const int comp = c0 + cb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-          if (v >= thr && comp < C) append_cand(lst, cnt, ov, comp, v, thr);
-        }
+  if (valid) {
+    if (first) {
+      for (int s = 0; s < CAPL; ++s) lst[s] = make_int2(-1, 0);
+    } else {
+      M = cM[g];
+      ov = cflag[g] != 0;
+      for (int s = 0; s < CAPL; ++s)
+        if (lst[s].x >= 0) cnt = s + 1;
     }
   }
-  // final candidate list: half h writes slots h*CAPL .. h*CAPL + CAPL-1
+  __syncthreads();
+
+  floatx16 acc[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = floatx16{0};
+  const float* xw = xs + (wave * FR + l32) * DS;
+  for (int q = 0; q < nq; ++q) {
+    const int cur = q & 1;
+    if (q + 1 < nq) gload(q + 1);
+    const float* wb = Ws + (cur * CT + l32) * WLD + 4 * h;
+    float4 wv[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) wv[cb] = *reinterpret_cast<const float4*>(wb + cb * 32 * WLD);
+    const uint32_t pw0 = prs[4 * q + 2 * h], pw1 = prs[4 * q + 2 * h + 1];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const uint32_t pr = ((s < 2) ? pw0 : pw1) >> ((s & 1) * 16);
+      const int a = pr & 0xff, b = (pr >> 8) & 0xff;
+      const float bv = xw[a] * xw[b];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const float av = (s == 0) ? wv[cb].x : (s == 1) ? wv[cb].y : (s == 2) ? wv[cb].z : wv[cb].w;
+        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[cb], 0, 0, 0);
+      }
+    }
+    if (q + 1 < nq) sstore(cur ^ 1);
+    __syncthreads();
+  }
+  // epilogue: lane holds frame l32 and rows 8*(r/4) + 4*h + r%4 of each
+  // 32-component block; its partner lane (lane ^ 32) holds the other rows
+  float vmax = -INFINITY;
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) vmax = fmaxf(vmax, acc[cb][r]);
+  const float lmax = vmax;
+  vmax = fmaxf(vmax, __shfl_xor(vmax, 32));
+  M = fmaxf(M, vmax);
   const float thr = M - margin;
+  if (valid && lmax >= thr) {
+    // two unrolled passes with small bodies keep acc[] in registers:
+    // count this tile's hits, make room once, then store them
+    int nh = 0;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) nh += (acc[cb][r] >= thr) ? 1 : 0;
+    if (cnt + nh > CAPL) cnt = compact_cands(lst, thr);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float v = acc[cb][r];
+        const int comp = c0 + cb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (v >= thr && comp < C) {
+          if (cnt < CAPL) {
+            lst[cnt] = make_int2(comp, __float_as_int(v));
+            ++cnt;
+          } else {
+            ov = true;
+          }
+        }
+      }
+  }
   const int ovi = ov ? 1 : 0;
   const int ovp = __shfl_xor(ovi, 32);
-  const int64_t g = f0 + wave * FR + l32;
-  if (g < F) {
-#pragma unroll
-    for (int s = 0; s < CAPL; ++s) {
-      int v = -1;
-      if (s < cnt) {
-        const int2 e = lst[s * 64];
-        if (__int_as_float(e.y) >= thr) v = e.x;
-      }
-      cand[g * KP + h * CAPL + s] = v;
-    }
-    if (h == 0) cflag[g] = ovi | ovp;
+  if (valid && h == 0) {
+    cM[g] = M;
+    cflag[g] = ovi | ovp;
   }
 }
 
@@ -180,7 +208,8 @@ __device__ inline double exact_ll(int c, double xd, int lane, int D, int Dp,
 __global__ void __launch_bounds__(256)
 k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __restrict__ mu,
           const double* __restrict__ linv, const double* __restrict__ cst,
-          const int* __restrict__ cand, const int* __restrict__ cflag,
+          const int2* __restrict__ cand, const float* __restrict__ cM, float margin,
+          const int* __restrict__ cflag,
           int* __restrict__ post_idx, float* __restrict__ post_val, double* __restrict__ frame_ll,
           int* __restrict__ err) {
   __shared__ double dsh[4][64];
@@ -194,7 +223,12 @@ k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __
   int m = 0;
   double full_lse = NAN;  // set when all components were scored
   if (cflag[g] == 0) {
-    const int ci = (lane < KP) ? cand[g * KP + lane] : -1;
+    const float thr = cM[g] - margin;
+    int ci = -1;
+    if (lane < KP) {
+      const int2 e = cand[g * KP + lane];
+      if (e.x >= 0 && __int_as_float(e.y) >= thr) ci = e.x;
+    }
     for (int s = 0; s < KP; ++s) {
       const int c = __shfl(ci, s);
       if (c < 0 || c >= C) continue;
@@ -278,17 +312,14 @@ __global__ void k_scatter_gamma(int64_t F, int C, const int* __restrict__ post_i
 void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, hipStream_t s) {
   if (F <= 0) return;
   const int DS = ctx->D + 1;
-  const size_t lds = sizeof(float) * (((size_t)FT * DS + 1) & ~(size_t)1) +
-                     sizeof(int2) * NW * CAPL * 64;
+  const size_t lds = sizeof(float) * (2 * CT * WLD + (size_t)FT * DS) + sizeof(uint16_t) * ctx->Kpad;
   const unsigned nblk = (unsigned)((F + FT - 1) / FT);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_frame_select),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
+  for (int c0 = 0; c0 < ctx->Cpad; c0 += CT) {
+    ProfScope ps(ctx, PK_FRAME_SELECT, s);
+    k_frame_tile<<<nblk, 256, lds, s>>>(X, F, ctx->D, ctx->shift, ctx->Wexp, ctx->C, ctx->Cpad,
+                                        ctx->Kpad, ctx->pairs, ctx->margin, c0, c0 == 0 ? 1 : 0,
+                                        ctx->cand, ctx->cM, ctx->cflag);
   }
-  k_frame_select<<<nblk, 256, lds, s>>>(X, F, ctx->D, ctx->shift, ctx->Wexp, ctx->C, ctx->Cpad, ctx->Kpad,
-                                        ctx->pairs, ctx->margin, ctx->cand, ctx->cflag);
 }
 
 void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int* post_idx, float* post_val,
@@ -296,7 +327,8 @@ void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int* post_idx, floa
   if (F <= 0) return;
   const unsigned nblk = (unsigned)((F + 3) / 4);
   k_rescore<<<nblk, 256, 0, s>>>(X, F, ctx->D, ctx->C, ctx->mu, ctx->linv, ctx->cst, ctx->cand,
-                                 ctx->cflag, post_idx, post_val, frame_ll, ctx->dev_err);
+                                 ctx->cM, ctx->margin, ctx->cflag, post_idx, post_val, frame_ll,
+                                 ctx->dev_err);
 }
 
 void launch_dense_gamma(ivx_ctx* ctx, int64_t F, const int* post_idx, const float* post_val,

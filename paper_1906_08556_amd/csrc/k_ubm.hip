@@ -47,9 +47,11 @@ __global__ void __launch_bounds__(64) k_ubm_prepare(
   __shared__ int bad;
   const int c = blockIdx.x;
   const int t = threadIdx.x;
-  float* wrow = Wexp + (size_t)c * Kpad;
+  // chunk-major layout: coefficient (c, k) at ((k / 8) * Cpad + c) * 8 + k % 8
+  const int Cpad = gridDim.x;
+  auto wat = [&](int k) -> float& { return Wexp[((size_t)(k >> 3) * Cpad + c) * 8 + (k & 7)]; };
   if (c >= C) {  // padding rows of the frame GEMM: never a candidate
-    for (int k = t; k < Kpad; k += 64) wrow[k] = (k == 0) ? -1e30f : 0.0f;
+    for (int k = t; k < Kpad; k += 64) wat(k) = (k == 0) ? -1e30f : 0.0f;
     return;
   }
   for (int i = t; i < D * D; i += 64) A[i] = cov[(size_t)c * D * D + i];
@@ -78,7 +80,7 @@ __global__ void __launch_bounds__(64) k_ubm_prepare(
     if (t == 0) {
       raise_error(err, IVX_ENOTPD, PK_UBM, c);
     }
-    for (int k = t; k < Kpad; k += 64) wrow[k] = (k == 0) ? -1e30f : 0.0f;
+    for (int k = t; k < Kpad; k += 64) wat(k) = (k == 0) ? -1e30f : 0.0f;
     if (t == 0) cst_out[c] = -INFINITY;
     return;
   }
@@ -143,7 +145,7 @@ __global__ void __launch_bounds__(64) k_ubm_prepare(
         v = (i == jj) ? -0.5 * P : -P;
       }
     }
-    wrow[k] = (float)v;
+    wat(k) = (float)v;
   }
 }
 
