@@ -15,8 +15,8 @@ Parity status: every function here is pinned by a ``-m "not gpu"`` test
 against something other than itself (brute-force densities, Gaussian
 conditioning of the joint, brute-force marginal likelihoods, finite
 differences of the EM auxiliary function, stated invariants).  The one
-exception is ``mlp_*`` (added with the learned-selection form), pinned by
-finite differences.
+learned-selection functions of ``mlp`` are pinned by finite differences,
+closed forms and the k = C special case.
 """
 from .tv import (  # noqa: F401
     LOG2PI,
@@ -33,4 +33,18 @@ from .tv import (  # noqa: F401
     realign_means,
     extract,
     em_iteration,
+)
+from .mlp import (  # noqa: F401
+    feature_stats,
+    standardise,
+    mlp_forward,
+    log_softmax,
+    softmax,
+    ce_loss,
+    mlp_backward,
+    adam_update,
+    topk,
+    proposed_mass,
+    learned_posteriors,
+    missed_mass,
 )
