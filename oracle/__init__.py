@@ -38,6 +38,8 @@ from .mlp import (  # noqa: F401
     feature_stats,
     standardise,
     mlp_forward,
+    round_bf16,
+    mlp_forward_bf16,
     log_softmax,
     softmax,
     ce_loss,

@@ -46,6 +46,32 @@ def mlp_forward(params, Xh):
     return z, (Xh, a1, h1, a2, h2)
 
 
+def round_bf16(a):
+    """Round to the nearest BF16 value (ties to even) and return float32.
+    BF16 keeps the sign, the 8 exponent bits and the top 7 mantissa bits of
+    an IEEE float32 (finite inputs)."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).reshape(a.shape)
+
+
+def mlp_forward_bf16(params, X, mean, std):
+    """The deployed network's arithmetic, used where its output decides an
+    integer (the proposals, the fallback): x_hat = (x - mean) * (1 / std) in
+    FP32; weights and x_hat rounded to BF16; each layer's products summed in
+    FP32 with the bias added after the sum; ReLU, then rounding to BF16, for
+    the hidden layers.  Returns (z, h1, h2) as float32."""
+    W1, b1, W2, b2, W3, b3 = [np.asarray(p, dtype=np.float32) for p in params]
+    mean = np.asarray(mean, dtype=np.float32)
+    istd = (np.float32(1.0) / np.asarray(std, dtype=np.float32)).astype(np.float32)
+    xh = round_bf16((np.asarray(X, dtype=np.float32) - mean) * istd)
+    h1 = round_bf16(np.maximum(xh @ round_bf16(W1).T + b1, np.float32(0.0)))
+    h2 = round_bf16(np.maximum(h1 @ round_bf16(W2).T + b2, np.float32(0.0)))
+    z = (h2 @ round_bf16(W3).T + b3).astype(np.float32)
+    return z, h1, h2
+
+
 def log_softmax(z):
     m = z.max(axis=1, keepdims=True)
     return z - (m + np.log(np.exp(z - m).sum(axis=1, keepdims=True)))

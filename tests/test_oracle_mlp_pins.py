@@ -172,3 +172,41 @@ def test_everything_falls_back_when_min_mass_exceeds_one():
     assert fb.all()
     ref, _ = oracle.posteriors(oracle.frame_loglik(X, wl.w, wl.mu, wl.cov))
     np.testing.assert_allclose(gam, ref, atol=1e-14)
+
+
+def test_bf16_rounding_matches_torch_and_hand_cases():
+    import torch
+    rng = np.random.default_rng(10)
+    a = np.concatenate([rng.normal(size=5000) * 10.0 ** rng.integers(-30, 30, size=5000),
+                        [0.0, -0.0, 1.0, -2.5, 3.4e38]]).astype(np.float32)
+    ref = torch.from_numpy(a).to(torch.bfloat16).to(torch.float32).numpy()
+    np.testing.assert_array_equal(oracle.round_bf16(a), ref)
+    # ties go to the even mantissa: 1 + 2^-8 lies halfway between 1 and 1 + 2^-7
+    assert oracle.round_bf16(np.float32(1 + 2.0 ** -8)) == np.float32(1.0)
+    assert oracle.round_bf16(np.float32(1 + 3 * 2.0 ** -8)) == np.float32(1 + 2.0 ** -6)
+    assert oracle.round_bf16(np.float32(1 + 2.0 ** -9)) == np.float32(1.0)
+
+
+def test_bf16_forward_is_close_to_the_exact_network_and_exact_on_representable_values():
+    rng = np.random.default_rng(11)
+    params = _tiny_net(rng)
+    X = rng.normal(size=(50, 5))
+    mean, std = np.zeros(5), np.ones(5)
+    z64, _ = oracle.mlp_forward(params, X)
+    z16, h1, h2 = oracle.mlp_forward_bf16(params, X, mean, std)
+    assert np.abs(z16 - z64).max() <= 0.05 * np.abs(z64).max()
+    # small integers: every weight, input and hidden value lies on the BF16
+    # grid (|h| < 256) and every sum is exact in FP32, so the BF16 network
+    # equals integer arithmetic
+    W1 = rng.integers(-1, 2, size=(7, 5)).astype(float)
+    W2 = rng.integers(-1, 2, size=(6, 7)).astype(float)
+    W3 = rng.integers(-1, 2, size=(9, 6)).astype(float)
+    b = [rng.integers(-1, 2, size=n).astype(float) for n in (7, 6, 9)]
+    Xi = rng.integers(-2, 3, size=(40, 5)).astype(float)
+    z16, h1, h2 = oracle.mlp_forward_bf16((W1, b[0], W2, b[1], W3, b[2]), Xi, mean, std)
+    e1 = np.maximum(Xi @ W1.T + b[0], 0)
+    e2 = np.maximum(e1 @ W2.T + b[1], 0)
+    assert e2.max() < 256
+    np.testing.assert_array_equal(h1, e1)
+    np.testing.assert_array_equal(h2, e2)
+    np.testing.assert_array_equal(z16, e2 @ W3.T + b[2])
