@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-utts", type=int, default=6)
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 form")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device-to-device once "
                          "(reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -137,45 +138,57 @@ def main():
     ll_utt = torch.zeros(1, dtype=torch.float64, device=dev)
     obj = torch.zeros(1, dtype=torch.float64, device=dev)
     acc = ctx.new_accum()
-
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    phase = {"frame": 0.0, "em": 0.0}
+    w_d = torch.from_numpy(wl.w).to(dev)
+    mu_d = torch.from_numpy(wl.mu).to(dev)
+    cov_d = torch.from_numpy(wl.cov).to(dev)
+    T0_d = torch.from_numpy(wl.T_init).to(dev)
 
-    def step(timed):
+    def reset_model():
+        ctx.set_ubm(w_d, mu_d, cov_d)
+        ctx.init_tv(T0_d, 100.0)
+
+    def step(prec, phase=None):
         S.zero_()
         ll_frames.zero_()
         ll_utt.zero_()
         acc.zero_()
-        if timed:
+        if phase is not None:
             ev[0].record()
-        ctx.bw_stats(X, off, n, f, S_acc=S, ll_acc=ll_frames)
-        if timed:
+        ctx.bw_stats(X, off, n, f, S_acc=S, ll_acc=ll_frames, prec=prec)
+        if phase is not None:
             ev[1].record()
-        ctx.tv_estep(n, f, phi, Phi=Phi, ll_acc=ll_utt)
+        ctx.tv_estep(n, f, phi, Phi=Phi, ll_acc=ll_utt, prec=prec)
         ctx.tv_mstep_accumulate(n, f, phi, Phi, acc)
         ctx.tv_mstep_solve(acc, S, update_sigma=True, ll_sum=ll_utt, objective=obj)
         ctx.tv_mindiv(acc)
         ctx.ubm_update_means()
-        if timed:
+        if phase is not None:
             ev[2].record()
 
-    for _ in range(args.warmup):
-        step(False)
-    ctx.sync_status()
-    ctx.profile_enable(4096)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
-        torch.cuda.synchronize()  # phase events of this step complete
-        phase["frame"] += ev[0].elapsed_time(ev[1])
-        phase["em"] += ev[1].elapsed_time(ev[2])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    prof = ctx.profile_read()
+    def timed(prec, steps, warmup):
+        reset_model()
+        for _ in range(warmup):
+            step(prec)
+        ctx.sync_status()
+        ctx.profile_enable(4096)
+        phase = {"frame": 0.0, "em": 0.0}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(prec, phase)
+            torch.cuda.synchronize()  # the phase events of this step are complete
+            phase["frame"] += ev[0].elapsed_time(ev[1])
+            phase["em"] += ev[1].elapsed_time(ev[2])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = ctx.profile_read()
+        ctx.profile_enable(0)
+        ctx.sync_status()
+        return el, phase, prof
+
     K = args.steps
-    ctx.profile_enable(0)
-    ctx.sync_status()
+    elapsed, phase, prof = timed(0, K, args.warmup)
     if args.copy_calib_mib > 0:
         nbytes = args.copy_calib_mib << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
@@ -202,9 +215,38 @@ def main():
             "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
             "avg_launch_ms": round(fs_avg_s * 1e3, 3), "launches_per_step": fs_calls // K,
             "flop_per_frame_per_launch": flop_per_frame_tile, "frames_per_launch": F}
-    log("[bench] kernel groups (ms per step): " + ", ".join(
+    log("[bench] FP32 kernel groups (ms per step): " + ", ".join(
         f"{k}={v[0] / K:.2f}" for k, v in prof.items() if v[1]))
     log(f"[bench] objective after last step: {obj.item():.6e}")
+
+    bf16 = None
+    if not args.no_bf16:
+        el16, ph16, prof16 = timed(1, K, args.warmup)
+        fs16_ms, fs16_calls = prof16["frame_select"]
+        fs16_avg_s = fs16_ms / max(fs16_calls, 1) / 1e3
+        bf16_peak = 2500.0
+        ach16 = 3.0 * flop_per_frame_tile * F / fs16_avg_s / 1e12  # three BF16 products per FP32 one
+        log("[bench] BF16 kernel groups (ms per step): " + ", ".join(
+            f"{k}={v[0] / K:.2f}" for k, v in prof16.items() if v[1]))
+        # one iteration of each form from the same initial model: BF16 vs FP32
+        outs = {}
+        for prec in (0, 1):
+            reset_model()
+            step(prec)
+            ctx.sync_status()
+            outs[prec] = (phi.double().cpu().numpy(), obj.item())
+        a, b = outs[1][0], outs[0][0]
+        cos = (a * b).sum(1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1))
+        bf16 = {"utts_per_s": round(U * K / el16, 3), "ms_per_step": round(el16 * 1e3 / K, 3),
+                "frame_posteriors_per_s": round(F * K / (ph16["frame"] / 1e3), 1),
+                "tv_em_utts_per_s": round(U * K / (ph16["em"] / 1e3), 3),
+                "frame_kernel": {"kernel": "k_frame_tile_bf16", "achieved_bf16_tflops": round(ach16, 2),
+                                 "peak": bf16_peak, "frac": round(ach16 / bf16_peak, 4),
+                                 "avg_launch_ms": round(fs16_avg_s * 1e3, 3)},
+                "vs_fp32_form_first_iteration": {
+                    "ivector_min_cosine": float(cos.min()),
+                    "objective_rel_diff": abs(outs[1][1] - outs[0][1]) / abs(outs[0][1])}}
+        log(f"[bench] BF16 form: {bf16}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -235,6 +277,7 @@ def main():
         "phase_ms_per_step": {"frame_stage": round(phase["frame"] / K, 3),
                               "em_stage": round(phase["em"] / K, 3)},
         "roofline": roof,
+        "bf16_form": bf16,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -57,6 +57,15 @@ typedef enum {
 } ivx_status;
 
 typedef enum { IVX_FP32 = 0, IVX_BF16 = 1 } ivx_precision;
+/* Which components a frame's posterior is computed over.
+ *   IVX_SEL_ALL      every component (Sec. 4.2 posteriors, exact).
+ *   IVX_SEL_LEARNED  the k proposals of the learned selector (ivx_selector_set),
+ *                    scored exactly and renormalised over the proposals; a
+ *                    frame whose proposals carry less than min_mass of the
+ *                    network's softmax falls back to IVX_SEL_ALL.  This stands
+ *                    where the paper's diagonal-UBM preselection of 20
+ *                    components stands (Sec. 4.2); the network is not from the
+ *                    paper. */
 typedef enum { IVX_SEL_ALL = 0, IVX_SEL_LEARNED = 1 } ivx_selection;
 
 /* Problem dimensions, fixed for the life of a context.
@@ -215,6 +224,94 @@ ivx_status tv_mindiv(ivx_ctx* ctx, const ivx_accum* acc, int method, void* strea
 /* Realignment (Sec. 3.2 step 5): mu_c <- p[0] * T_c[:, 0], then re-derives
  * the UBM quantities used by ubm_posteriors. */
 ivx_status ubm_update_means(ivx_ctx* ctx, void* stream);
+
+/* -------------------------------------------------------- iteration graphs */
+
+typedef struct ivx_graph ivx_graph;
+
+/* Records one full EM iteration (Sec. 3.2, steps 1-5) into a HIP graph:
+ * clears S, the accumulators and the two log-likelihood sums (fill kernels),
+ * then bw_stats, tv_estep (with the TV precompute), tv_mstep_accumulate,
+ * tv_mstep_solve (objective at the incoming parameters into objective[0]),
+ * tv_mindiv (Cholesky whitening) and, if realign != 0, ubm_update_means.
+ * Every pointer is caller-owned device memory with the layout of the
+ * corresponding call; it is bound at capture time and must stay valid for
+ * the life of the graph.  Capture runs on a private stream and executes
+ * nothing; each ivx_graph_launch runs one iteration on `stream`. */
+ivx_status ivx_graph_create_em(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_t U,
+                               int64_t F, ivx_precision prec, float* n, float* f, double* S,
+                               float* phi, float* Phi, const ivx_accum* acc, double* ll_frames,
+                               double* ll_utts, double* objective, int update_sigma, int realign,
+                               ivx_graph** out);
+ivx_status ivx_graph_launch(ivx_graph* g, void* stream);
+void ivx_graph_destroy(ivx_graph* g);
+
+/* ------------------------------------------------------- learned selection */
+
+/* The selector network: z = W3 relu(W2 relu(W1 x_hat + b1) + b2) + b3 over
+ * the standardised features x_hat = (x - mean) / std, softmax over the C
+ * components.  Inference runs on BF16 MFMA (weights and activations rounded to
+ * BF16, FP32 accumulation); training keeps an FP32 master copy.
+ *   H1, H2           hidden sizes, multiples of 128 in [128, 4096]
+ *   k                proposals per frame, 1..min(32, C)
+ *   min_mass         fallback threshold on the proposals' softmax mass
+ *   max_train_batch  largest training batch (0: inference only) */
+typedef struct {
+  int32_t H1, H2, k;
+  float min_mass;
+  int32_t max_train_batch;
+} ivx_selector_dims;
+
+/* Global mean and standard deviation of F frames X [F][D] (FP64 sums) into
+ * mean [D], std [D] (device FP32). */
+ivx_status ivx_feature_stats(ivx_ctx* ctx, const float* X, int64_t F, float* mean, float* std,
+                             void* stream);
+
+/* Installs a selector (replacing any previous one; synchronises `stream`,
+ * allocates its workspace: about maxF * (12 k + 4 D + 16) bytes plus the
+ * weights).  params: device FP32, flat, in the order W1 [H1][D], b1 [H1],
+ * W2 [H2][H1], b2 [H2], W3 [C][H2], b3 [C] (ivx_selector_param_count values).
+ * mean, std: [D] device FP32 (std > 0, else IVX_EINVAL from ivx_sync_status).
+ * Adam moments start at zero. */
+ivx_status ivx_selector_set(ivx_ctx* ctx, const ivx_selector_dims* dims, const float* params,
+                            const float* mean, const float* std, void* stream);
+int64_t ivx_selector_param_count(const ivx_ctx* ctx);
+/* Copies the FP32 master parameters (layout of ivx_selector_set) to params. */
+ivx_status ivx_selector_get(ivx_ctx* ctx, float* params, void* stream);
+
+/* Runs the network over X [F][D] and returns, each optional (NULL):
+ *   h1 [F][H1], h2 [F][H2]  BF16 activations (raw 16-bit patterns)
+ *   z  [F][C]  FP32 logits
+ *   prop [F][k] int32: the k largest logits, largest first, ties to the lower
+ *        component index
+ *   mass [F] FP32 sum of softmax(z) over the proposals
+ *   fallback [F] int32: 1 where mass < min_mass */
+ivx_status ivx_selector_forward(ivx_ctx* ctx, const float* X, int64_t F, uint16_t* h1,
+                                uint16_t* h2, float* z, int32_t* prop, float* mass,
+                                int32_t* fallback, void* stream);
+
+/* Soft-target cross-entropy -1/B sum_b sum_c gamma_bc log softmax(z_b)_c over
+ * the B frames X[frame_idx[b]] (FP32 forward and backward on MFMA, FP32
+ * master weights), with targets gamma from the posterior lists post_idx /
+ * post_val [F][16] (the layout of ubm_posteriors, indexed by frame).
+ *   ivx_selector_grad writes the gradient (parameter layout) to grad (device
+ *   FP32, or NULL) and the loss to loss[0] (device FP64, or NULL); the
+ *   parameters are unchanged.
+ *   ivx_selector_train_step also applies one Adam step (beta 0.9 / 0.999,
+ *   eps 1e-8) with learning rate lr and refreshes the BF16 copies.
+ * A frame index outside [0, F) records IVX_EINVAL (ivx_sync_status). */
+ivx_status ivx_selector_grad(ivx_ctx* ctx, const float* X, int64_t F, const int64_t* frame_idx,
+                             int32_t B, const int32_t* post_idx, const float* post_val,
+                             float* grad, double* loss, void* stream);
+ivx_status ivx_selector_train_step(ivx_ctx* ctx, const float* X, int64_t F,
+                                   const int64_t* frame_idx, int32_t B, const int32_t* post_idx,
+                                   const float* post_val, float lr, double* loss, void* stream);
+
+/* Counters of the last learned-selection pass (synchronises `stream`):
+ * frames that fell back to all components, and the (frame, proposal) pairs
+ * that were scored. */
+ivx_status ivx_selector_counts(ivx_ctx* ctx, int64_t* fallback_frames, int64_t* kept_pairs,
+                               void* stream);
 
 /* ----------------------------------------------------------------- tracing */
 

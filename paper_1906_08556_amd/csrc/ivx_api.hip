@@ -115,7 +115,9 @@ void ivx_destroy(ivx_ctx* ctx) {
     hipDeviceSynchronize();
     prof_free(ctx);
   }
-  void* ptrs[] = {ctx->w, ctx->mu, ctx->cov, ctx->shift, ctx->Wexp, ctx->linv, ctx->cst,
+  selector_free(ctx);
+  void* ptrs[] = {ctx->w, ctx->mu, ctx->cov, ctx->shift, ctx->Wexp, ctx->W16, ctx->linv,
+                  ctx->linv32r, ctx->cst,
                   ctx->pairs, ctx->T, ctx->Sigma, ctx->p, ctx->cand, ctx->cM, ctx->cflag, ctx->post_idx,
                   ctx->post_val, ctx->frame_ll, ctx->hist, ctx->coff, ctx->ent, ctx->partial,
                   ctx->Y32, ctx->V32, ctx->Utp, ctx->Psig, ctx->sig_logdet, ctx->Lbuf, ctx->Wbuf, ctx->Psi64,
@@ -149,11 +151,12 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   c->maxU = dims->max_batch_utts;
   c->maxF = dims->max_batch_frames;
   c->K = (c->D + 1) * (c->D + 2) / 2;
-  c->Kpad = (c->K + 7) / 8 * 8;
+  c->Kpad = (c->K + 15) / 16 * 16;
   c->Cpad = (c->C + 255) / 256 * 256;  // multiple of the frame GEMM component tile
   c->Dp = c->D * (c->D + 1) / 2;
   c->TP = tp_size(c->R);
   c->margin = candidate_margin(c->C);
+  c->margin_bf16 = candidate_margin_bf16(c->C);
   c->nhist = (int)((c->maxF + 8191) / 8192);
 
   const size_t C = c->C, D = c->D, R = c->R, F = c->maxF;
@@ -164,7 +167,9 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   A(dalloc(&c->cov, C * D * D));
   A(dalloc(&c->shift, D));
   A(dalloc(&c->Wexp, (size_t)c->Cpad * c->Kpad));
+  A(dalloc(&c->W16, (size_t)c->Cpad * c->Kpad * 2));
   A(dalloc(&c->linv, C * c->Dp));
+  A(dalloc(&c->linv32r, C * c->Dp));
   A(dalloc(&c->cst, C));
   A(dalloc(&c->pairs, (size_t)c->Kpad));
   A(dalloc(&c->T, C * D * R));
@@ -222,6 +227,11 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
     set_error("ivx_create: upload failed");
     return IVX_EDEVICE;
   }
+  if (!frame_set_attributes(c) || !select_set_attributes()) {
+    ivx_destroy(c);
+    set_error("ivx_create: hipFuncSetAttribute failed for a large-LDS kernel");
+    return IVX_EDEVICE;
+  }
   *out = c;
   return IVX_OK;
 }
@@ -238,7 +248,10 @@ ivx_status ivx_sync_status(ivx_ctx* ctx, void* stream) {
                                        "second-order statistics", "TV precompute (Sigma_c)",
                                        "E-step GEMMs", "E-step Cholesky of L(u)",
                                        "accumulators", "M-step (A_c)", "minimum divergence (G)",
-                                       "UBM preparation (covariance)"};
+                                       "UBM preparation (covariance)",
+                                       "learned selection (network)",
+                                       "learned selection (scoring)",
+                                       "learned selection (training batch)"};
   const char* src = (e[2] >= 0 && e[2] < PK_COUNT) ? kSrc[e[2]] : "?";
   const int idx = e[1] == 0x7fffffff ? -1 : e[1];
   switch (e[0]) {
@@ -334,8 +347,10 @@ static ivx_status check_frame_args(ivx_ctx* ctx, const char* fn, const float* X,
   IVX_CHECK(F >= 0 && F <= ctx->maxF, "%s: F=%lld outside [0, max_batch_frames=%lld]", fn,
             (long long)F, (long long)ctx->maxF);
   IVX_CHECK(F == 0 || X, "%s: null X", fn);
-  IVX_CHECK(prec == IVX_FP32, "%s: precision %d not available in this build", fn, (int)prec);
-  IVX_CHECK(sel == IVX_SEL_ALL, "%s: selection %d not available in this build", fn, (int)sel);
+  IVX_CHECK(prec == IVX_FP32 || prec == IVX_BF16, "%s: unknown precision %d", fn, (int)prec);
+  IVX_CHECK(sel == IVX_SEL_ALL || sel == IVX_SEL_LEARNED, "%s: unknown selection %d", fn,
+            (int)sel);
+  IVX_CHECK(sel == IVX_SEL_ALL || ctx->sel, "%s: IVX_SEL_LEARNED needs ivx_selector_set", fn);
   return IVX_OK;
 }
 
@@ -349,11 +364,7 @@ ivx_status ubm_posteriors(ivx_ctx* ctx, const float* X, int64_t F, ivx_precision
   hipStream_t s = as_stream(stream);
   int* pi = post_idx ? post_idx : ctx->post_idx;
   float* pv = post_val ? post_val : ctx->post_val;
-  launch_frame_select(ctx, X, F, s);
-  {
-    ProfScope ps(ctx, PK_RESCORE, s);
-    launch_rescore(ctx, X, F, pi, pv, frame_ll, s);
-  }
+  launch_posteriors(ctx, X, F, prec, sel, pi, pv, frame_ll, s);
   if (gamma) launch_dense_gamma(ctx, F, pi, pv, gamma, s);
   return after_launch("ubm_posteriors");
 }
@@ -367,11 +378,7 @@ ivx_status bw_stats(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_
   IVX_CHECK(utt_off && n && f, "bw_stats: null utt_off / n / f");
   if (set_device(ctx) != IVX_OK) return IVX_EDEVICE;
   hipStream_t s = as_stream(stream);
-  launch_frame_select(ctx, X, F, s);
-  {
-    ProfScope ps(ctx, PK_RESCORE, s);
-    launch_rescore(ctx, X, F, ctx->post_idx, ctx->post_val, ctx->frame_ll, s);
-  }
+  launch_posteriors(ctx, X, F, prec, sel, ctx->post_idx, ctx->post_val, ctx->frame_ll, s);
   {
     ProfScope ps(ctx, PK_STATS_NF, s);
     launch_stats_nf(ctx, X, utt_off, U, F, n, f, s);

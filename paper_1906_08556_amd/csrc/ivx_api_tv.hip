@@ -61,8 +61,8 @@ ivx_status ensure_tv(ivx_ctx* ctx, hipStream_t s) {
   return IVX_OK;
 }
 
-ivx_status estep_impl(ivx_ctx* ctx, const float* n, const float* f, int64_t U, float* phi,
-                      float* Phi, double* ll_acc, int32_t* info, hipStream_t s) {
+ivx_status estep_impl(ivx_ctx* ctx, const float* n, const float* f, int64_t U, int prec,
+                      float* phi, float* Phi, double* ll_acc, int32_t* info, hipStream_t s) {
   ivx_status st = ensure_tv(ctx, s);
   if (st != IVX_OK) return st;
   const int C = ctx->C, D = ctx->D, R = ctx->R;
@@ -78,7 +78,11 @@ ivx_status estep_impl(ivx_ctx* ctx, const float* n, const float* f, int64_t U, f
   gl.M = (int)U;
   gl.N = (int)ctx->TP;
   gl.K = C;
-  if ((st = gemm(gl, false, false, GEMM_STORE, 1, s, "tv_estep")) != IVX_OK) return st;
+  if (prec == IVX_BF16) {
+    gemm_bf16x3_nn(gl, s);
+  } else if ((st = gemm(gl, false, false, GEMM_STORE, 1, s, "tv_estep")) != IVX_OK) {
+    return st;
+  }
   launch_add_identity(ctx, ctx->Lbuf, U, s);
   // b(u) = p + sum_c V_c^T f_c(u), split over K = C*D
   const int64_t K = (int64_t)C * D;
@@ -125,13 +129,13 @@ ivx_status tv_estep(ivx_ctx* ctx, const float* n, const float* f, int64_t U, ivx
   IVX_CHECK(U >= 0 && U <= ctx->maxU, "tv_estep: U=%lld outside [0, max_batch_utts=%d]",
             (long long)U, ctx->maxU);
   IVX_CHECK(U == 0 || (n && f && phi), "tv_estep: null n / f / phi");
-  IVX_CHECK(prec == IVX_FP32, "tv_estep: precision %d not available in this build", (int)prec);
+  IVX_CHECK(prec == IVX_FP32 || prec == IVX_BF16, "tv_estep: unknown precision %d", (int)prec);
   if (U == 0) return IVX_OK;
   if (hipSetDevice(ctx->device) != hipSuccess) {
     set_error("tv_estep: hipSetDevice failed");
     return IVX_EDEVICE;
   }
-  return estep_impl(ctx, n, f, U, phi, Phi, ll_acc, info, as_stream(stream));
+  return estep_impl(ctx, n, f, U, prec, phi, Phi, ll_acc, info, as_stream(stream));
 }
 
 ivx_status tv_mstep_accumulate(ivx_ctx* ctx, const float* n, const float* f, const float* phi,
@@ -168,24 +172,22 @@ ivx_status extract_ivectors(ivx_ctx* ctx, const float* X, const int64_t* utt_off
   IVX_CHECK(F >= 0 && F <= ctx->maxF, "extract_ivectors: F=%lld outside [0, %lld]", (long long)F,
             (long long)ctx->maxF);
   IVX_CHECK(utt_off && phi && (F == 0 || X), "extract_ivectors: null argument");
-  IVX_CHECK(prec == IVX_FP32 && sel == IVX_SEL_ALL, "extract_ivectors: mode not available");
+  IVX_CHECK(prec == IVX_FP32 || prec == IVX_BF16, "extract_ivectors: unknown precision");
+  IVX_CHECK(sel == IVX_SEL_ALL || (sel == IVX_SEL_LEARNED && ctx->sel),
+            "extract_ivectors: unknown selection, or IVX_SEL_LEARNED without ivx_selector_set");
   if (hipSetDevice(ctx->device) != hipSuccess) {
     set_error("extract_ivectors: hipSetDevice failed");
     return IVX_EDEVICE;
   }
   hipStream_t s = as_stream(stream);
-  launch_frame_select(ctx, X, F, s);
-  {
-    ProfScope ps(ctx, PK_RESCORE, s);
-    launch_rescore(ctx, X, F, ctx->post_idx, ctx->post_val, ctx->frame_ll, s);
-  }
+  launch_posteriors(ctx, X, F, prec, sel, ctx->post_idx, ctx->post_val, ctx->frame_ll, s);
   {
     ProfScope ps(ctx, PK_STATS_NF, s);
     launch_stats_nf(ctx, X, utt_off, U, F, ctx->n_ws, ctx->f_ws, s);
   }
   ivx_status st = after_launch("extract_ivectors");
   if (st != IVX_OK) return st;
-  return estep_impl(ctx, ctx->n_ws, ctx->f_ws, U, phi, nullptr, nullptr, nullptr, s);
+  return estep_impl(ctx, ctx->n_ws, ctx->f_ws, U, prec, phi, nullptr, nullptr, nullptr, s);
 }
 
 ivx_status tv_mstep_solve(ivx_ctx* ctx, const ivx_accum* acc, const double* S, int update_sigma,

@@ -17,10 +17,19 @@ constexpr int KP = 16;
 // rounding of the kept posteriors; the extra 2 nats absorb the error of the
 // FP32 expanded-form filter (<= 0.4 nats measured on the workload).
 inline float candidate_margin(int C) { return logf((float)C) + 18.64f; }
+// The BF16 split-form filter is off by up to ~3 nats on the workload
+// (measured against FP64); its margin carries 16 nats of allowance instead of 2.
+inline float candidate_margin_bf16(int C) { return logf((float)C) + 16.64f + 16.0f; }
 // Largest posterior mass a frame may lose when more than KP components lie
 // within the margin (the top KP by exact score are kept); beyond it the frame
 // raises IVX_ECAPACITY.
 constexpr double kMaxDroppedMass = 1e-6;
+// Largest number of proposals per frame of the learned selection.
+constexpr int kMaxProposals = 32;
+// Margin of the learned selection's FP32 shifted-form filter: the proposals
+// more than ln k + 16.64 + 2 nats below the frame's best carry less than
+// 2^-24 e^-2 of its mass; the filter itself is off by far less than 2 nats.
+inline float selection_margin(int k) { return logf((float)k) + 18.64f; }
 // Tile size of the tile-packed symmetric layout.
 constexpr int TB = 16;
 
@@ -37,6 +46,9 @@ enum ProfKernel {
   PK_MSTEP,             // FP64 M-step solve and objective
   PK_MINDIV,            // minimum divergence
   PK_UBM,               // UBM preparation / realignment
+  PK_SEL_MLP,           // learned selection: network forward and top-k
+  PK_SEL_SCORE,         // learned selection: pair sort, filter and exact scores
+  PK_SEL_TRAIN,         // learned selection: training gradients
   PK_COUNT
 };
 
@@ -44,6 +56,52 @@ inline int64_t tp_size(int R) {
   int64_t nb = (R + TB - 1) / TB;
   return nb * (nb + 1) / 2 * TB * TB;
 }
+
+// State of the learned Gaussian selection: parameters (flat FP32 master
+// vector W1 [H1][D], b1 [H1], W2 [H2][H1], b2 [H2], W3 [C][H2], b3 [C]), Adam
+// moments, BF16 inference copies and workspace.  Owned by the context.
+struct Selector {
+  int H1 = 0, H2 = 0, k = 0, Bmax = 0;
+  float min_mass = 0.99f;
+  float margin = 0.0f;
+  int64_t P = 0, oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;
+  int64_t chunk = 0;  // frames per network pass
+  int step = 0;       // Adam steps taken
+  float* param = nullptr;
+  float* grad = nullptr;
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  float* mean = nullptr;  // [D]
+  float* stdv = nullptr;  // [D]
+  float* istd = nullptr;  // [D]
+  __bf16* W1b = nullptr;  // [H1][64], features padded with zeros
+  __bf16* W2b = nullptr;  // [H2][H1]
+  __bf16* W3b = nullptr;  // [Cpad][H2], padding components zero
+  float* b3p = nullptr;   // [Cpad]
+  __bf16* h1b = nullptr;  // [chunk][H1]
+  __bf16* h2b = nullptr;  // [chunk][H2]
+  int* prop = nullptr;    // [maxF][k] proposals, largest logit first
+  float* mass = nullptr;  // [maxF] the network's softmax mass on its proposals
+  int* fb = nullptr;      // [maxF] 1 = all-component fallback
+  int* fb_list = nullptr; // [maxF]
+  int* counters = nullptr;  // [4]: fallback frames, kept (frame, proposal) pairs
+  float* score = nullptr;   // [maxF][k] FP32 filter scores
+  int* hist = nullptr;      // [maxF / 8192 + 1][C]
+  int* coff = nullptr;      // [C + 1]
+  int2* ent = nullptr;      // [maxF * k] (frame * k + slot, component), by component
+  float* xfb = nullptr;     // [maxF][D] fallback frames, gathered
+  // training, batch <= Bmax
+  float* xs = nullptr;      // [Bmax][D]
+  float* a1 = nullptr;      // [Bmax][H1]
+  float* h1 = nullptr;
+  float* a2 = nullptr;      // [Bmax][H2]
+  float* h2 = nullptr;
+  float* z = nullptr;       // [Bmax][C]
+  float* dz = nullptr;
+  float* dh1 = nullptr;     // [Bmax][H1]
+  float* dh2 = nullptr;     // [Bmax][H2]
+  double* loss_part = nullptr;  // [Bmax]
+};
 
 // Records a message for ivx_last_error() (printf-style).
 void set_error(const char* fmt, ...);
@@ -66,11 +124,12 @@ struct ivx_ctx {
   int maxU = 0;
   int64_t maxF = 0;
   int K = 0;       // expanded features (D+1)(D+2)/2
-  int Kpad = 0;    // K rounded up to a multiple of 8
+  int Kpad = 0;    // K rounded up to a multiple of 16
   int Cpad = 0;    // C rounded up to a multiple of 256 (frame GEMM tile)
   int Dp = 0;      // D(D+1)/2
   int64_t TP = 0;  // tile-packed size for R
-  float margin = 0.0f;  // candidate margin (nats)
+  float margin = 0.0f;       // candidate margin (nats), FP32 filter
+  float margin_bf16 = 0.0f;  // candidate margin (nats), BF16 split-form filter
   bool ubm_set = false;
   bool tv_set = false;
 
@@ -81,7 +140,9 @@ struct ivx_ctx {
   // UBM-derived
   float* shift = nullptr;     // [D] global mean shift applied before expansion
   float* Wexp = nullptr;      // [Kpad/8][Cpad][8] expanded quadratic-form coefficients
+  __bf16* W16 = nullptr;      // [Kpad/16][Cpad][32] the same as BF16 (16 hi, 16 lo per chunk)
   double* linv = nullptr;     // [C][Dp] L_c^{-1}, lower triangle column by column
+  float* linv32r = nullptr;   // [C][Dp] L_c^{-1} in FP32, lower triangle row by row
   double* cst = nullptr;      // [C] log w_c - D/2 log 2pi - sum_i log L_c[i,i]
   uint16_t* pairs = nullptr;  // [Kpad] expanded-feature index pairs (a | b << 8)
 
@@ -132,6 +193,9 @@ struct ivx_ctx {
 
   int* dev_err = nullptr;     // [4]: see raise_error
 
+  // learned Gaussian selection (ivx_selector_set), null until set
+  ivx::Selector* sel = nullptr;
+
   // event profiler (off unless ivx_profile_enable)
   bool prof_on = false;
   int prof_cap = 0, prof_used = 0;
@@ -160,9 +224,14 @@ void launch_init_tv(ivx_ctx* ctx, const double* T_rand, double p0, hipStream_t s
 void launch_update_means(ivx_ctx* ctx, hipStream_t s);
 
 // ---- k_frame.hip
-void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, hipStream_t s);
-void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int* post_idx, float* post_val,
-                    double* frame_ll, hipStream_t s);
+bool frame_set_attributes(const ivx_ctx* ctx);
+// Fdev (optional): device frame count, at most F, read by the kernels (the
+// grid is sized for F).  fmap (optional): output row of compact frame i.
+void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, int prec, hipStream_t s,
+                         const int* Fdev = nullptr);
+void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int prec, int* post_idx,
+                    float* post_val, double* frame_ll, hipStream_t s, const int* Fdev = nullptr,
+                    const int* fmap = nullptr);
 void launch_dense_gamma(ivx_ctx* ctx, int64_t F, const int* post_idx, const float* post_val,
                         float* gamma, hipStream_t s);
 
@@ -171,5 +240,26 @@ void launch_stats_nf(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64
                      float* n, float* f, hipStream_t s);
 void launch_stats_S(ivx_ctx* ctx, const float* X, int64_t F, double* S_acc, hipStream_t s);
 void launch_sum_f64(ivx_ctx* ctx, const double* x, int64_t n, double* acc, hipStream_t s);
+void launch_hist_scan(int nb, int C, int* hist, int* coff, hipStream_t s);
+
+// ---- ivx_api_sel.hip
+void selector_free(ivx_ctx* ctx);
+void launch_posteriors(ivx_ctx* ctx, const float* X, int64_t F, int prec, int sel, int* post_idx,
+                       float* post_val, double* frame_ll, hipStream_t s);
+
+// ---- k_select.hip
+bool select_set_attributes();
+void launch_selector_pack(ivx_ctx* ctx, hipStream_t s);
+void launch_feature_stats(ivx_ctx* ctx, const float* X, int64_t F, float* mean, float* stdv,
+                          hipStream_t s);
+void launch_selector_inv_std(ivx_ctx* ctx, hipStream_t s);
+void launch_selector_mlp(ivx_ctx* ctx, const float* X, int64_t F, uint16_t* h1_out,
+                         uint16_t* h2_out, float* z_out, hipStream_t s);
+void launch_select_learned(ivx_ctx* ctx, const float* X, int64_t F, int prec, int* post_idx,
+                           float* post_val, double* frame_ll, hipStream_t s);
+bool launch_selector_grad(ivx_ctx* ctx, const float* X, int64_t F, const int64_t* fidx, int B,
+                          const int* post_idx, const float* post_val, double* loss,
+                          hipStream_t s);
+void launch_selector_adam(ivx_ctx* ctx, float lr, hipStream_t s);
 
 }  // namespace ivx

@@ -16,6 +16,7 @@
 #include <cmath>
 
 #include "ivx_internal.h"
+#include "k_exact.h"
 
 namespace ivx {
 namespace {
@@ -55,8 +56,11 @@ __global__ void __launch_bounds__(256, 2)
 k_frame_tile(const float* __restrict__ X, int64_t F, int D, const float* __restrict__ shift,
              const float* __restrict__ W, int C, int Cpad, int Kpad,
              const uint16_t* __restrict__ pairs, float margin, int c0, int first,
-             int2* __restrict__ cand, float* __restrict__ cM, int* __restrict__ cflag) {
+             int2* __restrict__ cand, float* __restrict__ cM, int* __restrict__ cflag,
+             const int* __restrict__ Fdev) {
   extern __shared__ float smem[];
+  if (Fdev && (int64_t)Fdev[0] < F) F = Fdev[0];
+  if ((int64_t)blockIdx.x * FT >= F) return;  // whole workgroup, before any barrier
   const int DS = D + 1;
   float* Ws = smem;                                              // [2][CT][WLD]
   float* xs = smem + 2 * CT * WLD;                               // [FT][DS]
@@ -178,31 +182,159 @@ k_frame_tile(const float* __restrict__ X, int64_t F, int D, const float* __restr
   }
 }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
+// ---------------------------------------------------------------- BF16 form
+// Same tiling as k_frame_tile, with the dot products on
+// v_mfma_f32_32x32x16_bf16 and FP32 accumulation.  Both operands are split
+// into BF16 high and low parts (v = hi + lo, lo = bf16(v - hi)) and three
+// products hi*hi + hi*lo + lo*hi are accumulated: plain BF16 would be off by
+// hundreds of nats on this range, the split form by a few nats.  The result
+// only selects candidates; every kept component is rescored exactly in FP64.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// Exact FP64 log w_c N(x; mu_c, Sigma_c) for the wave's frame; every lane
-// returns the same value.  xd: lane's feature (0 for lanes >= D); dsh: 64
-// doubles of wave-private LDS.
-__device__ inline double exact_ll(int c, double xd, int lane, int D, int Dp,
-                                  const double* __restrict__ mu, const double* __restrict__ linv,
-                                  const double* __restrict__ cst, double* dsh) {
-  const double d = (lane < D) ? (xd - mu[(size_t)c * D + lane]) : 0.0;
-  dsh[lane] = d;
-  __builtin_amdgcn_wave_barrier();
-  const double* Lc = linv + (size_t)c * Dp;
-  double y = 0.0;
-  int col = 0;
-  for (int j = 0; j < D; ++j) {
-    const double dj = dsh[j];
-    if (lane >= j && lane < D) y += Lc[col + (lane - j)] * dj;
-    col += D - j;
+constexpr int WB16 = 40;  // LDS row stride (bf16) of a staged comp: 16 hi, 16 lo, 8 pad
+
+// W16 layout (k_ubm_prepare): [Kpad/16][Cpad][32] bf16, per component 16 hi
+// then 16 lo coefficients of the chunk.
+__global__ void __launch_bounds__(256, 2)
+k_frame_tile_bf16(const float* __restrict__ X, int64_t F, int D, const float* __restrict__ shift,
+                  const __bf16* __restrict__ W16, int C, int Cpad, int Kpad,
+                  const uint16_t* __restrict__ pairs, float margin, int c0, int first,
+                  int2* __restrict__ cand, float* __restrict__ cM, int* __restrict__ cflag,
+                  const int* __restrict__ Fdev) {
+  extern __shared__ float smem[];
+  if (Fdev && (int64_t)Fdev[0] < F) F = Fdev[0];
+  if ((int64_t)blockIdx.x * FT >= F) return;  // whole workgroup, before any barrier
+  const int DS = D + 1;
+  __bf16* Ws = reinterpret_cast<__bf16*>(smem);                  // [2][CT][WB16]
+  float* xs = smem + (2 * CT * WB16) / 2;                         // [FT][DS]
+  uint32_t* prs = reinterpret_cast<uint32_t*>(xs + FT * DS);      // [Kpad/2]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t f0 = (int64_t)blockIdx.x * FT;
+  const int nq = Kpad / 16;
+
+  for (int i = tid; i < Kpad / 2; i += 256) prs[i] = reinterpret_cast<const uint32_t*>(pairs)[i];
+  for (int i = tid; i < FT * DS; i += 256) {
+    const int fr = i / DS, a = i - fr * DS;
+    const int64_t g = f0 + fr;
+    float v = (a == 0) ? 1.0f : 0.0f;
+    if (a > 0 && g < F) v = X[g * D + (a - 1)] - shift[a - 1];
+    xs[i] = v;
   }
-  __builtin_amdgcn_wave_barrier();
-  return cst[c] - 0.5 * wave_sum(y * y);
+  // chunk loader: thread t stages the 32 bf16 (64 B) of component c0 + t
+  uint4 r0, r1, r2, r3;
+  auto gload = [&](int q) {
+    const uint4* p = reinterpret_cast<const uint4*>(W16 + ((size_t)q * Cpad + c0 + tid) * 32);
+    r0 = p[0];
+    r1 = p[1];
+    r2 = p[2];
+    r3 = p[3];
+  };
+  auto sstore = [&](int buf) {
+    uint4* d = reinterpret_cast<uint4*>(Ws + (buf * CT + tid) * WB16);
+    d[0] = r0;
+    d[1] = r1;
+    d[2] = r2;
+    d[3] = r3;
+  };
+  gload(0);
+  sstore(0);
+
+  const int h = lane >> 5, l32 = lane & 31;
+  const int64_t g = f0 + wave * FR + l32;
+  const bool valid = g < F;
+  int2* lst = cand + (valid ? g : 0) * KP + h * CAPL;
+  float M = -INFINITY;
+  int cnt = 0;
+  bool ov = false;
+  if (valid) {
+    if (first) {
+      for (int s = 0; s < CAPL; ++s) lst[s] = make_int2(-1, 0);
+    } else {
+      M = cM[g];
+      ov = cflag[g] != 0;
+      for (int s = 0; s < CAPL; ++s)
+        if (lst[s].x >= 0) cnt = s + 1;
+    }
+  }
+  __syncthreads();
+
+  floatx16 acc[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = floatx16{0};
+  const float* xw = xs + (wave * FR + l32) * DS;
+  for (int q = 0; q < nq; ++q) {
+    const int cur = q & 1;
+    if (q + 1 < nq) gload(q + 1);
+    // B operand: products for k = 16 q + 8 h + e, e = 0..7, split hi / lo
+    const uint4 pw = *reinterpret_cast<const uint4*>(prs + 8 * q + 4 * h);
+    bf16x8 bh, bl;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t w32 = (e < 2) ? pw.x : (e < 4) ? pw.y : (e < 6) ? pw.z : pw.w;
+      const uint32_t pr = w32 >> ((e & 1) * 16);
+      const float v = xw[pr & 0xff] * xw[(pr >> 8) & 0xff];
+      const __bf16 hi = (__bf16)v;
+      bh[e] = hi;
+      bl[e] = (__bf16)(v - (float)hi);
+    }
+    const __bf16* wb = Ws + (cur * CT + l32) * WB16 + 8 * h;
+    bf16x8 wh[NCB], wl[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      wh[cb] = *reinterpret_cast<const bf16x8*>(wb + cb * 32 * WB16);
+      wl[cb] = *reinterpret_cast<const bf16x8*>(wb + cb * 32 * WB16 + 16);
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[cb], bh, acc[cb], 0, 0, 0);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[cb], bl, acc[cb], 0, 0, 0);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl[cb], bh, acc[cb], 0, 0, 0);
+    if (q + 1 < nq) sstore(cur ^ 1);
+    __syncthreads();
+  }
+  float vmax = -INFINITY;
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) vmax = fmaxf(vmax, acc[cb][r]);
+  const float lmax = vmax;
+  vmax = fmaxf(vmax, __shfl_xor(vmax, 32));
+  M = fmaxf(M, vmax);
+  const float thr = M - margin;
+  if (valid && lmax >= thr) {
+    int nh = 0;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) nh += (acc[cb][r] >= thr) ? 1 : 0;
+    if (cnt + nh > CAPL) cnt = compact_cands(lst, thr);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float v = acc[cb][r];
+        const int comp = c0 + cb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (v >= thr && comp < C) {
+          if (cnt < CAPL) {
+            lst[cnt] = make_int2(comp, __float_as_int(v));
+            ++cnt;
+          } else {
+            ov = true;
+          }
+        }
+      }
+  }
+  const int ovi = ov ? 1 : 0;
+  const int ovp = __shfl_xor(ovi, 32);
+  if (valid && h == 0) {
+    cM[g] = M;
+    cflag[g] = ovi | ovp;
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -211,13 +343,15 @@ k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __
           const int2* __restrict__ cand, const float* __restrict__ cM, float margin,
           const int* __restrict__ cflag,
           int* __restrict__ post_idx, float* __restrict__ post_val, double* __restrict__ frame_ll,
-          int* __restrict__ err) {
+          int* __restrict__ err, const int* __restrict__ Fdev, const int* __restrict__ fmap) {
   __shared__ double dsh[4][64];
   __shared__ double lsh[4][KP];
   __shared__ int ish[4][KP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t g = (int64_t)blockIdx.x * 4 + wave;
+  if (Fdev && (int64_t)Fdev[0] < F) F = Fdev[0];
   if (g >= F) return;  // wave-uniform; no workgroup barriers below
+  const int64_t go = fmap ? (int64_t)fmap[g] : g;  // output row
   const int Dp = D * (D + 1) / 2;
   const double xd = (lane < D) ? (double)X[g * D + lane] : 0.0;
   int m = 0;
@@ -275,9 +409,9 @@ k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __
   for (int s = 0; s < m; ++s) se += exp(lsh[wave][s] - mx);
   const double kept = mx + log(se);
   const double lse = isnan(full_lse) ? kept : full_lse;
-  if (!isfinite(lse) && lane == 0) raise_error(err, IVX_ENUMERIC, PK_RESCORE, (int)g);
+  if (!isfinite(lse) && lane == 0) raise_error(err, IVX_ENUMERIC, PK_RESCORE, (int)go);
   if (!isnan(full_lse) && lane == 0 && 1.0 - exp(kept - full_lse) > kMaxDroppedMass)
-    raise_error(err, IVX_ECAPACITY, PK_RESCORE, (int)g);
+    raise_error(err, IVX_ECAPACITY, PK_RESCORE, (int)go);
   if (lane < KP) {
     int id = -1;
     float v = 0.0f;
@@ -285,10 +419,10 @@ k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __
       id = ish[wave][lane];
       v = (float)exp(lsh[wave][lane] - lse);
     }
-    if (post_idx) post_idx[g * KP + lane] = id;
-    if (post_val) post_val[g * KP + lane] = v;
+    if (post_idx) post_idx[go * KP + lane] = id;
+    if (post_val) post_val[go * KP + lane] = v;
   }
-  if (lane == 0 && frame_ll) frame_ll[g] = lse;
+  if (lane == 0 && frame_ll) frame_ll[go] = lse;
 }
 
 __global__ void k_dense_gamma(int64_t F, int C, const int* __restrict__ post_idx,
@@ -309,26 +443,51 @@ __global__ void k_scatter_gamma(int64_t F, int C, const int* __restrict__ post_i
 
 }  // namespace
 
-void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, hipStream_t s) {
+// The BF16 tile kernel uses more than 64 KB of LDS (gfx950 has 160 KB per CU);
+// called once per context at creation, outside any stream capture.
+bool frame_set_attributes(const ivx_ctx* ctx) {
+  const size_t lds16 = sizeof(__bf16) * 2 * CT * WB16 + sizeof(float) * (size_t)FT * (ctx->D + 1) +
+                       sizeof(uint16_t) * ctx->Kpad;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_frame_tile_bf16),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds16) == hipSuccess;
+}
+
+void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, int prec, hipStream_t s,
+                         const int* Fdev) {
   if (F <= 0) return;
   const int DS = ctx->D + 1;
+  if (prec == IVX_BF16) {
+    const size_t lds16 = sizeof(__bf16) * 2 * CT * WB16 + sizeof(float) * (size_t)FT * DS +
+                         sizeof(uint16_t) * ctx->Kpad;
+    const unsigned nb16 = (unsigned)((F + FT - 1) / FT);
+    for (int c0 = 0; c0 < ctx->Cpad; c0 += CT) {
+      ProfScope ps(ctx, PK_FRAME_SELECT, s);
+      k_frame_tile_bf16<<<nb16, 256, lds16, s>>>(X, F, ctx->D, ctx->shift, ctx->W16, ctx->C,
+                                                 ctx->Cpad, ctx->Kpad, ctx->pairs,
+                                                 ctx->margin_bf16, c0, c0 == 0 ? 1 : 0, ctx->cand,
+                                                 ctx->cM, ctx->cflag, Fdev);
+    }
+    return;
+  }
   const size_t lds = sizeof(float) * (2 * CT * WLD + (size_t)FT * DS) + sizeof(uint16_t) * ctx->Kpad;
   const unsigned nblk = (unsigned)((F + FT - 1) / FT);
   for (int c0 = 0; c0 < ctx->Cpad; c0 += CT) {
     ProfScope ps(ctx, PK_FRAME_SELECT, s);
     k_frame_tile<<<nblk, 256, lds, s>>>(X, F, ctx->D, ctx->shift, ctx->Wexp, ctx->C, ctx->Cpad,
                                         ctx->Kpad, ctx->pairs, ctx->margin, c0, c0 == 0 ? 1 : 0,
-                                        ctx->cand, ctx->cM, ctx->cflag);
+                                        ctx->cand, ctx->cM, ctx->cflag, Fdev);
   }
 }
 
-void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int* post_idx, float* post_val,
-                    double* frame_ll, hipStream_t s) {
+void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int prec, int* post_idx,
+                    float* post_val, double* frame_ll, hipStream_t s, const int* Fdev,
+                    const int* fmap) {
   if (F <= 0) return;
   const unsigned nblk = (unsigned)((F + 3) / 4);
   k_rescore<<<nblk, 256, 0, s>>>(X, F, ctx->D, ctx->C, ctx->mu, ctx->linv, ctx->cst, ctx->cand,
-                                 ctx->cM, ctx->margin, ctx->cflag, post_idx, post_val, frame_ll,
-                                 ctx->dev_err);
+                                 ctx->cM, prec == IVX_BF16 ? ctx->margin_bf16 : ctx->margin,
+                                 ctx->cflag, post_idx, post_val, frame_ll, ctx->dev_err, Fdev,
+                                 fmap);
 }
 
 void launch_dense_gamma(ivx_ctx* ctx, int64_t F, const int* post_idx, const float* post_val,

@@ -26,6 +26,10 @@ struct GemmArgs {
 // nothing) for a combination that is not instantiated.
 bool gemm_f32(const GemmArgs& g, bool ta, bool tb, int epi, int batches, hipStream_t s);
 
+// C = A B (row-major FP32 operands, FP32 result) on BF16 MFMA with each
+// operand split into BF16 high and low parts (hi*hi + hi*lo + lo*hi).
+void gemm_bf16x3_nn(const GemmArgs& g, hipStream_t s);
+
 // C[m][n] += sum_k A[k*lda + m] * B[k*ldb + n] with FP64 products and sums
 // (k_gemm64.hip).  A is FP32; B is FP64 (b_is_double) or FP32.
 void gemm64_tn(const float* A, int64_t lda, const void* B, bool b_is_double, int64_t ldb,

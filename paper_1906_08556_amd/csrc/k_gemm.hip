@@ -18,6 +18,7 @@ namespace ivx {
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef floatx16 floatx16_t;
 
 constexpr int BM = 128, BN = 128, BK = 16;
 constexpr int LDSW = BM + 32;  // LDS row stride (floats) of the [k][m] / [k][n] tiles
@@ -179,8 +180,108 @@ bool gemm_f32(const GemmArgs& g0, bool ta, bool tb, int epi, int batches, hipStr
   IVX_GEMM_CASE(true, false, GEMM_ADD_F64)
   IVX_GEMM_CASE(true, false, GEMM_STORE_TP)
   IVX_GEMM_CASE(false, false, GEMM_ADD_F64)
+  IVX_GEMM_CASE(false, true, GEMM_STORE)
+  IVX_GEMM_CASE(true, false, GEMM_STORE)
 #undef IVX_GEMM_CASE
   return false;
+}
+
+}  // namespace ivx
+
+// ------------------------------------------------------------ BF16 split form
+// C = A B (both row-major, FP32 in memory) on v_mfma_f32_32x32x16_bf16 with
+// FP32 accumulation: each operand is split into BF16 high and low parts while
+// it is staged in LDS, and hi*hi + hi*lo + lo*hi are accumulated.  Used for
+// the precision assembly L(u) = I + N U in the BF16 form.
+namespace ivx {
+namespace {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+constexpr int BRS = 40;  // LDS row stride (bf16) of a [row][16 hi | 16 lo] tile row
+
+__global__ void __launch_bounds__(256, 2) k_gemm_bf16x3_nn(GemmArgs g) {
+  __shared__ __bf16 As[128 * BRS];  // [m][k hi 0..15 | k lo 0..15]
+  __shared__ __bf16 Bs[128 * BRS];  // [n][k hi | k lo]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int m0 = blockIdx.y * 128, n0 = blockIdx.x * 128;
+  const float* A = g.A;
+  const float* B = g.B;
+  floatx16_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx16_t{0};
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    // A tile: 128 rows x 16 k (thread: row tid/2, 8 consecutive k)
+    {
+      const int m = m0 + (tid >> 1), kk = (tid & 1) * 8;
+      __bf16* d = As + (tid >> 1) * BRS + kk;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float v = (m < g.M && k0 + kk + e < g.K) ? A[(int64_t)m * g.lda + k0 + kk + e] : 0.0f;
+        const __bf16 hi = (__bf16)v;
+        d[e] = hi;
+        d[16 + e] = (__bf16)(v - (float)hi);
+      }
+    }
+    // B tile: 16 k x 128 columns, stored transposed (thread: k = tid/16, 8 consecutive n)
+    {
+      const int k = tid >> 4, nn = (tid & 15) * 8;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int n = n0 + nn + e;
+        const float v = (n < g.N && k0 + k < g.K) ? B[(int64_t)(k0 + k) * g.ldb + n] : 0.0f;
+        const __bf16 hi = (__bf16)v;
+        Bs[(nn + e) * BRS + k] = hi;
+        Bs[(nn + e) * BRS + 16 + k] = (__bf16)(v - (float)hi);
+      }
+    }
+    __syncthreads();
+    bf16x8_t ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const __bf16* a = As + (wm * 64 + i * 32 + l32) * BRS + 8 * h;
+      ah[i] = *reinterpret_cast<const bf16x8_t*>(a);
+      al[i] = *reinterpret_cast<const bf16x8_t*>(a + 16);
+      const __bf16* b = Bs + (wn * 64 + i * 32 + l32) * BRS + 8 * h;
+      bh[i] = *reinterpret_cast<const bf16x8_t*>(b);
+      bl[i] = *reinterpret_cast<const bf16x8_t*>(b + 16);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn * 64 + j * 32 + l32;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (m < g.M && n < g.N) static_cast<float*>(g.C)[(int64_t)m * g.ldc + n] = acc[i][j][r];
+      }
+    }
+}
+
+}  // namespace
+
+void gemm_bf16x3_nn(const GemmArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return;
+  dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128));
+  k_gemm_bf16x3_nn<<<grid, 256, 0, s>>>(g);
 }
 
 }  // namespace ivx

@@ -453,9 +453,9 @@ void launch_mindiv(ivx_ctx* ctx, const ivx_accum* acc, hipStream_t s) {
   const int64_t rows = (int64_t)ctx->C * ctx->D;
   dim3 grid((unsigned)((ctx->R + 63) / 64), (unsigned)((rows + 63) / 64));
   k_apply_M<<<grid, 256, 0, s>>>(ctx->T, ctx->Mmat, rows, ctx->R, ctx->Tnew);
-  double* t = ctx->T;
-  ctx->T = ctx->Tnew;
-  ctx->Tnew = t;
+  // copy back on the stream (no host-side pointer swap, so a captured graph
+  // replays correctly)
+  hipMemcpyAsync(ctx->T, ctx->Tnew, sizeof(double) * rows * ctx->R, hipMemcpyDeviceToDevice, s);
 }
 
 }  // namespace ivx

@@ -233,6 +233,10 @@ void launch_stats_S(ivx_ctx* ctx, const float* X, int64_t F, double* S_acc, hipS
   k_S_accum<<<ctx->C, 256, sizeof(float) * SB * ctx->D, s>>>(X, ctx->D, ctx->coff, ctx->ent, S_acc);
 }
 
+void launch_hist_scan(int nb, int C, int* hist, int* coff, hipStream_t s) {
+  k_hist_scan<<<1, 1024, 0, s>>>(nb, C, hist, coff);
+}
+
 void launch_sum_f64(ivx_ctx* ctx, const double* x, int64_t n, double* acc, hipStream_t s) {
   if (n <= 0) return;
   int nb = (int)((n + 255) / 256);

@@ -38,7 +38,8 @@ __global__ void __launch_bounds__(64) k_ubm_shift(const double* __restrict__ w,
 __global__ void __launch_bounds__(64) k_ubm_prepare(
     const double* __restrict__ w, const double* __restrict__ mu, const double* __restrict__ cov,
     const float* __restrict__ shift, int C, int D, int K, int Kpad,
-    const uint16_t* __restrict__ pairs, float* __restrict__ Wexp, double* __restrict__ linv_out,
+    const uint16_t* __restrict__ pairs, float* __restrict__ Wexp, __bf16* __restrict__ W16,
+    double* __restrict__ linv_out, float* __restrict__ linv32r_out,
     double* __restrict__ cst_out, int* __restrict__ err) {
   extern __shared__ double sm[];
   double* A = sm;           // [D][D], becomes L (lower triangle)
@@ -50,8 +51,16 @@ __global__ void __launch_bounds__(64) k_ubm_prepare(
   // chunk-major layout: coefficient (c, k) at ((k / 8) * Cpad + c) * 8 + k % 8
   const int Cpad = gridDim.x;
   auto wat = [&](int k) -> float& { return Wexp[((size_t)(k >> 3) * Cpad + c) * 8 + (k & 7)]; };
+  // BF16 copy, [Kpad/16][Cpad][32]: 16 high parts then 16 low parts per chunk
+  auto put = [&](int k, float v) {
+    wat(k) = v;
+    const __bf16 hi = (__bf16)v;
+    __bf16* q = W16 + ((size_t)(k >> 4) * Cpad + c) * 32;
+    q[k & 15] = hi;
+    q[16 + (k & 15)] = (__bf16)(v - (float)hi);
+  };
   if (c >= C) {  // padding rows of the frame GEMM: never a candidate
-    for (int k = t; k < Kpad; k += 64) wat(k) = (k == 0) ? -1e30f : 0.0f;
+    for (int k = t; k < Kpad; k += 64) put(k, (k == 0) ? -1e30f : 0.0f);
     return;
   }
   for (int i = t; i < D * D; i += 64) A[i] = cov[(size_t)c * D * D + i];
@@ -80,7 +89,7 @@ __global__ void __launch_bounds__(64) k_ubm_prepare(
     if (t == 0) {
       raise_error(err, IVX_ENOTPD, PK_UBM, c);
     }
-    for (int k = t; k < Kpad; k += 64) wat(k) = (k == 0) ? -1e30f : 0.0f;
+    for (int k = t; k < Kpad; k += 64) put(k, (k == 0) ? -1e30f : 0.0f);
     if (t == 0) cst_out[c] = -INFINITY;
     return;
   }
@@ -128,6 +137,9 @@ __global__ void __launch_bounds__(64) k_ubm_prepare(
     const int col = j * D - j * (j - 1) / 2;
     if (t >= j && t < D) linv_out[(size_t)c * Dp + col + (t - j)] = Li[t * D + j];
   }
+  // FP32 copy packed by rows (row i: columns 0..i) for the learned-selection filter
+  for (int i = 0; i < D; ++i)
+    if (t <= i) linv32r_out[(size_t)c * Dp + i * (i + 1) / 2 + t] = (float)Li[i * D + t];
   // expanded coefficients
   for (int k = t; k < Kpad; k += 64) {
     double v = 0.0;
@@ -145,7 +157,7 @@ __global__ void __launch_bounds__(64) k_ubm_prepare(
         v = (i == jj) ? -0.5 * P : -P;
       }
     }
-    wat(k) = (float)v;
+    put(k, (float)v);
   }
 }
 
@@ -175,8 +187,8 @@ void launch_ubm_prepare(ivx_ctx* ctx, hipStream_t s) {
   k_ubm_shift<<<1, 64, 0, s>>>(ctx->w, ctx->mu, ctx->C, ctx->D, ctx->shift);
   const size_t lds = 2 * sizeof(double) * ctx->D * ctx->D;
   k_ubm_prepare<<<ctx->Cpad, 64, lds, s>>>(ctx->w, ctx->mu, ctx->cov, ctx->shift, ctx->C, ctx->D,
-                                           ctx->K, ctx->Kpad, ctx->pairs, ctx->Wexp, ctx->linv,
-                                           ctx->cst, ctx->dev_err);
+                                           ctx->K, ctx->Kpad, ctx->pairs, ctx->Wexp, ctx->W16,
+                                           ctx->linv, ctx->linv32r, ctx->cst, ctx->dev_err);
 }
 
 void launch_init_tv(ivx_ctx* ctx, const double* T_rand, double p0, hipStream_t s) {

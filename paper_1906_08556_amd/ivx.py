@@ -36,6 +36,11 @@ class Dims(ctypes.Structure):
                 ("max_batch_utts", ctypes.c_int32), ("max_batch_frames", ctypes.c_int64)]
 
 
+class SelectorDims(ctypes.Structure):
+    _fields_ = [("H1", ctypes.c_int32), ("H2", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("min_mass", ctypes.c_float), ("max_train_batch", ctypes.c_int32)]
+
+
 class Accum(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("Cc", ctypes.c_void_p), ("N", ctypes.c_void_p),
                 ("h", ctypes.c_void_p), ("H", ctypes.c_void_p), ("count", ctypes.c_void_p)]
@@ -63,12 +68,26 @@ PROTOTYPES = {
     "tv_mstep_solve": (_I32, [_P, ctypes.POINTER(Accum), _P, ctypes.c_int, _P, _P, _P, _P]),
     "tv_mindiv": (_I32, [_P, ctypes.POINTER(Accum), ctypes.c_int, _P]),
     "ubm_update_means": (_I32, [_P, _P]),
+    "ivx_graph_create_em": (_I32, [_P, _P, _P, _I64, _I64, _I32, _P, _P, _P, _P, _P,
+                                   ctypes.POINTER(Accum), _P, _P, _P, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(_P)]),
+    "ivx_graph_launch": (_I32, [_P, _P]),
+    "ivx_graph_destroy": (None, [_P]),
+    "ivx_feature_stats": (_I32, [_P, _P, _I64, _P, _P, _P]),
+    "ivx_selector_set": (_I32, [_P, ctypes.POINTER(SelectorDims), _P, _P, _P, _P]),
+    "ivx_selector_param_count": (_I64, [_P]),
+    "ivx_selector_get": (_I32, [_P, _P, _P]),
+    "ivx_selector_forward": (_I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
+    "ivx_selector_grad": (_I32, [_P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P]),
+    "ivx_selector_train_step": (_I32, [_P, _P, _I64, _P, _I32, _P, _P, ctypes.c_float, _P, _P]),
+    "ivx_selector_counts": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P]),
     "ivx_profile_enable": (_I32, [_P, _I32]),
     "ivx_profile_read": (_I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
 }
 
 PROFILE_GROUPS = ["frame_select", "rescore", "stats_nf", "stats_S", "tv_prep", "estep_gemm",
-                  "estep_chol", "accumulate", "mstep_solve", "mindiv", "ubm_prepare"]
+                  "estep_chol", "accumulate", "mstep_solve", "mindiv", "ubm_prepare", "sel_mlp",
+                  "sel_score", "sel_train"]
 
 _lib = None
 
@@ -229,6 +248,78 @@ class Context:
     def ubm_update_means(self, stream=None):
         self._check(self.lib.ubm_update_means(self.h, _stream(stream)))
 
+    # ------------------------------------------------------- iteration graph
+    def graph_create_em(self, X, utt_off, n, f, S, phi, Phi, acc: "Accumulators", ll_frames,
+                        ll_utts, objective, update_sigma=True, realign=True, prec=IVX_FP32):
+        """Captures one full EM iteration; returns an EMGraph (keeps the buffers alive)."""
+        U = utt_off.shape[0] - 1
+        h = ctypes.c_void_p()
+        acc_s = acc.struct()
+        f32, f64 = torch.float32, torch.float64
+        self._check(self.lib.ivx_graph_create_em(
+            self.h, self._p(X, f32, "X"), self._p(utt_off, torch.int64, "utt_off"), U, X.shape[0],
+            prec, self._p(n, f32, "n"), self._p(f, f32, "f"), self._p(S, f64, "S"),
+            self._p(phi, f32, "phi"), self._p(Phi, f32, "Phi"), ctypes.byref(acc_s),
+            self._p(ll_frames, f64, "ll_frames"), self._p(ll_utts, f64, "ll_utts"),
+            self._p(objective, f64, "objective"), int(bool(update_sigma)), int(bool(realign)),
+            ctypes.byref(h)))
+        return EMGraph(self, h, (X, utt_off, n, f, S, phi, Phi, acc, ll_frames, ll_utts, objective))
+
+    # ---------------------------------------------------- learned selection
+    def feature_stats(self, X, stream=None):
+        mean = torch.empty(self.D, dtype=torch.float32, device=self.device)
+        std = torch.empty(self.D, dtype=torch.float32, device=self.device)
+        self._check(self.lib.ivx_feature_stats(self.h, self._p(X, torch.float32, "X"), X.shape[0],
+                                               self._p(mean, torch.float32, "mean"),
+                                               self._p(std, torch.float32, "std"), _stream(stream)))
+        return mean, std
+
+    def selector_set(self, params, mean, std, H1=512, H2=512, k=20, min_mass=0.99,
+                     max_train_batch=0, stream=None):
+        self.sel_dims = SelectorDims(H1, H2, k, min_mass, max_train_batch)
+        f = torch.float32
+        self._check(self.lib.ivx_selector_set(self.h, ctypes.byref(self.sel_dims),
+                                              self._p(params, f, "params"), self._p(mean, f, "mean"),
+                                              self._p(std, f, "std"), _stream(stream)))
+
+    def selector_param_count(self) -> int:
+        return int(self.lib.ivx_selector_param_count(self.h))
+
+    def selector_get(self, stream=None):
+        out = torch.empty(self.selector_param_count(), dtype=torch.float32, device=self.device)
+        self._check(self.lib.ivx_selector_get(self.h, self._p(out, torch.float32, "params"),
+                                              _stream(stream)))
+        return out
+
+    def selector_forward(self, X, h1=None, h2=None, z=None, prop=None, mass=None, fallback=None,
+                         stream=None):
+        self._check(self.lib.ivx_selector_forward(
+            self.h, self._p(X, torch.float32, "X"), X.shape[0], self._p(h1, torch.bfloat16, "h1"),
+            self._p(h2, torch.bfloat16, "h2"), self._p(z, torch.float32, "z"),
+            self._p(prop, torch.int32, "prop"), self._p(mass, torch.float32, "mass"),
+            self._p(fallback, torch.int32, "fallback"), _stream(stream)))
+
+    def selector_grad(self, X, frame_idx, post_idx, post_val, grad=None, loss=None, stream=None):
+        self._check(self.lib.ivx_selector_grad(
+            self.h, self._p(X, torch.float32, "X"), X.shape[0],
+            self._p(frame_idx, torch.int64, "frame_idx"), frame_idx.shape[0],
+            self._p(post_idx, torch.int32, "post_idx"), self._p(post_val, torch.float32, "post_val"),
+            self._p(grad, torch.float32, "grad"), self._p(loss, torch.float64, "loss"),
+            _stream(stream)))
+
+    def selector_train_step(self, X, frame_idx, post_idx, post_val, lr, loss=None, stream=None):
+        self._check(self.lib.ivx_selector_train_step(
+            self.h, self._p(X, torch.float32, "X"), X.shape[0],
+            self._p(frame_idx, torch.int64, "frame_idx"), frame_idx.shape[0],
+            self._p(post_idx, torch.int32, "post_idx"), self._p(post_val, torch.float32, "post_val"),
+            float(lr), self._p(loss, torch.float64, "loss"), _stream(stream)))
+
+    def selector_counts(self, stream=None):
+        a, b = _I64(), _I64()
+        self._check(self.lib.ivx_selector_counts(self.h, ctypes.byref(a), ctypes.byref(b),
+                                                 _stream(stream)))
+        return a.value, b.value
+
     # ---------------------------------------------------------------- tracing
     def profile_enable(self, capacity=4096):
         self._check(self.lib.ivx_profile_enable(self.h, int(capacity)))
@@ -240,6 +331,27 @@ class Context:
         calls = (ctypes.c_int64 * n)()
         self._check(self.lib.ivx_profile_read(self.h, ms, calls, n))
         return {g: (ms[i], calls[i]) for i, g in enumerate(PROFILE_GROUPS)}
+
+
+class EMGraph:
+    """A captured EM iteration; launch() runs one iteration on the current stream."""
+
+    def __init__(self, ctx: Context, handle, keep):
+        self.ctx, self.h, self._keep = ctx, handle, keep
+
+    def launch(self, stream=None):
+        self.ctx._check(self.ctx.lib.ivx_graph_launch(self.h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.ivx_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Accumulators:

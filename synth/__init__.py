@@ -176,3 +176,30 @@ def make(shape_id: int, seed: int = 0, n_utts: Optional[int] = None,
 def tiny(D=3, C=4, R=2, U=3, lo=4, hi=7, seed=0) -> Workload:
     """A very small custom workload for brute-force pins."""
     return make(1, seed=seed, D=D, C=C, R=R, U=U, lengths=f"uniform:{lo}:{hi}")
+
+
+def mlp_init(D, H1, H2, C, seed=0):
+    """Initial selector parameters, flat FP32 in the order W1 [H1][D], b1,
+    W2 [H2][H1], b2, W3 [C][H2], b3: weights N(0, 2 / fan_in), biases 0."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([9001, seed])))
+    parts = [rng.normal(0.0, np.sqrt(2.0 / D), size=(H1, D)), np.zeros(H1),
+             rng.normal(0.0, np.sqrt(2.0 / H1), size=(H2, H1)), np.zeros(H2),
+             rng.normal(0.0, np.sqrt(2.0 / H2), size=(C, H2)), np.zeros(C)]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def mlp_split(flat, D, H1, H2, C):
+    """Views of a flat parameter vector as (W1, b1, W2, b2, W3, b3)."""
+    shapes = [(H1, D), (H1,), (H2, H1), (H2,), (C, H2), (C,)]
+    out, o = [], 0
+    for sh in shapes:
+        n = int(np.prod(sh))
+        out.append(np.asarray(flat[o:o + n]).reshape(sh))
+        o += n
+    return tuple(out)
+
+
+def sample_frames(F, B, seed):
+    """B distinct frame indices in [0, F), drawn without replacement."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([9002, seed])))
+    return np.sort(rng.choice(F, size=B, replace=False)).astype(np.int64)

@@ -41,7 +41,7 @@ def cfg2_sub():
     return wl, gamma, lse, n, f, S
 
 
-def _run_posteriors(wl):
+def _run_posteriors(wl, prec=0):
     ctx = make_ctx(wl)
     X = dev(wl.X)
     F, C = wl.F, wl.shape.C
@@ -49,17 +49,20 @@ def _run_posteriors(wl):
     pidx = torch.empty((F, 16), dtype=torch.int32, device="cuda")
     pval = torch.empty((F, 16), dtype=torch.float32, device="cuda")
     fll = torch.empty(F, dtype=torch.float64, device="cuda")
-    ctx.ubm_posteriors(X, gamma=gamma, post_idx=pidx, post_val=pval, frame_ll=fll)
+    ctx.ubm_posteriors(X, gamma=gamma, post_idx=pidx, post_val=pval, frame_ll=fll, prec=prec)
     ctx.sync_status()
     return gamma.cpu().numpy(), pidx.cpu().numpy(), pval.cpu().numpy(), fll.cpu().numpy()
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16"])
 @pytest.mark.parametrize("which", ["cfg1", "cfg2_sub"])
-def test_posteriors_match_oracle(which, request):
+def test_posteriors_match_oracle(which, prec, request):
+    """The BF16 split-form filter only changes which components are rescored;
+    the kept ones are scored exactly in FP64, so both forms meet the same bound."""
     wl, g_ref, lse_ref, *_ = request.getfixturevalue(which)
-    gamma, pidx, pval, fll = _run_posteriors(wl)
+    gamma, pidx, pval, fll = _run_posteriors(wl, prec)
     err = np.abs(gamma - g_ref)
-    print(which, "max |dgamma|", err.max(), "candidates/frame", (pidx >= 0).sum(1).mean())
+    print(which, "prec", prec, "max |dgamma|", err.max(), "candidates/frame", (pidx >= 0).sum(1).mean())
     assert err.max() <= 1e-4
     np.testing.assert_allclose(gamma.sum(1), 1.0, atol=1e-5)
     np.testing.assert_allclose(fll, lse_ref, rtol=0, atol=1e-8)
@@ -70,7 +73,7 @@ def test_posteriors_match_oracle(which, request):
     np.testing.assert_array_equal(gamma[rows[ok], pidx[ok]], pval[ok])
 
 
-def _run_stats(wl, with_S=True):
+def _run_stats(wl, with_S=True, prec=0):
     ctx = make_ctx(wl)
     X = dev(wl.X)
     off = dev(wl.utt_off)
@@ -79,15 +82,16 @@ def _run_stats(wl, with_S=True):
     f = torch.empty((U, C, D), dtype=torch.float32, device="cuda")
     S = torch.zeros((C, D * (D + 1) // 2), dtype=torch.float64, device="cuda") if with_S else None
     ll = torch.zeros(1, dtype=torch.float64, device="cuda")
-    ctx.bw_stats(X, off, n, f, S_acc=S, ll_acc=ll)
+    ctx.bw_stats(X, off, n, f, S_acc=S, ll_acc=ll, prec=prec)
     ctx.sync_status()
     return n.cpu().numpy(), f.cpu().numpy(), (S.cpu().numpy() if with_S else None), ll.item()
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16"])
 @pytest.mark.parametrize("which", ["cfg1", "cfg2_sub"])
-def test_bw_stats_match_oracle(which, request):
+def test_bw_stats_match_oracle(which, prec, request):
     wl, g_ref, lse_ref, n_ref, f_ref, S_ref = request.getfixturevalue(which)
-    n, f, S, ll = _run_stats(wl)
+    n, f, S, ll = _run_stats(wl, prec=prec)
     np.testing.assert_allclose(n, n_ref, rtol=1e-5, atol=1e-5)
     np.testing.assert_allclose(f, f_ref, rtol=1e-5, atol=1e-4)
     Sp = packed_upper(S_ref)
