@@ -44,11 +44,47 @@ def parse():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device-to-device once "
                          "(reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the EM iteration replayed from a captured HIP graph")
+    ap.add_argument("--learned-steps", type=int, default=3000,
+                    help="training steps of the learned selector (0: skip the learned form)")
+    ap.add_argument("--learned-batch", type=int, default=4096)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of timing the candidates")
     return ap.parse_args()
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest(path):
+    import hashlib
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, frames):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
+    or None when there is none for this workload and frame count, or when
+    the kernel's source file changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    try:
+        src = os.path.join(ROOT, vals["source"])
+        if source_digest(src) != vals["source_sha256_16"] or int(vals["frames"]) != frames:
+            return None
+        return int(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError, OSError):
+        return None
 
 
 def cpu_baseline(wl, n_sample):
@@ -104,6 +140,83 @@ def cpu_baseline(wl, n_sample):
     }
 
 
+def learned_form(args, ctx, wl, X, step, timed, reset_model, phi, K, dev):
+    """Trains the learned selector on the GPU (exact all-component posteriors
+    of the first tenth of the utterances as targets), then reports its
+    accuracy on the other utterances and the throughput of the EM iteration
+    with IVX_SEL_LEARNED, against the plain all-component form."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1906_08556_amd import ivx
+    C, D, U, F = wl.shape.C, wl.shape.D, wl.U, wl.F
+    H, k, B = 512, 20, args.learned_batch
+    Utr = max(1, U // 10)
+    Ftr = int(wl.utt_off[Utr])
+    reset_model()
+    pi = torch.empty((F, 16), dtype=torch.int32, device=dev)
+    pv = torch.empty((F, 16), dtype=torch.float32, device=dev)
+    ctx.ubm_posteriors(X, post_idx=pi, post_val=pv)
+    mean, std = ctx.feature_stats(X[:Ftr])
+    params = torch.from_numpy(synth.mlp_init(D, H, H, C, seed=args.seed)).to(dev)
+    ctx.selector_set(params, mean, std, H1=H, H2=H, k=k, min_mass=0.99, max_train_batch=B)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_steps = args.learned_steps
+    for i in range(n_steps):
+        fidx = torch.from_numpy(synth.sample_frames(Ftr, B, seed=i)).to(dev)
+        ctx.selector_train_step(X, fidx, pi, pv, 1e-3 if i < 0.7 * n_steps else 3e-4, loss=loss)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    ctx.sync_status()
+    # held-out accuracy: proposal mass, fallback, posterior mass the proposals miss
+    Fe = F - Ftr
+    prop = torch.empty((Fe, k), dtype=torch.int32, device=dev)
+    mass = torch.empty(Fe, dtype=torch.float32, device=dev)
+    ctx.selector_forward(X[Ftr:], prop=prop, mass=mass)
+    fb = mass < 0.99
+    miss = torch.empty(Fe, dtype=torch.float64, device=dev)
+    for r0 in range(0, Fe, 1 << 18):
+        r1 = min(Fe, r0 + (1 << 18))
+        a = pi[Ftr + r0:Ftr + r1].long()
+        hit = ((a.unsqueeze(2) == prop[r0:r1].long().unsqueeze(1)) & (a.unsqueeze(2) >= 0)).any(2)
+        miss[r0:r1] = 1.0 - (pv[Ftr + r0:Ftr + r1].double() * hit).sum(1)
+    kept = ~fb
+    # throughput of the whole EM iteration with the learned selection
+    el, ph, prof = timed(0, K, args.warmup, sel=ivx.IVX_SEL_LEARNED)
+    nfb, pairs = ctx.selector_counts()
+    mlp_ms = prof["sel_mlp"][0] / K
+    mlp_tflops = 2.0 * (D * H + H * H + H * C) * F / (mlp_ms / 1e3) / 1e12 if mlp_ms > 0 else None
+    # one iteration of each form from the same model: i-vectors
+    outs = []
+    for sel in (ivx.IVX_SEL_ALL, ivx.IVX_SEL_LEARNED):
+        reset_model()
+        step(0, sel=sel)
+        ctx.sync_status()
+        outs.append(phi.double().cpu().numpy())
+    a, b = outs
+    cos = (a * b).sum(1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1))
+    m = miss[kept].cpu().numpy() if bool(kept.any()) else np.zeros(1)
+    return {
+        "utts_per_s": round(U * K / el, 3), "ms_per_step": round(el * 1e3 / K, 3),
+        "frame_posteriors_per_s": round(F * K / (ph["frame"] / 1e3), 1),
+        "train": {"steps": n_steps, "batch": B, "seconds": round(t_train, 2),
+                  "final_loss": round(loss.item(), 4), "train_utterances": Utr},
+        "heldout": {"frames": Fe, "fallback_fraction": round(float(fb.float().mean()), 4),
+                    "missed_mass_kept_mean": float(m.mean()),
+                    "missed_mass_kept_p99": float(np.quantile(m, 0.99)),
+                    "missed_mass_all_mean": float(miss.mean())},
+        "timed_pass": {"fallback_frames": nfb, "scored_pairs": pairs},
+        "network_kernels": {"ms_per_step": round(mlp_ms, 3), "achieved_bf16_tflops":
+                            None if mlp_tflops is None else round(mlp_tflops, 2),
+                            "peak": 2500.0,
+                            "frac": None if mlp_tflops is None else round(mlp_tflops / 2500.0, 4)},
+        "vs_plain_first_iteration": {"ivector_min_cosine": float(cos.min())},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -138,7 +251,7 @@ def main():
     ll_utt = torch.zeros(1, dtype=torch.float64, device=dev)
     obj = torch.zeros(1, dtype=torch.float64, device=dev)
     acc = ctx.new_accum()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(max(args.steps, 1))]
     w_d = torch.from_numpy(wl.w).to(dev)
     mu_d = torch.from_numpy(wl.mu).to(dev)
     cov_d = torch.from_numpy(wl.cov).to(dev)
@@ -148,45 +261,49 @@ def main():
         ctx.set_ubm(w_d, mu_d, cov_d)
         ctx.init_tv(T0_d, 100.0)
 
-    def step(prec, phase=None):
+    def step(prec, e=None, sel=ivx.IVX_SEL_ALL):
         S.zero_()
         ll_frames.zero_()
         ll_utt.zero_()
         acc.zero_()
-        if phase is not None:
-            ev[0].record()
-        ctx.bw_stats(X, off, n, f, S_acc=S, ll_acc=ll_frames, prec=prec)
-        if phase is not None:
-            ev[1].record()
+        if e is not None:
+            e[0].record()
+        ctx.bw_stats(X, off, n, f, S_acc=S, ll_acc=ll_frames, prec=prec, sel=sel)
+        if e is not None:
+            e[1].record()
         ctx.tv_estep(n, f, phi, Phi=Phi, ll_acc=ll_utt, prec=prec)
         ctx.tv_mstep_accumulate(n, f, phi, Phi, acc)
         ctx.tv_mstep_solve(acc, S, update_sigma=True, ll_sum=ll_utt, objective=obj)
         ctx.tv_mindiv(acc)
         ctx.ubm_update_means()
-        if phase is not None:
-            ev[2].record()
+        if e is not None:
+            e[2].record()
 
-    def timed(prec, steps, warmup):
+    def timed(prec, steps, warmup, sel=ivx.IVX_SEL_ALL):
         reset_model()
         for _ in range(warmup):
-            step(prec)
+            step(prec, sel=sel)
         ctx.sync_status()
-        ctx.profile_enable(4096)
-        phase = {"frame": 0.0, "em": 0.0}
+        ctx.profile_enable(8192)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            step(prec, phase)
-            torch.cuda.synchronize()  # the phase events of this step are complete
-            phase["frame"] += ev[0].elapsed_time(ev[1])
-            phase["em"] += ev[1].elapsed_time(ev[2])
+        for i in range(steps):
+            step(prec, ev[i], sel=sel)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        phase = {"frame": sum(ev[i][0].elapsed_time(ev[i][1]) for i in range(steps)),
+                 "em": sum(ev[i][1].elapsed_time(ev[i][2]) for i in range(steps))}
         prof = ctx.profile_read()
         ctx.profile_enable(0)
         ctx.sync_status()
         return el, phase, prof
 
+    tuning = None
+    if not args.no_autotune:
+        reset_model()
+        t0 = time.time()
+        tuning = ctx.autotune(X, off)
+        log(f"[bench] autotuned launch shapes {tuning} in {time.time() - t0:.1f}s")
     K = args.steps
     elapsed, phase, prof = timed(0, K, args.warmup)
     if args.copy_calib_mib > 0:
@@ -212,7 +329,8 @@ def main():
     achieved = flop_per_frame_tile * F / fs_avg_s / 1e12
     roof = {"kernel": "k_frame_tile", "bound": "mfma", "achieved": round(achieved, 2),
             "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+            "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
+            "traffic": measured_traffic("k_frame_tile", f"shape{args.shape}", F),
             "avg_launch_ms": round(fs_avg_s * 1e3, 3), "launches_per_step": fs_calls // K,
             "flop_per_frame_per_launch": flop_per_frame_tile, "frames_per_launch": F}
     log("[bench] FP32 kernel groups (ms per step): " + ", ".join(
@@ -248,6 +366,29 @@ def main():
                     "objective_rel_diff": abs(outs[1][1] - outs[0][1]) / abs(outs[0][1])}}
         log(f"[bench] BF16 form: {bf16}")
 
+    graph = None
+    if args.graph:
+        reset_model()
+        g = ctx.graph_create_em(X, off, n, f, S, phi, Phi, acc, ll_frames, ll_utt, obj)
+        for _ in range(args.warmup):
+            g.launch()
+        ctx.sync_status()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            g.launch()
+        torch.cuda.synchronize()
+        elg = time.perf_counter() - t0
+        ctx.sync_status()
+        g.close()
+        graph = {"utts_per_s": round(U * K / elg, 3), "ms_per_step": round(elg * 1e3 / K, 3)}
+        log(f"[bench] graph replay: {graph}")
+
+    learned = None
+    if args.learned_steps > 0:
+        learned = learned_form(args, ctx, wl, X, step, timed, reset_model, phi, K, dev)
+        log(f"[bench] learned selection: {learned}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample ...")
@@ -277,7 +418,10 @@ def main():
         "phase_ms_per_step": {"frame_stage": round(phase["frame"] / K, 3),
                               "em_stage": round(phase["em"] / K, 3)},
         "roofline": roof,
+        "tuning": tuning,
         "bf16_form": bf16,
+        "graph_replay": graph,
+        "learned_selection": learned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -313,6 +313,31 @@ ivx_status ivx_selector_train_step(ivx_ctx* ctx, const float* X, int64_t F,
 ivx_status ivx_selector_counts(ivx_ctx* ctx, int64_t* fallback_frames, int64_t* kept_pairs,
                                void* stream);
 
+/* -------------------------------------------------------------- autotuner */
+
+/* Launch shapes of the hot-path kernels.  Every choice computes the same
+ * result (up to FP32 summation order in the split GEMM).
+ *   frame_ncb       32-component MFMA blocks per launch of the FP32 frame
+ *                   GEMM (4 or 8; 8 * 32 = 256 components per launch)
+ *   frame_ncb_bf16  the same for the BF16 split form
+ *   nf_block        components per n/f statistics workgroup (128 or 256)
+ *   b_split         K-splits of the linear-term GEMM b = p + F V (0: chosen
+ *                   from the grid size; else 1..max) */
+typedef struct {
+  int32_t frame_ncb, frame_ncb_bf16, nf_block, b_split;
+} ivx_tuning;
+
+/* Times the candidate launch shapes on the given workload (X, utt_off as in
+ * bw_stats; needs the UBM and the TV model) with HIP events on `stream`,
+ * keeps the fastest in the context and returns them in *out (or NULL).
+ * Synchronises; allocates nothing; overwrites the context's workspace. */
+ivx_status ivx_autotune(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_t U,
+                        int64_t F, ivx_tuning* out, void* stream);
+ivx_status ivx_tuning_get(const ivx_ctx* ctx, ivx_tuning* out);
+/* Sets the launch shapes (e.g. a saved tuning); IVX_EINVAL for values
+ * outside the lists above. */
+ivx_status ivx_tuning_set(ivx_ctx* ctx, const ivx_tuning* t);
+
 /* ----------------------------------------------------------------- tracing */
 
 /* Opt-in kernel timing with HIP events recorded on the stream each kernel

@@ -122,7 +122,7 @@ void ivx_destroy(ivx_ctx* ctx) {
                   ctx->post_val, ctx->frame_ll, ctx->hist, ctx->coff, ctx->ent, ctx->partial,
                   ctx->Y32, ctx->V32, ctx->Utp, ctx->Psig, ctx->sig_logdet, ctx->Lbuf, ctx->Wbuf, ctx->Psi64,
                   ctx->bpart, ctx->bvec, ctx->llu, ctx->n_ws, ctx->f_ws, ctx->Tnew, ctx->obj_part,
-                  ctx->Gmat, ctx->Mmat, ctx->mvec, ctx->mstat, ctx->dev_err};
+                  ctx->Gmat, ctx->Mmat, ctx->Winv, ctx->mvec, ctx->mstat, ctx->dev_err};
   for (void* p : ptrs)
     if (p) hipFree(p);
   delete ctx;
@@ -203,6 +203,7 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   A(dalloc(&c->obj_part, C));
   A(dalloc(&c->Gmat, R * R));
   A(dalloc(&c->Mmat, R * R));
+  A(dalloc(&c->Winv, (size_t)C * ((R + 15) / 16) * 256));
   A(dalloc(&c->mvec, 4 * R));
   A(dalloc(&c->mstat, C));
   A(dalloc(&c->dev_err, 4));
@@ -227,7 +228,7 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
     set_error("ivx_create: upload failed");
     return IVX_EDEVICE;
   }
-  if (!frame_set_attributes(c) || !select_set_attributes()) {
+  if (!frame_set_attributes(c) || !select_set_attributes() || !mstep_set_attributes()) {
     ivx_destroy(c);
     set_error("ivx_create: hipFuncSetAttribute failed for a large-LDS kernel");
     return IVX_EDEVICE;

@@ -61,6 +61,53 @@ ivx_status ensure_tv(ivx_ctx* ctx, hipStream_t s) {
   return IVX_OK;
 }
 
+}  // namespace
+
+namespace ivx {
+
+// b(u) = p + sum_c V_c^T f_c(u) into ctx->bvec: the FP32 GEMM F V split over
+// K = C D into ns partial products (ns <= 0: enough splits for ~1024
+// workgroups), then a reduction that adds p.
+ivx_status launch_linear_term(ivx_ctx* ctx, const float* f, int64_t U, int ns_req, hipStream_t s) {
+  const int C = ctx->C, D = ctx->D, R = ctx->R;
+  const int64_t K = (int64_t)C * D;
+  int64_t ns = ns_req;
+  if (ns <= 0) {
+    const int64_t tiles = ((U + 127) / 128) * ((R + 127) / 128);
+    ns = (1024 + tiles - 1) / tiles;
+  }
+  if (ns > ctx->nsplit_max) ns = ctx->nsplit_max;
+  if (ns < 1) ns = 1;
+  int64_t kchunk = (K + ns - 1) / ns;
+  kchunk = (kchunk + 15) / 16 * 16;
+  ns = (K + kchunk - 1) / kchunk;
+  GemmArgs gb;
+  gb.A = f;
+  gb.lda = K;
+  gb.B = ctx->V32;
+  gb.ldb = R;
+  gb.C = ctx->bpart;
+  gb.ldc = R;
+  gb.sS = U * R;
+  gb.M = (int)U;
+  gb.N = R;
+  gb.K = (int)K;
+  gb.ksplit = (int)ns;
+  gb.kchunk = (int)kchunk;
+  if (!gemm_f32(gb, false, false, GEMM_STORE, 1, s)) {
+    set_error("tv_estep: GEMM variant not instantiated");
+    return IVX_EINVAL;
+  }
+  launch_reduce_b(ctx, ctx->bpart, (int)ns, U * R, U, ctx->bvec, s);
+  return IVX_OK;
+}
+
+ivx_status ensure_tv_ready(ivx_ctx* ctx, hipStream_t s) { return ensure_tv(ctx, s); }
+
+}  // namespace ivx
+
+namespace {
+
 ivx_status estep_impl(ivx_ctx* ctx, const float* n, const float* f, int64_t U, int prec,
                       float* phi, float* Phi, double* ll_acc, int32_t* info, hipStream_t s) {
   ivx_status st = ensure_tv(ctx, s);
@@ -85,29 +132,7 @@ ivx_status estep_impl(ivx_ctx* ctx, const float* n, const float* f, int64_t U, i
   }
   launch_add_identity(ctx, ctx->Lbuf, U, s);
   // b(u) = p + sum_c V_c^T f_c(u), split over K = C*D
-  const int64_t K = (int64_t)C * D;
-  const int64_t tiles = ((U + 127) / 128) * ((R + 127) / 128);
-  int64_t ns = (1024 + tiles - 1) / tiles;
-  if (ns > ctx->nsplit_max) ns = ctx->nsplit_max;
-  if (ns < 1) ns = 1;
-  int64_t kchunk = (K + ns - 1) / ns;
-  kchunk = (kchunk + 15) / 16 * 16;
-  ns = (K + kchunk - 1) / kchunk;
-  GemmArgs gb;
-  gb.A = f;
-  gb.lda = K;
-  gb.B = ctx->V32;
-  gb.ldb = R;
-  gb.C = ctx->bpart;
-  gb.ldc = R;
-  gb.sS = U * R;
-  gb.M = (int)U;
-  gb.N = R;
-  gb.K = (int)K;
-  gb.ksplit = (int)ns;
-  gb.kchunk = (int)kchunk;
-  if ((st = gemm(gb, false, false, GEMM_STORE, 1, s, "tv_estep")) != IVX_OK) return st;
-  launch_reduce_b(ctx, ctx->bpart, (int)ns, U * R, U, ctx->bvec, s);
+  if ((st = launch_linear_term(ctx, f, U, ctx->tune.b_split, s)) != IVX_OK) return st;
   prof_end(ctx, slot, s);
   {
     ProfScope ps(ctx, PK_ESTEP_CHOL, s);

@@ -188,10 +188,14 @@ struct ivx_ctx {
   double* obj_part = nullptr; // [C]
   double* Gmat = nullptr;     // [R][R]
   double* Mmat = nullptr;     // [R][R]
+  double* Winv = nullptr;     // [C][nb * 256] inverses of the diagonal Cholesky tiles (FP64 solves)
   double* mvec = nullptr;     // [4][R]
   int* mstat = nullptr;       // [C]
 
   int* dev_err = nullptr;     // [4]: see raise_error
+
+  // launch shapes picked by the autotuner (ivx_autotune); defaults below
+  ivx_tuning tune = {8, 8, 256, 0};
 
   // learned Gaussian selection (ivx_selector_set), null until set
   ivx::Selector* sel = nullptr;
@@ -225,6 +229,7 @@ void launch_update_means(ivx_ctx* ctx, hipStream_t s);
 
 // ---- k_frame.hip
 bool frame_set_attributes(const ivx_ctx* ctx);
+bool mstep_set_attributes();
 // Fdev (optional): device frame count, at most F, read by the kernels (the
 // grid is sized for F).  fmap (optional): output row of compact frame i.
 void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, int prec, hipStream_t s,
@@ -241,6 +246,10 @@ void launch_stats_nf(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64
 void launch_stats_S(ivx_ctx* ctx, const float* X, int64_t F, double* S_acc, hipStream_t s);
 void launch_sum_f64(ivx_ctx* ctx, const double* x, int64_t n, double* acc, hipStream_t s);
 void launch_hist_scan(int nb, int C, int* hist, int* coff, hipStream_t s);
+
+// ---- ivx_api_tv.hip
+ivx_status launch_linear_term(ivx_ctx* ctx, const float* f, int64_t U, int ns, hipStream_t s);
+ivx_status ensure_tv_ready(ivx_ctx* ctx, hipStream_t s);
 
 // ---- ivx_api_sel.hip
 void selector_free(ivx_ctx* ctx);

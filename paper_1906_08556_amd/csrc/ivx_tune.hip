@@ -1,0 +1,149 @@
+// Autotuner: times the candidate launch shapes of the hot-path kernels on the
+// caller's workload with HIP events and keeps the fastest in the context.
+//   frame GEMM (FP32 and BF16 forms): 128 or 256 components per launch
+//   n/f statistics: 128 or 256 components per workgroup
+//   linear-term GEMM b = p + F V: number of K splits
+#include <cmath>
+
+#include "ivx_internal.h"
+
+using namespace ivx;
+
+namespace {
+
+#define TUNE_CHECK(cond, ...)      \
+  do {                             \
+    if (!(cond)) {                 \
+      set_error(__VA_ARGS__);      \
+      return IVX_EINVAL;           \
+    }                              \
+  } while (0)
+
+bool valid_tuning(const ivx_tuning& t) {
+  return (t.frame_ncb == 4 || t.frame_ncb == 8) && (t.frame_ncb_bf16 == 4 || t.frame_ncb_bf16 == 8) &&
+         (t.nf_block == 128 || t.nf_block == 256) && t.b_split >= 0 && t.b_split <= 1024;
+}
+
+struct Timer {
+  hipStream_t s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool ok = false;
+  explicit Timer(hipStream_t st) : s(st) {
+    ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  }
+  ~Timer() {
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  }
+  // best of `reps` timed runs after one untimed run; ms, or INFINITY on error
+  template <typename Fn>
+  float best(Fn fn, int reps = 2) {
+    fn();
+    float b = INFINITY;
+    for (int r = 0; r < reps; ++r) {
+      if (hipEventRecord(e0, s) != hipSuccess) return INFINITY;
+      fn();
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return INFINITY;
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return INFINITY;
+      b = std::fmin(b, ms);
+    }
+    return b;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+ivx_status ivx_tuning_get(const ivx_ctx* ctx, ivx_tuning* out) {
+  TUNE_CHECK(ctx && out, "ivx_tuning_get: null argument");
+  *out = ctx->tune;
+  return IVX_OK;
+}
+
+ivx_status ivx_tuning_set(ivx_ctx* ctx, const ivx_tuning* t) {
+  TUNE_CHECK(ctx && t, "ivx_tuning_set: null argument");
+  TUNE_CHECK(valid_tuning(*t), "ivx_tuning_set: value outside the candidate lists");
+  ctx->tune = *t;
+  return IVX_OK;
+}
+
+ivx_status ivx_autotune(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_t U,
+                        int64_t F, ivx_tuning* out, void* stream) {
+  TUNE_CHECK(ctx && X && utt_off, "ivx_autotune: null argument");
+  TUNE_CHECK(ctx->ubm_set && ctx->tv_set, "ivx_autotune: UBM and TV model required");
+  TUNE_CHECK(U >= 1 && U <= ctx->maxU, "ivx_autotune: U=%lld outside [1, %d]", (long long)U,
+             ctx->maxU);
+  TUNE_CHECK(F >= 1 && F <= ctx->maxF, "ivx_autotune: F=%lld outside [1, %lld]", (long long)F,
+             (long long)ctx->maxF);
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    set_error("ivx_autotune: hipSetDevice failed");
+    return IVX_EDEVICE;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Timer tm(s);
+  if (!tm.ok) {
+    set_error("ivx_autotune: hipEventCreate failed");
+    return IVX_EDEVICE;
+  }
+  const bool prof = ctx->prof_on;
+  ctx->prof_on = false;
+  ivx_tuning best = ctx->tune;
+  // frame GEMM, both forms
+  for (int prec = 0; prec < 2; ++prec) {
+    float tb = INFINITY;
+    for (int ncb : {8, 4}) {
+      if (prec == IVX_BF16)
+        ctx->tune.frame_ncb_bf16 = ncb;
+      else
+        ctx->tune.frame_ncb = ncb;
+      const float t = tm.best([&] { launch_frame_select(ctx, X, F, prec, s); });
+      if (t < tb) {
+        tb = t;
+        (prec == IVX_BF16 ? best.frame_ncb_bf16 : best.frame_ncb) = ncb;
+      }
+    }
+  }
+  ctx->tune = best;
+  // posteriors for the statistics candidates
+  launch_frame_select(ctx, X, F, IVX_FP32, s);
+  launch_rescore(ctx, X, F, IVX_FP32, ctx->post_idx, ctx->post_val, ctx->frame_ll, s);
+  {
+    float tb = INFINITY;
+    for (int nfb : {256, 128}) {
+      ctx->tune.nf_block = nfb;
+      const float t = tm.best([&] { launch_stats_nf(ctx, X, utt_off, U, F, ctx->n_ws, ctx->f_ws, s); });
+      if (t < tb) {
+        tb = t;
+        best.nf_block = nfb;
+      }
+    }
+    ctx->tune = best;
+  }
+  ivx_status st = ensure_tv_ready(ctx, s);
+  if (st == IVX_OK) {
+    float tb = INFINITY;
+    for (int ns : {1, 2, 4, 8, 16, 32, 64}) {
+      if (ns > ctx->nsplit_max) break;
+      const float t = tm.best([&] { st = launch_linear_term(ctx, ctx->f_ws, U, ns, s); });
+      if (st != IVX_OK) break;
+      if (t < tb) {
+        tb = t;
+        best.b_split = ns;
+      }
+    }
+  }
+  ctx->tune = best;
+  ctx->prof_on = prof;
+  if (st != IVX_OK) return st;
+  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
+    set_error("ivx_autotune: a timed launch failed");
+    return IVX_EDEVICE;
+  }
+  if (out) *out = best;
+  return IVX_OK;
+}
+
+}  // extern "C"

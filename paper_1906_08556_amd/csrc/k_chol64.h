@@ -1,0 +1,224 @@
+// FP64 tile kernels for symmetric positive definite matrices in the
+// tile-packed layout (16 x 16 lower tiles, row-major tile order, each tile
+// row-major), on v_mfma_f64_16x16x4f64.  Used by the M-step solve and the
+// minimum-divergence set-up; every function is called by all 256 threads of
+// the workgroup.
+#pragma once
+
+#include "ivx_internal.h"
+
+namespace ivx {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__device__ inline int64_t tp_off(int bi, int bj) { return (int64_t)(bi * (bi + 1) / 2 + bj) * 256; }
+
+// v_mfma_f64_16x16x4f64 operand layout: lane l holds A[l % 16][k] and
+// B[k][l % 16] with k = l / 16 of each 4-wide K step; result register r of
+// lane l is C[4 r + l / 16][l % 16].
+// acc += s * X Y^T for 16 x 16 row-major tiles given by element accessors
+// x(i, k), y(j, k).
+template <typename FX, typename FY>
+__device__ inline doublex4 mma16_xyt(FX x, FY y, doublex4 acc, double s) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, q16 = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double a = s * x(l16, 4 * q + q16);
+    const double b = y(l16, 4 * q + q16);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__device__ inline void tri_decode(int t, int& ii, int& jj) {
+  int i = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  ii = i;
+  jj = t - i * (i + 1) / 2;
+}
+
+// Blocked right-looking Cholesky A = G G^T of an nb x nb-tile matrix in
+// place (lower tiles).  The inverse of every diagonal tile, W_k = G_kk^{-1}
+// (row-major, upper part zero), goes to Winv[k * 256].  LDS: dg [256],
+// pan [(nb - 1) * 256].  Returns 0, or 1 + the first row whose pivot was not
+// positive (then A is partly overwritten).
+__device__ inline int chol_tp64(double* __restrict__ A, int nb, double* __restrict__ Winv,
+                                double* dg, double* pan, int* s_bad) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, q16 = lane >> 4;
+  if (tid == 0) *s_bad = 0;
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    if (wave == 0) {
+      double* Akk = A + tp_off(k, k);
+      for (int e = lane; e < 256; e += 64) dg[e] = Akk[e];
+      __builtin_amdgcn_wave_barrier();
+      for (int j = 0; j < 16; ++j) {
+        const double piv = dg[j * 16 + j];
+        if (!(piv > 0.0) || !isfinite(piv)) {
+          if (lane == 0) *s_bad = k * 16 + j + 1;
+          break;  // piv is the same in every lane: uniform exit
+        }
+        const double ljj = sqrt(piv);
+        __builtin_amdgcn_wave_barrier();
+        if (lane > j && lane < 16) dg[lane * 16 + j] /= ljj;
+        if (lane == j) dg[j * 16 + j] = ljj;
+        __builtin_amdgcn_wave_barrier();
+        for (int e = lane; e < 256; e += 64) {
+          const int i = e >> 4, c = e & 15;
+          if (c > j && i >= c) dg[e] -= dg[i * 16 + j] * dg[c * 16 + j];
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      for (int e = lane; e < 256; e += 64) {
+        const int i = e >> 4, c = e & 15;
+        const double v = (c <= i) ? dg[e] : 0.0;
+        dg[e] = v;
+        Akk[e] = v;
+      }
+      __builtin_amdgcn_wave_barrier();
+      // W = G_kk^{-1}: lane j < 16 solves column j by forward substitution
+      if (lane < 16 && *s_bad == 0) {
+        const int j = lane;
+        double w[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+          for (int l = 0; l < i; ++l) s -= dg[i * 16 + l] * w[l];
+          w[i] = (i >= j) ? s / dg[i * 16 + i] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Winv[k * 256 + i * 16 + j] = w[i];
+      }
+    }
+    __syncthreads();
+    if (*s_bad) return *s_bad;
+    const double* W = Winv + k * 256;
+    const int m = nb - k - 1;
+    // panel: P_i = A_(k+1+i),k W^T, to A and LDS
+    for (int it = wave; it < m; it += 4) {
+      double* At = A + tp_off(k + 1 + it, k);
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16_xyt([&](int i, int l) { return At[i * 16 + l]; },
+                      [&](int j, int l) { return W[j * 16 + l]; }, acc, 1.0);
+      // all lanes have read the tile before anyone writes it
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = (4 * r + q16) * 16 + l16;
+        At[e] = acc[r];
+        pan[it * 256 + e] = acc[r];
+      }
+    }
+    __syncthreads();
+    // trailing update: A_(k+1+ii),(k+1+jj) -= P_ii P_jj^T, jj <= ii
+    const int nt = m * (m + 1) / 2;
+    for (int t = wave; t < nt; t += 4) {
+      int ii, jj;
+      tri_decode(t, ii, jj);
+      double* Ct = A + tp_off(k + 1 + ii, k + 1 + jj);
+      doublex4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = Ct[(4 * r + q16) * 16 + l16];
+      const double* Pi = pan + ii * 256;
+      const double* Pj = pan + jj * 256;
+      acc = mma16_xyt([&](int i, int l) { return Pi[i * 16 + l]; },
+                      [&](int j, int l) { return Pj[j * 16 + l]; }, acc, -1.0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Ct[(4 * r + q16) * 16 + l16] = acc[r];
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
+// Solves (G G^T) X = B in place for B of nrow (<= nb * 16) rows and ncol
+// (<= 64) columns, element (r, d) at B[d * ldb + r]; rows >= nrow and
+// columns >= ncol are treated as zero and never written.  G and Winv come
+// from chol_tp64.  LDS: zb [16 * 64].
+__device__ inline void solve_tp64(const double* __restrict__ G, const double* __restrict__ Winv,
+                                  int nb, double* __restrict__ B, int64_t ldb, int nrow, int ncol,
+                                  double* zb) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, q16 = lane >> 4;
+  auto bat = [&](int r, int d) -> double {
+    return (r < nrow && d < ncol) ? B[(int64_t)d * ldb + r] : 0.0;
+  };
+  // forward: G Z = B
+  for (int k = 0; k < nb; ++k) {
+    const double* W = Winv + k * 256;
+    {  // Z_k = W_k B_k, column block `wave`
+      const int d0 = wave * 16;
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16_xyt([&](int i, int l) { return W[i * 16 + l]; },
+                      [&](int j, int l) { return bat(k * 16 + l, d0 + j); }, acc, 1.0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) zb[(4 * r + q16) * 64 + d0 + l16] = acc[r];
+    }
+    __syncthreads();
+    {
+      const int d0 = wave * 16;
+      for (int r = 0; r < 4; ++r) {
+        const int row = k * 16 + 4 * r + q16, d = d0 + l16;
+        if (row < nrow && d < ncol) B[(int64_t)d * ldb + row] = zb[(4 * r + q16) * 64 + d];
+      }
+    }
+    // B_i -= G_ik Z_k for i > k
+    const int m = nb - k - 1;
+    for (int w = wave; w < 4 * m; w += 4) {
+      const int it = k + 1 + (w >> 2), d0 = (w & 3) * 16;
+      const double* Gt = G + tp_off(it, k);
+      doublex4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = bat(it * 16 + 4 * r + q16, d0 + l16);
+      acc = mma16_xyt([&](int i, int l) { return Gt[i * 16 + l]; },
+                      [&](int j, int l) { return zb[l * 64 + d0 + j]; }, acc, -1.0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = it * 16 + 4 * r + q16, d = d0 + l16;
+        if (row < nrow && d < ncol) B[(int64_t)d * ldb + row] = acc[r];
+      }
+    }
+    __syncthreads();
+  }
+  // backward: G^T X = Z
+  for (int k = nb - 1; k >= 0; --k) {
+    const double* W = Winv + k * 256;
+    {  // X_k = W_k^T Z_k
+      const int d0 = wave * 16;
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16_xyt([&](int i, int l) { return W[l * 16 + i]; },
+                      [&](int j, int l) { return bat(k * 16 + l, d0 + j); }, acc, 1.0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) zb[(4 * r + q16) * 64 + d0 + l16] = acc[r];
+    }
+    __syncthreads();
+    {
+      const int d0 = wave * 16;
+      for (int r = 0; r < 4; ++r) {
+        const int row = k * 16 + 4 * r + q16, d = d0 + l16;
+        if (row < nrow && d < ncol) B[(int64_t)d * ldb + row] = zb[(4 * r + q16) * 64 + d];
+      }
+    }
+    // Z_i -= G_ki^T X_k for i < k
+    for (int w = wave; w < 4 * k; w += 4) {
+      const int it = w >> 2, d0 = (w & 3) * 16;
+      const double* Gt = G + tp_off(k, it);
+      doublex4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = bat(it * 16 + 4 * r + q16, d0 + l16);
+      acc = mma16_xyt([&](int i, int l) { return Gt[l * 16 + i]; },
+                      [&](int j, int l) { return zb[l * 64 + d0 + j]; }, acc, -1.0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = it * 16 + 4 * r + q16, d = d0 + l16;
+        if (row < nrow && d < ncol) B[(int64_t)d * ldb + row] = acc[r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace ivx

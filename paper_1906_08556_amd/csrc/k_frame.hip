@@ -26,8 +26,8 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 constexpr int FR = 32;        // frames per wave (one 32-frame MFMA block)
 constexpr int NW = 4;         // waves per workgroup
 constexpr int FT = FR * NW;   // frames per workgroup
-constexpr int NCB = 8;        // 32-component MFMA blocks per tile
-constexpr int CT = 32 * NCB;  // components per launch (one tile)
+// NCB (template): 32-component MFMA blocks per tile, CT = 32 NCB components
+// per launch; 4 or 8 (picked by the autotuner)
 constexpr int CAPL = KP / 2;  // candidate slots per lane-half per frame
 constexpr int WLD = 12;       // LDS row stride (floats) of a staged [CT][8] W chunk
 
@@ -52,12 +52,16 @@ __device__ inline int compact_cands(int2* __restrict__ lst, float thr) {
 //
 // W layout (k_ubm_prepare): chunk-major, coefficient (c, k) at
 // ((k / 8) * Cpad + c) * 8 + k % 8, so a chunk of a tile is contiguous.
+template <int NCB>
 __global__ void __launch_bounds__(256, 2)
 k_frame_tile(const float* __restrict__ X, int64_t F, int D, const float* __restrict__ shift,
              const float* __restrict__ W, int C, int Cpad, int Kpad,
              const uint16_t* __restrict__ pairs, float margin, int c0, int first,
              int2* __restrict__ cand, float* __restrict__ cM, int* __restrict__ cflag,
              const int* __restrict__ Fdev) {
+  constexpr int CT = 32 * NCB;   // components per launch
+  constexpr int TPC = 256 / CT;  // threads per staged component
+  constexpr int NV = 2 / TPC;    // float4 per thread and chunk
   extern __shared__ float smem[];
   if (Fdev && (int64_t)Fdev[0] < F) F = Fdev[0];
   if ((int64_t)blockIdx.x * FT >= F) return;  // whole workgroup, before any barrier
@@ -78,17 +82,19 @@ k_frame_tile(const float* __restrict__ X, int64_t F, int D, const float* __restr
     if (a > 0 && g < F) v = X[g * D + (a - 1)] - shift[a - 1];
     xs[i] = v;
   }
-  // W chunk loader: thread t stages the 8 coefficients of component c0 + t
-  float4 r0, r1;
+  // W chunk loader: TPC threads stage the 8 coefficients of one component
+  const int lc = tid / TPC, part = tid % TPC;
+  float4 rv[NV];
   auto gload = [&](int q) {
-    const float4* p = reinterpret_cast<const float4*>(W + ((size_t)q * Cpad + c0 + tid) * 8);
-    r0 = p[0];
-    r1 = p[1];
+    const float4* p =
+        reinterpret_cast<const float4*>(W + ((size_t)q * Cpad + c0 + lc) * 8 + part * 4 * NV);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) rv[v] = p[v];
   };
   auto sstore = [&](int buf) {
-    float* d = Ws + (buf * CT + tid) * WLD;
-    *reinterpret_cast<float4*>(d) = r0;
-    *reinterpret_cast<float4*>(d + 4) = r1;
+    float* d = Ws + (buf * CT + lc) * WLD + part * 4 * NV;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) *reinterpret_cast<float4*>(d + 4 * v) = rv[v];
   };
   gload(0);
   sstore(0);
@@ -195,12 +201,16 @@ constexpr int WB16 = 40;  // LDS row stride (bf16) of a staged comp: 16 hi, 16 l
 
 // W16 layout (k_ubm_prepare): [Kpad/16][Cpad][32] bf16, per component 16 hi
 // then 16 lo coefficients of the chunk.
+template <int NCB>
 __global__ void __launch_bounds__(256, 2)
 k_frame_tile_bf16(const float* __restrict__ X, int64_t F, int D, const float* __restrict__ shift,
                   const __bf16* __restrict__ W16, int C, int Cpad, int Kpad,
                   const uint16_t* __restrict__ pairs, float margin, int c0, int first,
                   int2* __restrict__ cand, float* __restrict__ cM, int* __restrict__ cflag,
                   const int* __restrict__ Fdev) {
+  constexpr int CT = 32 * NCB;   // components per launch
+  constexpr int TPC = 256 / CT;  // threads per staged component
+  constexpr int NV = 4 / TPC;    // uint4 (8 bf16) per thread and chunk
   extern __shared__ float smem[];
   if (Fdev && (int64_t)Fdev[0] < F) F = Fdev[0];
   if ((int64_t)blockIdx.x * FT >= F) return;  // whole workgroup, before any barrier
@@ -221,21 +231,19 @@ k_frame_tile_bf16(const float* __restrict__ X, int64_t F, int D, const float* __
     if (a > 0 && g < F) v = X[g * D + (a - 1)] - shift[a - 1];
     xs[i] = v;
   }
-  // chunk loader: thread t stages the 32 bf16 (64 B) of component c0 + t
-  uint4 r0, r1, r2, r3;
+  // chunk loader: TPC threads stage the 32 bf16 (64 B) of one component
+  const int lc = tid / TPC, part = tid % TPC;
+  uint4 rv[NV];
   auto gload = [&](int q) {
-    const uint4* p = reinterpret_cast<const uint4*>(W16 + ((size_t)q * Cpad + c0 + tid) * 32);
-    r0 = p[0];
-    r1 = p[1];
-    r2 = p[2];
-    r3 = p[3];
+    const uint4* p =
+        reinterpret_cast<const uint4*>(W16 + ((size_t)q * Cpad + c0 + lc) * 32 + part * 8 * NV);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) rv[v] = p[v];
   };
   auto sstore = [&](int buf) {
-    uint4* d = reinterpret_cast<uint4*>(Ws + (buf * CT + tid) * WB16);
-    d[0] = r0;
-    d[1] = r1;
-    d[2] = r2;
-    d[3] = r3;
+    uint4* d = reinterpret_cast<uint4*>(Ws + (buf * CT + lc) * WB16 + part * 8 * NV);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) d[v] = rv[v];
   };
   gload(0);
   sstore(0);
@@ -441,42 +449,67 @@ __global__ void k_scatter_gamma(int64_t F, int C, const int* __restrict__ post_i
   if (c >= 0) gamma[(i / KP) * C + c] = post_val[i];
 }
 
+template <int NCB>
+size_t frame_lds_bf16(int D, int Kpad) {
+  return sizeof(__bf16) * 2 * (32 * NCB) * WB16 + sizeof(float) * (size_t)FT * (D + 1) +
+         sizeof(uint16_t) * Kpad;
+}
+template <int NCB>
+size_t frame_lds_f32(int D, int Kpad) {
+  return sizeof(float) * (2 * (32 * NCB) * WLD + (size_t)FT * (D + 1)) + sizeof(uint16_t) * Kpad;
+}
+
+template <int NCB>
+void frame_launches(ivx_ctx* ctx, const float* X, int64_t F, int prec, hipStream_t s,
+                    const int* Fdev) {
+  constexpr int CT = 32 * NCB;
+  const unsigned nblk = (unsigned)((F + FT - 1) / FT);
+  if (prec == IVX_BF16) {
+    const size_t lds = frame_lds_bf16<NCB>(ctx->D, ctx->Kpad);
+    for (int c0 = 0; c0 < ctx->Cpad; c0 += CT) {
+      ProfScope ps(ctx, PK_FRAME_SELECT, s);
+      k_frame_tile_bf16<NCB><<<nblk, 256, lds, s>>>(X, F, ctx->D, ctx->shift, ctx->W16, ctx->C,
+                                                    ctx->Cpad, ctx->Kpad, ctx->pairs,
+                                                    ctx->margin_bf16, c0, c0 == 0 ? 1 : 0,
+                                                    ctx->cand, ctx->cM, ctx->cflag, Fdev);
+    }
+    return;
+  }
+  const size_t lds = frame_lds_f32<NCB>(ctx->D, ctx->Kpad);
+  for (int c0 = 0; c0 < ctx->Cpad; c0 += CT) {
+    ProfScope ps(ctx, PK_FRAME_SELECT, s);
+    k_frame_tile<NCB><<<nblk, 256, lds, s>>>(X, F, ctx->D, ctx->shift, ctx->Wexp, ctx->C,
+                                             ctx->Cpad, ctx->Kpad, ctx->pairs, ctx->margin, c0,
+                                             c0 == 0 ? 1 : 0, ctx->cand, ctx->cM, ctx->cflag,
+                                             Fdev);
+  }
+}
+
 }  // namespace
 
-// The BF16 tile kernel uses more than 64 KB of LDS (gfx950 has 160 KB per CU);
-// called once per context at creation, outside any stream capture.
+// Kernels using more than 64 KB of LDS (gfx950 has 160 KB per CU); called
+// once per context at creation, outside any stream capture.
 bool frame_set_attributes(const ivx_ctx* ctx) {
-  const size_t lds16 = sizeof(__bf16) * 2 * CT * WB16 + sizeof(float) * (size_t)FT * (ctx->D + 1) +
-                       sizeof(uint16_t) * ctx->Kpad;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_frame_tile_bf16),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds16) == hipSuccess;
+  bool ok = true;
+  auto set = [&](const void* fn, size_t bytes) {
+    ok = ok && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+                   hipSuccess;
+  };
+  set(reinterpret_cast<const void*>(&k_frame_tile_bf16<8>), frame_lds_bf16<8>(ctx->D, ctx->Kpad));
+  set(reinterpret_cast<const void*>(&k_frame_tile_bf16<4>), frame_lds_bf16<4>(ctx->D, ctx->Kpad));
+  set(reinterpret_cast<const void*>(&k_frame_tile<8>), frame_lds_f32<8>(ctx->D, ctx->Kpad));
+  set(reinterpret_cast<const void*>(&k_frame_tile<4>), frame_lds_f32<4>(ctx->D, ctx->Kpad));
+  return ok;
 }
 
 void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, int prec, hipStream_t s,
                          const int* Fdev) {
   if (F <= 0) return;
-  const int DS = ctx->D + 1;
-  if (prec == IVX_BF16) {
-    const size_t lds16 = sizeof(__bf16) * 2 * CT * WB16 + sizeof(float) * (size_t)FT * DS +
-                         sizeof(uint16_t) * ctx->Kpad;
-    const unsigned nb16 = (unsigned)((F + FT - 1) / FT);
-    for (int c0 = 0; c0 < ctx->Cpad; c0 += CT) {
-      ProfScope ps(ctx, PK_FRAME_SELECT, s);
-      k_frame_tile_bf16<<<nb16, 256, lds16, s>>>(X, F, ctx->D, ctx->shift, ctx->W16, ctx->C,
-                                                 ctx->Cpad, ctx->Kpad, ctx->pairs,
-                                                 ctx->margin_bf16, c0, c0 == 0 ? 1 : 0, ctx->cand,
-                                                 ctx->cM, ctx->cflag, Fdev);
-    }
-    return;
-  }
-  const size_t lds = sizeof(float) * (2 * CT * WLD + (size_t)FT * DS) + sizeof(uint16_t) * ctx->Kpad;
-  const unsigned nblk = (unsigned)((F + FT - 1) / FT);
-  for (int c0 = 0; c0 < ctx->Cpad; c0 += CT) {
-    ProfScope ps(ctx, PK_FRAME_SELECT, s);
-    k_frame_tile<<<nblk, 256, lds, s>>>(X, F, ctx->D, ctx->shift, ctx->Wexp, ctx->C, ctx->Cpad,
-                                        ctx->Kpad, ctx->pairs, ctx->margin, c0, c0 == 0 ? 1 : 0,
-                                        ctx->cand, ctx->cM, ctx->cflag, Fdev);
-  }
+  const int ncb = (prec == IVX_BF16) ? ctx->tune.frame_ncb_bf16 : ctx->tune.frame_ncb;
+  if (ncb == 4)
+    frame_launches<4>(ctx, X, F, prec, s, Fdev);
+  else
+    frame_launches<8>(ctx, X, F, prec, s, Fdev);
 }
 
 void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int prec, int* post_idx,

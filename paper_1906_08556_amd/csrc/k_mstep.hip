@@ -4,10 +4,10 @@
 //  k_objective_parts  per component: N_c(-D/2 log 2pi - 1/2 log|Sigma_c|)
 //                     - 1/2 tr(Sigma_c^{-1} S_c) at the incoming Sigma_c.
 //  k_mstep_solve      per component: blocked Cholesky of A_c (tile-packed,
-//                     in place), T_c^T = A_c^{-1} Cc_c^T by two blocked
-//                     triangular solves (16 right-hand sides at a time), then
-//                     Sigma_c = sym((S_c - T_c Cc_c^T) / N_c) kept only if it
-//                     is positive definite.
+//                     in place, FP64 MFMA updates), T_c^T = A_c^{-1} Cc_c^T
+//                     by two blocked triangular solves over all D right-hand
+//                     sides, then Sigma_c = sym((S_c - T_c Cc_c^T) / N_c) kept
+//                     only if it is positive definite.
 //  k_mindiv_setup     one workgroup: G = H/U - (h/U)(h/U)^T = L_G L_G^T,
 //                     g = L_G^{-1} h/U, Householder vector a, p = P2 g and
 //                     M = P1^{-1} P2^{-1} = L_G P2.
@@ -16,6 +16,7 @@
 
 #include "ivx_internal.h"
 #include "ivx_tv.h"
+#include "k_chol64.h"
 
 namespace ivx {
 namespace {
@@ -25,19 +26,10 @@ constexpr double kLog2Pi = 1.8378770664093454836;
 // frame counts when posteriors are near one-hot) keep T_c and Sigma_c.
 constexpr double kMinCount = 0.5;
 
-__device__ inline int64_t tile_off(int bi, int bj) { return (int64_t)(bi * (bi + 1) / 2 + bj) * 256; }
-
 __device__ inline int64_t packed_idx(int i, int j, int D) {  // i <= j, upper row by row
   return (int64_t)i * D - (int64_t)i * (i - 1) / 2 + (j - i);
 }
 
-__device__ inline void decode_tri(int t, int& ii, int& jj) {
-  int i = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  while (i * (i + 1) / 2 > t) --i;
-  ii = i;
-  jj = t - i * (i + 1) / 2;
-}
 
 __device__ inline double block_sum(double v, double* red) {
   const int tid = threadIdx.x;
@@ -79,181 +71,83 @@ k_objective_finish(const double* __restrict__ part, int C, const double* __restr
   if (threadIdx.x == 0) out[0] = s + (ll_sum ? ll_sum[0] : 0.0);
 }
 
-// one workgroup per component
+// One workgroup per component: blocked FP64 Cholesky of A_c on MFMA
+// (chol_tp64), T_c^T = A_c^{-1} Cc_c^T with all D right-hand sides at once
+// (solve_tp64, in place in T_c), then Sigma_c = sym((S_c - T_c Cc_c^T) / N_c)
+// with T_c Cc_c^T on MFMA, kept only if it is positive definite.  T_c and
+// Sigma_c are untouched when A_c is not positive definite.
 __global__ void __launch_bounds__(256)
 k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
               const double* __restrict__ Cc, const double* __restrict__ N,
               const double* __restrict__ S, int update_sigma, double* __restrict__ T,
-              double* __restrict__ Sigma, int* __restrict__ status, int* __restrict__ err) {
-  extern __shared__ double X[];  // max(nb*256, 2*D*D) doubles
-  __shared__ double dg[256];
+              double* __restrict__ Sigma, double* __restrict__ Winv_all,
+              int* __restrict__ status, int* __restrict__ err) {
+  extern __shared__ double sm[];
+  double* dg = sm;            // [256]
+  double* zb = sm + 256;      // [16 * 64]
+  double* big = sm + 1280;    // max((nb - 1) * 256, 4096 + D * D)
   __shared__ int s_bad;
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, q16 = lane >> 4;
   const double Nc = N[c];
   if (!(Nc >= kMinCount)) {  // no data: keep T_c, Sigma_c
     if (tid == 0) status[c] = 1;
     return;
   }
   double* Ac = A + (int64_t)c * TP;
-  if (tid == 0) s_bad = 0;
+  double* Winv = Winv_all + (int64_t)c * nb * 256;
   // identity on the padded diagonal so the padding factors trivially
-  for (int d = R + tid; d < nb * 16; d += 256) Ac[tile_off(d >> 4, d >> 4) + (d & 15) * 17] = 1.0;
+  for (int d = R + tid; d < nb * 16; d += 256) Ac[tp_off(d >> 4, d >> 4) + (d & 15) * 17] = 1.0;
   __syncthreads();
-
-  // ---- blocked Cholesky of A_c
-  for (int k = 0; k < nb; ++k) {
-    if (wave == 0) {
-      double* Akk = Ac + tile_off(k, k);
-      for (int e = lane; e < 256; e += 64) dg[e] = Akk[e];
-      __builtin_amdgcn_wave_barrier();
-      for (int j = 0; j < 16; ++j) {
-        const double piv = dg[j * 16 + j];
-        if (!(piv > 0.0) || !isfinite(piv)) {
-          if (lane == 0) s_bad = k * 16 + j + 1;
-          break;
-        }
-        const double ljj = sqrt(piv);
-        __builtin_amdgcn_wave_barrier();
-        if (lane > j && lane < 16) dg[lane * 16 + j] /= ljj;
-        if (lane == j) dg[j * 16 + j] = ljj;
-        __builtin_amdgcn_wave_barrier();
-        for (int e = lane; e < 256; e += 64) {
-          const int i = e >> 4, cc = e & 15;
-          if (cc > j && i >= cc) dg[e] -= dg[i * 16 + j] * dg[cc * 16 + j];
-        }
-        __builtin_amdgcn_wave_barrier();
-      }
-      for (int e = lane; e < 256; e += 64) {
-        const int i = e >> 4, cc = e & 15;
-        const double v = (cc <= i) ? dg[e] : 0.0;
-        dg[e] = v;
-        Akk[e] = v;
-      }
-    }
-    __syncthreads();
-    if (s_bad) break;
-    const int m = nb - k - 1;
-    for (int row = tid; row < m * 16; row += 256) {
-      const int it = row >> 4, r = row & 15;
-      double* src = Ac + tile_off(k + 1 + it, k) + r * 16;
-      double x[16];
-#pragma unroll
-      for (int cc = 0; cc < 16; ++cc) x[cc] = src[cc];
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        double s = x[j];
-#pragma unroll
-        for (int l = 0; l < j; ++l) s -= x[l] * dg[j * 16 + l];
-        x[j] = s / dg[j * 16 + j];
-      }
-#pragma unroll
-      for (int cc = 0; cc < 16; ++cc) {
-        src[cc] = x[cc];
-        X[it * 256 + r * 16 + cc] = x[cc];
-      }
-    }
-    __syncthreads();
-    const int ntile = m * (m + 1) / 2;
-    const int i = tid >> 4, j = tid & 15;
-    for (int t = 0; t < ntile; ++t) {
-      int ii, jj;
-      decode_tri(t, ii, jj);
-      const double* Pi = X + ii * 256;
-      const double* Pj = X + jj * 256;
-      double s = 0.0;
-#pragma unroll
-      for (int l = 0; l < 16; ++l) s += Pi[i * 16 + l] * Pj[j * 16 + l];
-      Ac[tile_off(k + 1 + ii, k + 1 + jj) + i * 16 + j] -= s;
-    }
-    __syncthreads();
-  }
-  if (s_bad) {
+  const int bad = chol_tp64(Ac, nb, Winv, dg, big, &s_bad);
+  if (bad) {
     if (tid == 0) {
       status[c] = 3;
       raise_error(err, IVX_ENOTPD, PK_MSTEP, c);
     }
     return;
   }
-
-  // ---- T_c^T = A_c^{-1} Cc_c^T, 16 columns (feature dims) at a time
+  // T_c^T = A_c^{-1} Cc_c^T: right-hand sides copied into T_c ([D][R])
   const double* Ccc = Cc + (int64_t)c * D * R;
   double* Tc = T + (int64_t)c * D * R;
-  for (int d0 = 0; d0 < D; d0 += 16) {
-    for (int e = tid; e < nb * 256; e += 256) {
-      const int r = e >> 4, jc = e & 15;
-      X[e] = (r < R && d0 + jc < D) ? Ccc[(int64_t)(d0 + jc) * R + r] : 0.0;
-    }
-    __syncthreads();
-    for (int k = 0; k < nb; ++k) {  // forward: G z = b
-      if (tid < 16) {
-        const double* Gkk = Ac + tile_off(k, k);
-        const int jc = tid;
-        for (int l = 0; l < 16; ++l) {
-          double s = X[(k * 16 + l) * 16 + jc];
-          for (int q = 0; q < l; ++q) s -= Gkk[l * 16 + q] * X[(k * 16 + q) * 16 + jc];
-          X[(k * 16 + l) * 16 + jc] = s / Gkk[l * 16 + l];
-        }
-      }
-      __syncthreads();
-      for (int e = tid; e < (nb - k - 1) * 256; e += 256) {
-        const int row = (k + 1) * 16 + (e >> 4), jc = e & 15;
-        const double* G = Ac + tile_off(row >> 4, k) + (row & 15) * 16;
-        double s = 0.0;
-#pragma unroll
-        for (int l = 0; l < 16; ++l) s += G[l] * X[(k * 16 + l) * 16 + jc];
-        X[row * 16 + jc] -= s;
-      }
-      __syncthreads();
-    }
-    for (int k = nb - 1; k >= 0; --k) {  // backward: G^T x = z
-      if (tid < 16) {
-        const double* Gkk = Ac + tile_off(k, k);
-        const int jc = tid;
-        for (int l = 15; l >= 0; --l) {
-          double s = X[(k * 16 + l) * 16 + jc];
-          for (int q = l + 1; q < 16; ++q) s -= Gkk[q * 16 + l] * X[(k * 16 + q) * 16 + jc];
-          X[(k * 16 + l) * 16 + jc] = s / Gkk[l * 16 + l];
-        }
-      }
-      __syncthreads();
-      for (int e = tid; e < k * 256; e += 256) {
-        const int row = e >> 4, jc = e & 15;  // row in blocks < k
-        const double* G = Ac + tile_off(k, row >> 4) + (row & 15);
-        double s = 0.0;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) s += G[r * 16] * X[(k * 16 + r) * 16 + jc];
-        X[row * 16 + jc] -= s;
-      }
-      __syncthreads();
-    }
-    for (int e = tid; e < 16 * R; e += 256) {
-      const int jc = e / R, r = e - jc * R;
-      if (d0 + jc < D) Tc[(int64_t)(d0 + jc) * R + r] = X[r * 16 + jc];
-    }
-    __syncthreads();
-  }
+  for (int e = tid; e < D * R; e += 256) Tc[e] = Ccc[e];
+  __syncthreads();
+  solve_tp64(Ac, Winv, nb, Tc, R, R, D, zb);
   if (!update_sigma) {
     if (tid == 0) status[c] = 0;
     return;
   }
   // ---- Sigma_c = sym((S_c - T_c Cc_c^T) / N_c), kept if positive definite
+  double* Cb = big;          // [64][64] T_c Cc_c^T
+  double* Ms = big + 4096;   // [D][D] candidate
+  for (int t = wave; t < 16; t += 4) {
+    const int ta = t >> 2, tb = t & 3;
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < R; r0 += 16) {
+      acc = mma16_xyt(
+          [&](int i, int l) {
+            const int a = ta * 16 + i, r = r0 + l;
+            return (a < D && r < R) ? Tc[(int64_t)a * R + r] : 0.0;
+          },
+          [&](int j, int l) {
+            const int b = tb * 16 + j, r = r0 + l;
+            return (b < D && r < R) ? Ccc[(int64_t)b * R + r] : 0.0;
+          },
+          acc, 1.0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Cb[(ta * 16 + 4 * r + q16) * 64 + tb * 16 + l16] = acc[r];
+  }
+  __syncthreads();
   const int Dp = D * (D + 1) / 2;
-  double* Ms = X;          // [D][D] symmetric candidate
-  double* Lc = X + D * D;  // [D][D] Cholesky scratch
   for (int e = tid; e < D * D; e += 256) {
     const int a = e / D, b = e - a * D;
-    if (a > b) continue;
-    double s1 = 0.0, s2 = 0.0;
-    for (int r = 0; r < R; ++r) {
-      s1 += Tc[(int64_t)a * R + r] * Ccc[(int64_t)b * R + r];
-      s2 += Tc[(int64_t)b * R + r] * Ccc[(int64_t)a * R + r];
-    }
-    const double v = (S[(int64_t)c * Dp + packed_idx(a, b, D)] - 0.5 * (s1 + s2)) / Nc;
-    Ms[a * D + b] = v;
-    Ms[b * D + a] = v;
-    Lc[a * D + b] = v;
-    Lc[b * D + a] = v;
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    Ms[e] = (S[(int64_t)c * Dp + packed_idx(lo, hi, D)] - 0.5 * (Cb[a * 64 + b] + Cb[b * 64 + a])) / Nc;
   }
+  __syncthreads();
+  double* Lc = Cb;  // Cholesky scratch, D x D
+  for (int e = tid; e < D * D; e += 256) Lc[e] = Ms[e];
   if (tid == 0) s_bad = 0;
   __syncthreads();
   for (int j = 0; j < D; ++j) {
@@ -282,14 +176,22 @@ k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
   if (tid == 0) status[c] = 0;
 }
 
-// Minimum-divergence set-up, one workgroup of 256 threads.
+// Minimum-divergence set-up, one workgroup of 256 threads:
+//   G = H/U - (h/U)(h/U)^T (tile-packed) = L_G L_G^T  (chol_tp64, MFMA)
+//   g = L_G^{-1} h/U, Householder vector a from g, p = P2 g,
+//   M = P1^{-1} P2^{-1} = L_G P2 = L_G - 2 (L_G a) a^T   ([R][R] row-major).
+// On failure M = I and p is left unchanged.
 __global__ void __launch_bounds__(256)
 k_mindiv_setup(int R, int nb, const double* __restrict__ hsum, const double* __restrict__ Htp,
-               const double* __restrict__ count, double* __restrict__ G, double* __restrict__ M,
-               double* __restrict__ vec, double* __restrict__ p, int* __restrict__ err) {
+               const double* __restrict__ count, double* __restrict__ G, double* __restrict__ Winv,
+               double* __restrict__ M, double* __restrict__ vec, double* __restrict__ p,
+               int* __restrict__ err) {
+  extern __shared__ double sm[];
+  double* dg = sm;          // [256]
+  double* pan = sm + 256;   // [(nb - 1) * 256]
   __shared__ double red[256];
   __shared__ double sc[4];
-  __shared__ int bad;
+  __shared__ int s_bad;
   const int tid = threadIdx.x;
   const double U = count[0];
   double* hb = vec;         // h / U
@@ -297,63 +199,66 @@ k_mindiv_setup(int R, int nb, const double* __restrict__ hsum, const double* __r
   double* a = vec + 2 * R;  // Householder vector
   double* v = vec + 3 * R;  // L_G a
   for (int i = tid; i < R; i += 256) hb[i] = hsum[i] / U;
-  if (tid == 0) bad = 0;
   __syncthreads();
-  for (int e = tid; e < R * R; e += 256) {
-    const int i = e / R, j = e - i * R;
-    const int bi = i >> 4, bj = j >> 4;
-    const double Hij = (bi >= bj) ? Htp[tile_off(bi, bj) + (i & 15) * 16 + (j & 15)]
-                                  : Htp[tile_off(bj, bi) + (j & 15) * 16 + (i & 15)];
-    G[e] = Hij / U - hb[i] * hb[j];
+  // G in the tile-packed layout, identity on the padded diagonal
+  const int64_t ntp = (int64_t)nb * (nb + 1) / 2 * 256;
+  for (int64_t e = tid; e < ntp; e += 256) {
+    const int t = (int)(e >> 8), w = (int)(e & 255);
+    int bi, bj;
+    tri_decode(t, bi, bj);
+    const int i = bi * 16 + (w >> 4), j = bj * 16 + (w & 15);
+    double v0;
+    if (i < R && j < R)
+      v0 = Htp[e] / U - hb[i] * hb[j];
+    else
+      v0 = (i == j) ? 1.0 : 0.0;
+    G[e] = v0;
   }
   __syncthreads();
-  // Cholesky of G (lower, in place), column by column
-  for (int j = 0; j < R; ++j) {
-    const double djj = G[(int64_t)j * R + j];
-    if (!(djj > 0.0) || !isfinite(djj)) {
-      if (tid == 0) bad = 1;
-      break;
-    }
-    const double ljj = sqrt(djj);
-    __syncthreads();
-    for (int i = j + 1 + tid; i < R; i += 256) G[(int64_t)i * R + j] /= ljj;
-    if (tid == 0) G[(int64_t)j * R + j] = ljj;
-    __syncthreads();
-    const int m = R - j - 1;
-    const int64_t ne = (int64_t)m * (m + 1) / 2;
-    for (int64_t e = tid; e < ne; e += 256) {
-      int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-      while ((int64_t)(ii + 1) * (ii + 2) / 2 <= e) ++ii;
-      while ((int64_t)ii * (ii + 1) / 2 > e) --ii;
-      const int kk = (int)(e - (int64_t)ii * (ii + 1) / 2);
-      const int row = j + 1 + ii, col = j + 1 + kk;
-      G[(int64_t)row * R + col] -= G[(int64_t)row * R + j] * G[(int64_t)col * R + j];
-    }
-    __syncthreads();
-  }
-  __syncthreads();
+  const int bad = chol_tp64(G, nb, Winv, dg, pan, &s_bad);
   if (bad) {  // leave T and p unchanged: M = I
-    if (tid == 0) raise_error(err, IVX_ENOTPD, PK_MINDIV);
+    if (tid == 0) raise_error(err, IVX_ENOTPD, PK_MINDIV, bad - 1);
     for (int e = tid; e < R * R; e += 256) M[e] = (e / R == e % R) ? 1.0 : 0.0;
     return;
   }
-  // g = L^{-1} hb (forward substitution; the dot products are block reductions)
-  for (int i = 0; i < R; ++i) {
-    double s = 0.0;
-    for (int k = tid; k < i; k += 256) s += G[(int64_t)i * R + k] * g[k];
-    s = block_sum(s, red);
-    if (tid == 0) g[i] = (hb[i] - s) / G[(int64_t)i * R + i];
+  // g = L^{-1} hb, blocked: g_k = W_k r_k, then r_i -= L_ik g_k (i > k)
+  for (int i = tid; i < R; i += 256) g[i] = hb[i];  // r
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    if (tid < 16) {
+      double s = 0.0;
+      for (int l = 0; l < 16; ++l) {
+        const int r = k * 16 + l;
+        if (r < R) s += Winv[k * 256 + tid * 16 + l] * g[r];
+      }
+      red[tid] = s;
+    }
+    __syncthreads();
+    if (tid < 16 && k * 16 + tid < R) g[k * 16 + tid] = red[tid];
+    __syncthreads();
+    for (int i = (k + 1) * 16 + tid; i < R; i += 256) {
+      const double* Lt = G + tp_off(i >> 4, k) + (i & 15) * 16;
+      double s = 0.0;
+      for (int l = 0; l < 16; ++l) s += Lt[l] * g[k * 16 + l];
+      g[i] -= s;
+    }
     __syncthreads();
   }
   double s2 = 0.0;
   for (int i = 1 + tid; i < R; i += 256) s2 += g[i] * g[i];
-  s2 = block_sum(s2, red);
+  red[tid] = s2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
   if (tid == 0) {
-    const double tail = sqrt(s2);
-    const double gn = sqrt(s2 + g[0] * g[0]);
+    const double ss = red[0];
+    const double tail = sqrt(ss);
+    const double gn = sqrt(ss + g[0] * g[0]);
     double alpha = 0.0;
     if (tail > 1e-12 * gn) {
-      const double one_minus = (g[0] > 0.0) ? s2 / (gn * (gn + g[0])) : 1.0 - g[0] / gn;
+      const double one_minus = (g[0] > 0.0) ? ss / (gn * (gn + g[0])) : 1.0 - g[0] / gn;
       alpha = 1.0 / sqrt(2.0 * one_minus);
     }
     sc[0] = gn;
@@ -364,21 +269,28 @@ k_mindiv_setup(int R, int nb, const double* __restrict__ hsum, const double* __r
   // a = alpha h~ + beta e_1, beta = -alpha (a = 0 means P2 = I)
   for (int i = tid; i < R; i += 256) a[i] = alpha * (g[i] / gn) - ((i == 0) ? alpha : 0.0);
   __syncthreads();
-  // p = P2 g = g - 2 a (a^T g);  v = L a
   double ag = 0.0;
   for (int i = tid; i < R; i += 256) ag += a[i] * g[i];
-  ag = block_sum(ag, red);
+  red[tid] = ag;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  ag = red[0];
+  // p = P2 g = g - 2 a (a^T g);  v = L a
   for (int i = tid; i < R; i += 256) {
     p[i] = g[i] - 2.0 * a[i] * ag;
     double s = 0.0;
-    for (int k = 0; k <= i; ++k) s += G[(int64_t)i * R + k] * a[k];
+    for (int k = 0; k <= i; ++k) s += G[tp_off(i >> 4, k >> 4) + (i & 15) * 16 + (k & 15)] * a[k];
     v[i] = s;
   }
   __syncthreads();
   // M = L_G P2 = L_G - 2 (L_G a) a^T
   for (int e = tid; e < R * R; e += 256) {
     const int i = e / R, j = e - i * R;
-    M[e] = ((j <= i) ? G[e] : 0.0) - 2.0 * v[i] * a[j];
+    const double lij = (j <= i) ? G[tp_off(i >> 4, j >> 4) + (i & 15) * 16 + (j & 15)] : 0.0;
+    M[e] = lij - 2.0 * v[i] * a[j];
   }
 }
 
@@ -436,20 +348,34 @@ void launch_objective(ivx_ctx* ctx, const double* N, const double* S, const doub
   k_objective_finish<<<1, 256, 0, s>>>(ctx->obj_part, ctx->C, ll_sum, objective);
 }
 
+size_t mstep_lds_bytes(int R, int D);
+
+bool mstep_set_attributes() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mstep_solve),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)mstep_lds_bytes(480, 63)) == hipSuccess;
+}
+
+size_t mstep_lds_bytes(int R, int D) {
+  const int nb = (R + 15) / 16;
+  size_t nbig = (size_t)(nb - 1) * 256;
+  if ((size_t)4096 + (size_t)D * D > nbig) nbig = (size_t)4096 + (size_t)D * D;
+  return sizeof(double) * (1280 + nbig);
+}
+
 void launch_mstep_solve(ivx_ctx* ctx, const ivx_accum* acc, const double* S, int update_sigma,
                         int* status, hipStream_t s) {
   const int nb = (ctx->R + 15) / 16;
-  size_t nx = (size_t)nb * 256;
-  if ((size_t)2 * ctx->D * ctx->D > nx) nx = (size_t)2 * ctx->D * ctx->D;
-  k_mstep_solve<<<ctx->C, 256, nx * sizeof(double), s>>>(ctx->C, ctx->D, ctx->R, nb, ctx->TP,
-                                                         acc->A, acc->Cc, acc->N, S, update_sigma,
-                                                         ctx->T, ctx->Sigma, status, ctx->dev_err);
+  k_mstep_solve<<<ctx->C, 256, mstep_lds_bytes(ctx->R, ctx->D), s>>>(
+      ctx->C, ctx->D, ctx->R, nb, ctx->TP, acc->A, acc->Cc, acc->N, S, update_sigma, ctx->T,
+      ctx->Sigma, ctx->Winv, status, ctx->dev_err);
 }
 
 void launch_mindiv(ivx_ctx* ctx, const ivx_accum* acc, hipStream_t s) {
   const int nb = (ctx->R + 15) / 16;
-  k_mindiv_setup<<<1, 256, 0, s>>>(ctx->R, nb, acc->h, acc->H, acc->count, ctx->Gmat, ctx->Mmat,
-                                   ctx->mvec, ctx->p, ctx->dev_err);
+  k_mindiv_setup<<<1, 256, sizeof(double) * 256 * nb, s>>>(
+      ctx->R, nb, acc->h, acc->H, acc->count, ctx->Gmat, ctx->Winv, ctx->Mmat, ctx->mvec, ctx->p,
+      ctx->dev_err);
   const int64_t rows = (int64_t)ctx->C * ctx->D;
   dim3 grid((unsigned)((ctx->R + 63) / 64), (unsigned)((rows + 63) / 64));
   k_apply_M<<<grid, 256, 0, s>>>(ctx->T, ctx->Mmat, rows, ctx->R, ctx->Tnew);

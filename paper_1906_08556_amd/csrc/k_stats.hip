@@ -12,9 +12,10 @@
 namespace ivx {
 namespace {
 
-constexpr int NFB = 256;       // components per n/f workgroup
+// NFB (template): components per n/f workgroup, 128 or 256 (autotuner)
 constexpr int HB = 8192;       // frames per histogram block
 
+template <int NFB>
 __global__ void __launch_bounds__(256)
 k_stats_nf(const float* __restrict__ X, const int64_t* __restrict__ utt_off, int64_t U, int64_t F,
            int D, int C, const int* __restrict__ post_idx, const float* __restrict__ post_val,
@@ -217,9 +218,18 @@ __global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ pa
 void launch_stats_nf(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_t U, int64_t F,
                      float* n, float* f, hipStream_t s) {
   if (U <= 0) return;
+  if (ctx->tune.nf_block == 128) {
+    constexpr int NFB = 128;
+    dim3 grid((unsigned)U, (unsigned)((ctx->C + NFB - 1) / NFB));
+    const size_t lds = sizeof(float) * NFB * (ctx->D + 1);
+    k_stats_nf<NFB><<<grid, 256, lds, s>>>(X, utt_off, U, F, ctx->D, ctx->C, ctx->post_idx,
+                                           ctx->post_val, n, f, ctx->dev_err);
+    return;
+  }
+  constexpr int NFB = 256;
   dim3 grid((unsigned)U, (unsigned)((ctx->C + NFB - 1) / NFB));
   const size_t lds = sizeof(float) * NFB * (ctx->D + 1);
-  k_stats_nf<<<grid, 256, lds, s>>>(X, utt_off, U, F, ctx->D, ctx->C, ctx->post_idx,
+  k_stats_nf<NFB><<<grid, 256, lds, s>>>(X, utt_off, U, F, ctx->D, ctx->C, ctx->post_idx,
                                     ctx->post_val, n, f, ctx->dev_err);
 }
 

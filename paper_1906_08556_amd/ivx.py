@@ -41,6 +41,14 @@ class SelectorDims(ctypes.Structure):
                 ("min_mass", ctypes.c_float), ("max_train_batch", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("frame_ncb", ctypes.c_int32), ("frame_ncb_bf16", ctypes.c_int32),
+                ("nf_block", ctypes.c_int32), ("b_split", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class Accum(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("Cc", ctypes.c_void_p), ("N", ctypes.c_void_p),
                 ("h", ctypes.c_void_p), ("H", ctypes.c_void_p), ("count", ctypes.c_void_p)]
@@ -81,6 +89,9 @@ PROTOTYPES = {
     "ivx_selector_grad": (_I32, [_P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P]),
     "ivx_selector_train_step": (_I32, [_P, _P, _I64, _P, _I32, _P, _P, ctypes.c_float, _P, _P]),
     "ivx_selector_counts": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P]),
+    "ivx_autotune": (_I32, [_P, _P, _P, _I64, _I64, ctypes.POINTER(Tuning), _P]),
+    "ivx_tuning_get": (_I32, [_P, ctypes.POINTER(Tuning)]),
+    "ivx_tuning_set": (_I32, [_P, ctypes.POINTER(Tuning)]),
     "ivx_profile_enable": (_I32, [_P, _I32]),
     "ivx_profile_read": (_I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
 }
@@ -319,6 +330,24 @@ class Context:
         self._check(self.lib.ivx_selector_counts(self.h, ctypes.byref(a), ctypes.byref(b),
                                                  _stream(stream)))
         return a.value, b.value
+
+    # ---------------------------------------------------------------- autotuner
+    def autotune(self, X, utt_off, stream=None) -> dict:
+        t = Tuning()
+        self._check(self.lib.ivx_autotune(self.h, self._p(X, torch.float32, "X"),
+                                          self._p(utt_off, torch.int64, "utt_off"),
+                                          utt_off.shape[0] - 1, X.shape[0], ctypes.byref(t),
+                                          _stream(stream)))
+        return t.as_dict()
+
+    def tuning_get(self) -> dict:
+        t = Tuning()
+        self._check(self.lib.ivx_tuning_get(self.h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def tuning_set(self, **kw):
+        t = Tuning(**{**self.tuning_get(), **kw})
+        self._check(self.lib.ivx_tuning_set(self.h, ctypes.byref(t)))
 
     # ---------------------------------------------------------------- tracing
     def profile_enable(self, capacity=4096):

@@ -11,7 +11,8 @@ Generator recipe (all draws PCG64, seeded from SeedSequence([config, seed])):
   * weights  w ~ Dirichlet(1_C)
   * means    mu_c ~ N(0, 4 I)
   * covs     Sigma_c = A^T A, A in R^{(D+5) x D}, A_ij ~ N(0, 1/(D+5))
-  * T_true   entries ~ N(0, 0.05)   (0.05 is a variance)
+  * T_true   entries ~ N(0, 0.05)   (0.05 is a variance); shape 6 reads the
+             same text with 0.05 as the standard deviation (variance 0.0025)
   * utterance u: w_u ~ N(0, I_R); c_t ~ Cat(w);
                x_t = mu_{c_t} + T_true_{c_t} w_u + chol(Sigma_{c_t}) z_t,
                z_t ~ N(0, I_D)
@@ -40,6 +41,7 @@ class Shape:
     U: int
     lengths: str  # "uniform:lo:hi" or "loguniform:lo:hi"
     iters: int
+    t_var: float = 0.05  # variance of the T_true entries
 
 
 # Workload shapes.  Shape 3 shares shape 2's data, shape 5 shares shape 4's.
@@ -49,8 +51,10 @@ SHAPES = {
     3: Shape("full-bf16-precision", 60, 2048, 400, 4000, "uniform:500:1500", 5),
     4: Shape("batching-loguniform", 60, 2048, 400, 20000, "loguniform:200:3000", 5),
     5: Shape("learned-selection", 60, 2048, 400, 20000, "loguniform:200:3000", 5),
+    6: Shape("batching-loguniform-tstd", 60, 2048, 400, 20000, "loguniform:200:3000", 5,
+             t_var=0.0025),
 }
-DATA_OF = {1: 1, 2: 2, 3: 2, 4: 4, 5: 4}
+DATA_OF = {1: 1, 2: 2, 3: 2, 4: 4, 5: 4, 6: 6}
 
 
 @dataclasses.dataclass
@@ -104,7 +108,7 @@ def make_ubm(D: int, C: int, rng: np.random.Generator):
 def make(shape_id: int, seed: int = 0, n_utts: Optional[int] = None,
          D: Optional[int] = None, C: Optional[int] = None, R: Optional[int] = None,
          U: Optional[int] = None, lengths: Optional[str] = None) -> Workload:
-    """Generate workload ``shape_id`` (1..5).
+    """Generate workload ``shape_id`` (1..6).
 
     ``n_utts`` keeps only the first n utterances (they are identical to the
     first n of the full workload).  D/C/R/U/lengths override the shape for
@@ -126,7 +130,7 @@ def make(shape_id: int, seed: int = 0, n_utts: Optional[int] = None,
         s_ubm, s_ttrue, s_lens, s_tinit, s_utts = extra.spawn(5)
     Dd, Cc, Rr = sh.D, sh.C, sh.R
     w, mu, cov = make_ubm(Dd, Cc, np.random.Generator(np.random.PCG64(s_ubm)))
-    T_true = np.sqrt(0.05) * np.random.Generator(np.random.PCG64(s_ttrue)).standard_normal((Cc, Dd, Rr))
+    T_true = np.sqrt(sh.t_var) * np.random.Generator(np.random.PCG64(s_ttrue)).standard_normal((Cc, Dd, Rr))
     T_init = np.random.Generator(np.random.PCG64(s_tinit)).standard_normal((Cc, Dd, Rr))
     lens = _lengths(sh.lengths, sh.U, np.random.Generator(np.random.PCG64(s_lens)))
     nU = sh.U if n_utts is None else min(n_utts, sh.U)
