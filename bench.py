@@ -320,9 +320,11 @@ def main():
     em_utts_per_s = U * K / (phase["em"] / 1e3)
 
     # roofline of the dominant kernel: the expanded-feature frame GEMM, one
-    # launch per 256-component tile (C/256 launches per pass over the frames)
+    # launch per tile of 32 * frame_ncb components (Cpad / tile launches per
+    # pass over the frames)
     Kexp = (D + 1) * (D + 2) // 2
-    tile = 256
+    tune_now = ctx.tuning_get()
+    tile = 32 * tune_now["frame_ncb"]
     flop_per_frame_tile = 2.0 * Kexp * tile
     fs_ms, fs_calls = prof["frame_select"]
     fs_avg_s = fs_ms / max(fs_calls, 1) / 1e3
@@ -332,7 +334,8 @@ def main():
             "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
             "traffic": measured_traffic("k_frame_tile", f"shape{args.shape}", F),
             "avg_launch_ms": round(fs_avg_s * 1e3, 3), "launches_per_step": fs_calls // K,
-            "flop_per_frame_per_launch": flop_per_frame_tile, "frames_per_launch": F}
+            "flop_per_frame_per_launch": flop_per_frame_tile, "frames_per_launch": F,
+            "components_per_launch": tile}
     log("[bench] FP32 kernel groups (ms per step): " + ", ".join(
         f"{k}={v[0] / K:.2f}" for k, v in prof.items() if v[1]))
     log(f"[bench] objective after last step: {obj.item():.6e}")
@@ -343,7 +346,9 @@ def main():
         fs16_ms, fs16_calls = prof16["frame_select"]
         fs16_avg_s = fs16_ms / max(fs16_calls, 1) / 1e3
         bf16_peak = 2500.0
-        ach16 = 3.0 * flop_per_frame_tile * F / fs16_avg_s / 1e12  # three BF16 products per FP32 one
+        tile16 = 32 * tune_now["frame_ncb_bf16"]
+        # three BF16 products (hi*hi, hi*lo, lo*hi) per FP32 one
+        ach16 = 3.0 * 2.0 * Kexp * tile16 * F / fs16_avg_s / 1e12
         log("[bench] BF16 kernel groups (ms per step): " + ", ".join(
             f"{k}={v[0] / K:.2f}" for k, v in prof16.items() if v[1]))
         # one iteration of each form from the same initial model: BF16 vs FP32
@@ -360,7 +365,8 @@ def main():
                 "tv_em_utts_per_s": round(U * K / (ph16["em"] / 1e3), 3),
                 "frame_kernel": {"kernel": "k_frame_tile_bf16", "achieved_bf16_tflops": round(ach16, 2),
                                  "peak": bf16_peak, "frac": round(ach16 / bf16_peak, 4),
-                                 "avg_launch_ms": round(fs16_avg_s * 1e3, 3)},
+                                 "avg_launch_ms": round(fs16_avg_s * 1e3, 3),
+                                 "components_per_launch": tile16},
                 "vs_fp32_form_first_iteration": {
                     "ivector_min_cosine": float(cos.min()),
                     "objective_rel_diff": abs(outs[1][1] - outs[0][1]) / abs(outs[0][1])}}

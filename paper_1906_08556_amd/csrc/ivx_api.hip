@@ -122,7 +122,8 @@ void ivx_destroy(ivx_ctx* ctx) {
                   ctx->post_val, ctx->frame_ll, ctx->hist, ctx->coff, ctx->ent, ctx->partial,
                   ctx->Y32, ctx->V32, ctx->Utp, ctx->Psig, ctx->sig_logdet, ctx->Lbuf, ctx->Wbuf, ctx->Psi64,
                   ctx->bpart, ctx->bvec, ctx->llu, ctx->n_ws, ctx->f_ws, ctx->Tnew, ctx->obj_part,
-                  ctx->Gmat, ctx->Mmat, ctx->Winv, ctx->mvec, ctx->mstat, ctx->dev_err};
+                  ctx->Gmat, ctx->Mmat, ctx->Winv, ctx->Ut16hi, ctx->Ut16lo, ctx->n16hi,
+                  ctx->n16lo, ctx->mvec, ctx->mstat, ctx->dev_err};
   for (void* p : ptrs)
     if (p) hipFree(p);
   delete ctx;
@@ -204,6 +205,13 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   A(dalloc(&c->Gmat, R * R));
   A(dalloc(&c->Mmat, R * R));
   A(dalloc(&c->Winv, (size_t)C * ((R + 15) / 16) * 256));
+  {
+    const size_t Ck = ((size_t)C + 7) / 8 * 8;
+    A(dalloc(&c->Ut16hi, (size_t)TP * Ck));
+    A(dalloc(&c->Ut16lo, (size_t)TP * Ck));
+    A(dalloc(&c->n16hi, (size_t)U * Ck));
+    A(dalloc(&c->n16lo, (size_t)U * Ck));
+  }
   A(dalloc(&c->mvec, 4 * R));
   A(dalloc(&c->mstat, C));
   A(dalloc(&c->dev_err, 4));

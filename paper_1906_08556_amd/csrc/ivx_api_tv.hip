@@ -58,6 +58,7 @@ ivx_status ensure_tv(ivx_ctx* ctx, hipStream_t s) {
   ivx_status st = gemm(g, true, false, GEMM_STORE_TP, ctx->C, s, "tv precompute");
   if (st != IVX_OK) return st;
   ctx->tv_dirty = false;
+  ctx->utp16_valid = false;
   return IVX_OK;
 }
 
@@ -126,7 +127,16 @@ ivx_status estep_impl(ivx_ctx* ctx, const float* n, const float* f, int64_t U, i
   gl.N = (int)ctx->TP;
   gl.K = C;
   if (prec == IVX_BF16) {
-    gemm_bf16x3_nn(gl, s);
+    // operands split into BF16 high / low parts, K (= C) contiguous and
+    // padded to a multiple of 8: U^tp once per model, N per call
+    const int64_t Ck = (C + 7) / 8 * 8;
+    if (!ctx->utp16_valid) {
+      split_bf16_transposed(ctx->Utp, C, ctx->TP, Ck, ctx->Ut16hi, ctx->Ut16lo, s);
+      ctx->utp16_valid = true;
+    }
+    split_bf16(n, U, C, Ck, ctx->n16hi, ctx->n16lo, s);
+    gemm_bf16x3_nt(ctx->n16hi, ctx->n16lo, Ck, ctx->Ut16hi, ctx->Ut16lo, Ck, ctx->Lbuf, ctx->TP,
+                   (int)U, (int)ctx->TP, (int)Ck, s);
   } else if ((st = gemm(gl, false, false, GEMM_STORE, 1, s, "tv_estep")) != IVX_OK) {
     return st;
   }

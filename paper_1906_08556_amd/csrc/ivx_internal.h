@@ -189,6 +189,13 @@ struct ivx_ctx {
   double* Gmat = nullptr;     // [R][R]
   double* Mmat = nullptr;     // [R][R]
   double* Winv = nullptr;     // [C][nb * 256] inverses of the diagonal Cholesky tiles (FP64 solves)
+  // BF16 precision assembly: U^tp transposed and split hi / lo, [TP][Ck];
+  // N split hi / lo, [maxU][Ck] (Ck = C rounded up to a multiple of 8)
+  __bf16* Ut16hi = nullptr;
+  __bf16* Ut16lo = nullptr;
+  __bf16* n16hi = nullptr;
+  __bf16* n16lo = nullptr;
+  bool utp16_valid = false;
   double* mvec = nullptr;     // [4][R]
   int* mstat = nullptr;       // [C]
 

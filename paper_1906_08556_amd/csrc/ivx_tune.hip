@@ -37,7 +37,7 @@ struct Timer {
   }
   // best of `reps` timed runs after one untimed run; ms, or INFINITY on error
   template <typename Fn>
-  float best(Fn fn, int reps = 2) {
+  float best(Fn fn, int reps = 3) {
     fn();
     float b = INFINITY;
     for (int r = 0; r < reps; ++r) {
@@ -100,7 +100,8 @@ ivx_status ivx_autotune(ivx_ctx* ctx, const float* X, const int64_t* utt_off, in
       else
         ctx->tune.frame_ncb = ncb;
       const float t = tm.best([&] { launch_frame_select(ctx, X, F, prec, s); });
-      if (t < tb) {
+      // the 256-component launch is kept unless the other is clearly faster
+      if (t < 0.99f * tb) {
         tb = t;
         (prec == IVX_BF16 ? best.frame_ncb_bf16 : best.frame_ncb) = ncb;
       }

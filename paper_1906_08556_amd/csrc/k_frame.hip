@@ -84,17 +84,19 @@ k_frame_tile(const float* __restrict__ X, int64_t F, int D, const float* __restr
   }
   // W chunk loader: TPC threads stage the 8 coefficients of one component
   const int lc = tid / TPC, part = tid % TPC;
-  float4 rv[NV];
+  // (named registers, not an array: an array captured by the lambdas ends
+  // up in scratch memory)
+  float4 r0, r1;
   auto gload = [&](int q) {
     const float4* p =
         reinterpret_cast<const float4*>(W + ((size_t)q * Cpad + c0 + lc) * 8 + part * 4 * NV);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) rv[v] = p[v];
+    r0 = p[0];
+    if constexpr (NV == 2) r1 = p[1];
   };
   auto sstore = [&](int buf) {
     float* d = Ws + (buf * CT + lc) * WLD + part * 4 * NV;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) *reinterpret_cast<float4*>(d + 4 * v) = rv[v];
+    *reinterpret_cast<float4*>(d) = r0;
+    if constexpr (NV == 2) *reinterpret_cast<float4*>(d + 4) = r1;
   };
   gload(0);
   sstore(0);
@@ -233,17 +235,25 @@ k_frame_tile_bf16(const float* __restrict__ X, int64_t F, int D, const float* __
   }
   // chunk loader: TPC threads stage the 32 bf16 (64 B) of one component
   const int lc = tid / TPC, part = tid % TPC;
-  uint4 rv[NV];
+  uint4 r0, r1, r2, r3;  // named registers (see k_frame_tile)
   auto gload = [&](int q) {
     const uint4* p =
         reinterpret_cast<const uint4*>(W16 + ((size_t)q * Cpad + c0 + lc) * 32 + part * 8 * NV);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) rv[v] = p[v];
+    r0 = p[0];
+    r1 = p[1];
+    if constexpr (NV == 4) {
+      r2 = p[2];
+      r3 = p[3];
+    }
   };
   auto sstore = [&](int buf) {
     uint4* d = reinterpret_cast<uint4*>(Ws + (buf * CT + lc) * WB16 + part * 8 * NV);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) d[v] = rv[v];
+    d[0] = r0;
+    d[1] = r1;
+    if constexpr (NV == 4) {
+      d[2] = r2;
+      d[3] = r3;
+    }
   };
   gload(0);
   sstore(0);

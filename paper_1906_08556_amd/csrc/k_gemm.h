@@ -26,9 +26,18 @@ struct GemmArgs {
 // nothing) for a combination that is not instantiated.
 bool gemm_f32(const GemmArgs& g, bool ta, bool tb, int epi, int batches, hipStream_t s);
 
-// C = A B (row-major FP32 operands, FP32 result) on BF16 MFMA with each
-// operand split into BF16 high and low parts (hi*hi + hi*lo + lo*hi).
-void gemm_bf16x3_nn(const GemmArgs& g, hipStream_t s);
+// C[m][n] = sum_k A[m][k] B[n][k] (FP32 result) on BF16 MFMA from operands
+// pre-split into BF16 high and low parts, K-contiguous (hi*hi + hi*lo +
+// lo*hi).  K must be a multiple of 8 (rows padded with zeros).
+void gemm_bf16x3_nt(const __bf16* Ahi, const __bf16* Alo, int64_t lda, const __bf16* Bhi,
+                    const __bf16* Blo, int64_t ldb, float* C, int64_t ldc, int M, int N, int K,
+                    hipStream_t s);
+// src [rows][cols] FP32 -> BF16 hi / lo [rows][ldo] (zero padding)
+void split_bf16(const float* src, int64_t rows, int64_t cols, int64_t ldo, __bf16* hi, __bf16* lo,
+                hipStream_t s);
+// src [rows][cols] FP32 -> BF16 hi / lo [cols][ldo], transposed (zero padding)
+void split_bf16_transposed(const float* src, int64_t rows, int64_t cols, int64_t ldo, __bf16* hi,
+                           __bf16* lo, hipStream_t s);
 
 // C[m][n] += sum_k A[k*lda + m] * B[k*ldb + n] with FP64 products and sums
 // (k_gemm64.hip).  A is FP32; B is FP64 (b_is_double) or FP32.

@@ -189,99 +189,150 @@ bool gemm_f32(const GemmArgs& g0, bool ta, bool tb, int epi, int batches, hipStr
 }  // namespace ivx
 
 // ------------------------------------------------------------ BF16 split form
-// C = A B (both row-major, FP32 in memory) on v_mfma_f32_32x32x16_bf16 with
-// FP32 accumulation: each operand is split into BF16 high and low parts while
-// it is staged in LDS, and hi*hi + hi*lo + lo*hi are accumulated.  Used for
-// the precision assembly L(u) = I + N U in the BF16 form.
+// C[m][n] = sum_k A[m][k] B[n][k] (FP32 result) on v_mfma_f32_32x32x16_bf16
+// from operands stored pre-split as BF16 high and low parts (v = hi + lo,
+// both K-contiguous): hi*hi + hi*lo + lo*hi are accumulated in FP32.  Used
+// for the precision assembly L(u) = I + N U in the BF16 form.  128 x 128
+// output tile per workgroup, K staged 16 at a time, double-buffered LDS.
 namespace ivx {
 namespace {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-constexpr int BRS = 40;  // LDS row stride (bf16) of a [row][16 hi | 16 lo] tile row
+constexpr int SR = 24;  // LDS row stride (bf16) of a staged 16-k row (48 B)
 
-__global__ void __launch_bounds__(256, 2) k_gemm_bf16x3_nn(GemmArgs g) {
-  __shared__ __bf16 As[128 * BRS];  // [m][k hi 0..15 | k lo 0..15]
-  __shared__ __bf16 Bs[128 * BRS];  // [n][k hi | k lo]
+__global__ void __launch_bounds__(256, 2)
+k_gemm_bf16x3_nt(const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo, int64_t lda,
+                 const __bf16* __restrict__ Bhi, const __bf16* __restrict__ Blo, int64_t ldb,
+                 float* __restrict__ C, int64_t ldc, int M, int N, int K) {
+  // [buf][operand: A hi, A lo, B hi, B lo][128 rows][SR]
+  __shared__ __bf16 St[2][4][128 * SR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int h = lane >> 5, l32 = lane & 31;
-  const int m0 = blockIdx.y * 128, n0 = blockIdx.x * 128;
-  const float* A = g.A;
-  const float* B = g.B;
+  const int64_t m0 = (int64_t)blockIdx.y * 128;
+  const int64_t n0 = (int64_t)blockIdx.x * 128;
+  // loader: thread covers row tid / 2 and k half (tid & 1) * 8 of each operand
+  const int lr = tid >> 1, lk = (tid & 1) * 8;
+  uint4 rg[4];
+  auto load = [&](int k0) {
+    const int64_t am = m0 + lr, bn = n0 + lr;
+    const int k = k0 + lk;
+    const bool ka = k < K;  // K is a multiple of 8
+    rg[0] = (am < M && ka) ? *reinterpret_cast<const uint4*>(Ahi + am * lda + k) : make_uint4(0, 0, 0, 0);
+    rg[1] = (am < M && ka) ? *reinterpret_cast<const uint4*>(Alo + am * lda + k) : make_uint4(0, 0, 0, 0);
+    rg[2] = (bn < N && ka) ? *reinterpret_cast<const uint4*>(Bhi + bn * ldb + k) : make_uint4(0, 0, 0, 0);
+    rg[3] = (bn < N && ka) ? *reinterpret_cast<const uint4*>(Blo + bn * ldb + k) : make_uint4(0, 0, 0, 0);
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int o = 0; o < 4; ++o) *reinterpret_cast<uint4*>(&St[buf][o][lr * SR + lk]) = rg[o];
+  };
   floatx16_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx16_t{0};
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
-    // A tile: 128 rows x 16 k (thread: row tid/2, 8 consecutive k)
-    {
-      const int m = m0 + (tid >> 1), kk = (tid & 1) * 8;
-      __bf16* d = As + (tid >> 1) * BRS + kk;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float v = (m < g.M && k0 + kk + e < g.K) ? A[(int64_t)m * g.lda + k0 + kk + e] : 0.0f;
-        const __bf16 hi = (__bf16)v;
-        d[e] = hi;
-        d[16 + e] = (__bf16)(v - (float)hi);
-      }
-    }
-    // B tile: 16 k x 128 columns, stored transposed (thread: k = tid/16, 8 consecutive n)
-    {
-      const int k = tid >> 4, nn = (tid & 15) * 8;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int n = n0 + nn + e;
-        const float v = (n < g.N && k0 + k < g.K) ? B[(int64_t)(k0 + k) * g.ldb + n] : 0.0f;
-        const __bf16 hi = (__bf16)v;
-        Bs[(nn + e) * BRS + k] = hi;
-        Bs[(nn + e) * BRS + 16 + k] = (__bf16)(v - (float)hi);
-      }
-    }
-    __syncthreads();
+  const int nk = (K + 15) / 16;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) load((it + 1) * 16);
     bf16x8_t ah[2], al[2], bh[2], bl[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const __bf16* a = As + (wm * 64 + i * 32 + l32) * BRS + 8 * h;
-      ah[i] = *reinterpret_cast<const bf16x8_t*>(a);
-      al[i] = *reinterpret_cast<const bf16x8_t*>(a + 16);
-      const __bf16* b = Bs + (wn * 64 + i * 32 + l32) * BRS + 8 * h;
-      bh[i] = *reinterpret_cast<const bf16x8_t*>(b);
-      bl[i] = *reinterpret_cast<const bf16x8_t*>(b + 16);
+      const int ra = (wm * 64 + i * 32 + l32) * SR + 8 * h;
+      const int rb = (wn * 64 + i * 32 + l32) * SR + 8 * h;
+      ah[i] = *reinterpret_cast<const bf16x8_t*>(&St[cur][0][ra]);
+      al[i] = *reinterpret_cast<const bf16x8_t*>(&St[cur][1][ra]);
+      bh[i] = *reinterpret_cast<const bf16x8_t*>(&St[cur][2][rb]);
+      bl[i] = *reinterpret_cast<const bf16x8_t*>(&St[cur][3][rb]);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < 2; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+    if (it + 1 < nk) store(cur ^ 1);
     __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int n = n0 + wn * 64 + j * 32 + l32;
+      const int64_t n = n0 + wn * 64 + j * 32 + l32;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        if (m < g.M && n < g.N) static_cast<float*>(g.C)[(int64_t)m * g.ldc + n] = acc[i][j][r];
+        const int64_t m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (m < M && n < N) C[m * ldc + n] = acc[i][j][r];
       }
     }
 }
 
+// src [rows][cols] FP32 -> hi / lo [rows][ldo] BF16 (cols <= ldo; padding 0)
+__global__ void k_split_bf16(const float* __restrict__ src, int64_t rows, int64_t cols,
+                             int64_t ldo, __bf16* __restrict__ hi, __bf16* __restrict__ lo) {
+  const int64_t n = rows * ldo;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / ldo, c = i - r * ldo;
+    const float v = (c < cols) ? src[r * cols + c] : 0.0f;
+    const __bf16 vh = (__bf16)v;
+    hi[i] = vh;
+    lo[i] = (__bf16)(v - (float)vh);
+  }
+}
+
+// src [rows][cols] FP32 -> hi / lo [cols][ldo] BF16 transposed (rows <= ldo;
+// padding 0), through 64 x 64 LDS tiles
+__global__ void __launch_bounds__(256)
+k_split_bf16_t(const float* __restrict__ src, int64_t rows, int64_t cols, int64_t ldo,
+               __bf16* __restrict__ hi, __bf16* __restrict__ lo) {
+  __shared__ float t[64][65];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int rr = e >> 6, cc = e & 63;
+    const int64_t r = r0 + rr, c = c0 + cc;
+    t[rr][cc] = (r < rows && c < cols) ? src[r * cols + c] : 0.0f;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int cc = e >> 6, rr = e & 63;
+    const int64_t r = r0 + rr, c = c0 + cc;
+    if (c < cols && r < ldo) {
+      const float v = t[rr][cc];
+      const __bf16 vh = (__bf16)v;
+      hi[c * ldo + r] = vh;
+      lo[c * ldo + r] = (__bf16)(v - (float)vh);
+    }
+  }
+}
+
 }  // namespace
 
-void gemm_bf16x3_nn(const GemmArgs& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0) return;
-  dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128));
-  k_gemm_bf16x3_nn<<<grid, 256, 0, s>>>(g);
+void split_bf16(const float* src, int64_t rows, int64_t cols, int64_t ldo, __bf16* hi, __bf16* lo,
+                hipStream_t s) {
+  if (rows <= 0) return;
+  k_split_bf16<<<2048, 256, 0, s>>>(src, rows, cols, ldo, hi, lo);
+}
+
+void split_bf16_transposed(const float* src, int64_t rows, int64_t cols, int64_t ldo, __bf16* hi,
+                           __bf16* lo, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((ldo + 63) / 64));
+  k_split_bf16_t<<<grid, 256, 0, s>>>(src, rows, cols, ldo, hi, lo);
+}
+
+void gemm_bf16x3_nt(const __bf16* Ahi, const __bf16* Alo, int64_t lda, const __bf16* Bhi,
+                    const __bf16* Blo, int64_t ldb, float* C, int64_t ldc, int M, int N, int K,
+                    hipStream_t s) {
+  if (M <= 0 || N <= 0) return;
+  dim3 grid((unsigned)((N + 127) / 128), (unsigned)((M + 127) / 128));
+  k_gemm_bf16x3_nt<<<grid, 256, 0, s>>>(Ahi, Alo, lda, Bhi, Blo, ldb, C, ldc, M, N, K);
 }
 
 }  // namespace ivx
