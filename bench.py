@@ -324,7 +324,7 @@ def main():
     # pass over the frames)
     Kexp = (D + 1) * (D + 2) // 2
     tune_now = ctx.tuning_get()
-    tile = 32 * tune_now["frame_ncb"]
+    tile = 256 if tune_now["frame_ncb"] == 8 else 128
     flop_per_frame_tile = 2.0 * Kexp * tile
     fs_ms, fs_calls = prof["frame_select"]
     fs_avg_s = fs_ms / max(fs_calls, 1) / 1e3
@@ -346,7 +346,7 @@ def main():
         fs16_ms, fs16_calls = prof16["frame_select"]
         fs16_avg_s = fs16_ms / max(fs16_calls, 1) / 1e3
         bf16_peak = 2500.0
-        tile16 = 32 * tune_now["frame_ncb_bf16"]
+        tile16 = 256 if tune_now["frame_ncb_bf16"] == 8 else 128
         # three BF16 products (hi*hi, hi*lo, lo*hi) per FP32 one
         ach16 = 3.0 * 2.0 * Kexp * tile16 * F / fs16_avg_s / 1e12
         log("[bench] BF16 kernel groups (ms per step): " + ", ".join(

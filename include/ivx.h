@@ -317,8 +317,10 @@ ivx_status ivx_selector_counts(ivx_ctx* ctx, int64_t* fallback_frames, int64_t* 
 
 /* Launch shapes of the hot-path kernels.  Every choice computes the same
  * result (up to FP32 summation order in the split GEMM).
- *   frame_ncb       32-component MFMA blocks per launch of the FP32 frame
- *                   GEMM (4 or 8; 8 * 32 = 256 components per launch)
+ *   frame_ncb       launch shape of the FP32 frame GEMM: 8 (256 components
+ *                   per launch, one 32-frame block per wave), 4 (128
+ *                   components) or 2 (128 components, two frame blocks per
+ *                   wave)
  *   frame_ncb_bf16  the same for the BF16 split form
  *   nf_block        components per n/f statistics workgroup (128 or 256)
  *   b_split         K-splits of the linear-term GEMM b = p + F V (0: chosen

@@ -1,6 +1,7 @@
 // Autotuner: times the candidate launch shapes of the hot-path kernels on the
 // caller's workload with HIP events and keeps the fastest in the context.
-//   frame GEMM (FP32 and BF16 forms): 128 or 256 components per launch
+//   frame GEMM (FP32 and BF16 forms): 256 components per launch, or 128
+//   with one or two 32-frame blocks per wave
 //   n/f statistics: 128 or 256 components per workgroup
 //   linear-term GEMM b = p + F V: number of K splits
 #include <cmath>
@@ -20,7 +21,8 @@ namespace {
   } while (0)
 
 bool valid_tuning(const ivx_tuning& t) {
-  return (t.frame_ncb == 4 || t.frame_ncb == 8) && (t.frame_ncb_bf16 == 4 || t.frame_ncb_bf16 == 8) &&
+  auto ncb_ok = [](int v) { return v == 2 || v == 4 || v == 8; };
+  return ncb_ok(t.frame_ncb) && ncb_ok(t.frame_ncb_bf16) &&
          (t.nf_block == 128 || t.nf_block == 256) && t.b_split >= 0 && t.b_split <= 1024;
 }
 
@@ -94,7 +96,7 @@ ivx_status ivx_autotune(ivx_ctx* ctx, const float* X, const int64_t* utt_off, in
   // frame GEMM, both forms
   for (int prec = 0; prec < 2; ++prec) {
     float tb = INFINITY;
-    for (int ncb : {8, 4}) {
+    for (int ncb : {8, 4, 2}) {
       if (prec == IVX_BF16)
         ctx->tune.frame_ncb_bf16 = ncb;
       else

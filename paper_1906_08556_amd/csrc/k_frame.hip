@@ -43,17 +43,111 @@ __device__ inline int compact_cands(int2* __restrict__ lst, float thr) {
   return w;
 }
 
-// One launch per 256-component tile [c0, c0 + 256).  All workgroups of a
-// launch stream the same 1.9 MB slice of W, so it stays resident in every
-// XCD's L2; chunks of 8 expanded features are staged through LDS (double
-// buffered) and shared by the 4 waves.  The per-frame running maximum M, the
-// candidate lists and the overflow flag persist in global memory between
-// launches.
+// Per-frame candidate state of one lane-half, carried between launches in
+// global memory: running maximum M, candidate list (CAPL slots of the
+// lane-half), overflow flag.
+struct FrameState {
+  int64_t g;
+  bool valid;
+  int2* lst;
+  float M;
+  int cnt;
+  bool ov;
+};
+
+__device__ inline void frame_state_load(FrameState& st, int64_t g, int64_t F, int h, int first,
+                                        int2* __restrict__ cand, const float* __restrict__ cM,
+                                        const int* __restrict__ cflag) {
+  st.g = g;
+  st.valid = g < F;
+  st.lst = cand + (st.valid ? g : 0) * KP + h * CAPL;
+  st.M = -INFINITY;
+  st.cnt = 0;
+  st.ov = false;
+  if (st.valid) {
+    if (first) {
+      for (int s = 0; s < CAPL; ++s) st.lst[s] = make_int2(-1, 0);
+    } else {
+      st.M = cM[g];
+      st.ov = cflag[g] != 0;
+      for (int s = 0; s < CAPL; ++s)
+        if (st.lst[s].x >= 0) st.cnt = s + 1;
+    }
+  }
+}
+
+// Epilogue of one 32-frame block: lane holds frame l32 and rows
+// 8*(r/4) + 4*h + r%4 of each 32-component block; its partner lane
+// (lane ^ 32) holds the other rows.  Two unrolled passes with small bodies
+// keep acc[] in registers: count this tile's hits, make room once, store.
+template <int NCB>
+__device__ inline void frame_epilogue(const floatx16 (&acc)[NCB], FrameState& st, int h, int c0,
+                                      int C, float margin, float* __restrict__ cM,
+                                      int* __restrict__ cflag) {
+  float vmax = -INFINITY;
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) vmax = fmaxf(vmax, acc[cb][r]);
+  const float lmax = vmax;
+  vmax = fmaxf(vmax, __shfl_xor(vmax, 32));
+  st.M = fmaxf(st.M, vmax);
+  const float thr = st.M - margin;
+  if (st.valid && lmax >= thr) {
+    int nh = 0;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) nh += (acc[cb][r] >= thr) ? 1 : 0;
+    if (st.cnt + nh > CAPL) st.cnt = compact_cands(st.lst, thr);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float v = acc[cb][r];
+        const int comp = c0 + cb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (v >= thr && comp < C) {
+          if (st.cnt < CAPL) {
+            st.lst[st.cnt] = make_int2(comp, __float_as_int(v));
+            ++st.cnt;
+          } else {
+            st.ov = true;
+          }
+        }
+      }
+  }
+  const int ovi = st.ov ? 1 : 0;
+  const int ovp = __shfl_xor(ovi, 32);
+  if (st.valid && h == 0) {
+    cM[st.g] = st.M;
+    cflag[st.g] = ovi | ovp;
+  }
+}
+
+// Loads the workgroup's frames as x~ = [1, x - shift] rows of DS floats.
+__device__ inline void load_frames(float* xs, int nfr, int DS, const float* __restrict__ X,
+                                   int64_t f0, int64_t F, int D, const float* __restrict__ shift) {
+  for (int i = threadIdx.x; i < nfr * DS; i += 256) {
+    const int fr = i / DS, a = i - fr * DS;
+    const int64_t g = f0 + fr;
+    float v = (a == 0) ? 1.0f : 0.0f;
+    if (a > 0 && g < F) v = X[g * D + (a - 1)] - shift[a - 1];
+    xs[i] = v;
+  }
+}
+
+// One launch per tile of CT = 32 NCB components [c0, c0 + CT); each wave
+// handles FB blocks of 32 frames (FT FB frames per workgroup).  All
+// workgroups of a launch stream the same slice of W, so it stays resident in
+// every XCD's L2; chunks of 8 expanded features are staged through LDS
+// (double buffered) and shared by the 4 waves, and each staged coefficient
+// serves the FB frame blocks of a wave.  The per-frame running maximum,
+// candidate lists and overflow flag persist in global memory between launches.
 //
 // W layout (k_ubm_prepare): chunk-major, coefficient (c, k) at
 // ((k / 8) * Cpad + c) * 8 + k % 8, so a chunk of a tile is contiguous.
-template <int NCB>
-__global__ void __launch_bounds__(256, 2)
+template <int NCB, int FB>
+__global__ void __launch_bounds__(256, FB == 1 ? 2 : 1)
 k_frame_tile(const float* __restrict__ X, int64_t F, int D, const float* __restrict__ shift,
              const float* __restrict__ W, int C, int Cpad, int Kpad,
              const uint16_t* __restrict__ pairs, float margin, int c0, int first,
@@ -62,30 +156,25 @@ k_frame_tile(const float* __restrict__ X, int64_t F, int D, const float* __restr
   constexpr int CT = 32 * NCB;   // components per launch
   constexpr int TPC = 256 / CT;  // threads per staged component
   constexpr int NV = 2 / TPC;    // float4 per thread and chunk
+  constexpr int FTB = FT * FB;   // frames per workgroup
   extern __shared__ float smem[];
   if (Fdev && (int64_t)Fdev[0] < F) F = Fdev[0];
-  if ((int64_t)blockIdx.x * FT >= F) return;  // whole workgroup, before any barrier
+  if ((int64_t)blockIdx.x * FTB >= F) return;  // whole workgroup, before any barrier
   const int DS = D + 1;
   float* Ws = smem;                                              // [2][CT][WLD]
-  float* xs = smem + 2 * CT * WLD;                               // [FT][DS]
-  uint32_t* prs = reinterpret_cast<uint32_t*>(xs + FT * DS);     // [Kpad/2] index pairs
+  float* xs = smem + 2 * CT * WLD;                               // [FTB][DS]
+  uint32_t* prs = reinterpret_cast<uint32_t*>(xs + FTB * DS);    // [Kpad/2] index pairs
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t f0 = (int64_t)blockIdx.x * FT;
+  const int64_t f0 = (int64_t)blockIdx.x * FTB;
   const int nq = Kpad / 8;
 
   for (int i = tid; i < Kpad / 2; i += 256) prs[i] = reinterpret_cast<const uint32_t*>(pairs)[i];
-  for (int i = tid; i < FT * DS; i += 256) {
-    const int fr = i / DS, a = i - fr * DS;
-    const int64_t g = f0 + fr;
-    float v = (a == 0) ? 1.0f : 0.0f;
-    if (a > 0 && g < F) v = X[g * D + (a - 1)] - shift[a - 1];
-    xs[i] = v;
-  }
+  load_frames(xs, FTB, DS, X, f0, F, D, shift);
   // W chunk loader: TPC threads stage the 8 coefficients of one component
-  const int lc = tid / TPC, part = tid % TPC;
   // (named registers, not an array: an array captured by the lambdas ends
   // up in scratch memory)
+  const int lc = tid / TPC, part = tid % TPC;
   float4 r0, r1;
   auto gload = [&](int q) {
     const float4* p =
@@ -102,28 +191,18 @@ k_frame_tile(const float* __restrict__ X, int64_t F, int D, const float* __restr
   sstore(0);
 
   const int h = lane >> 5, l32 = lane & 31;
-  const int64_t g = f0 + wave * FR + l32;
-  const bool valid = g < F;
-  int2* lst = cand + (valid ? g : 0) * KP + h * CAPL;
-  float M = -INFINITY;
-  int cnt = 0;
-  bool ov = false;
-  if (valid) {
-    if (first) {
-      for (int s = 0; s < CAPL; ++s) lst[s] = make_int2(-1, 0);
-    } else {
-      M = cM[g];
-      ov = cflag[g] != 0;
-      for (int s = 0; s < CAPL; ++s)
-        if (lst[s].x >= 0) cnt = s + 1;
-    }
-  }
+  FrameState st[FB];
+#pragma unroll
+  for (int fb = 0; fb < FB; ++fb)
+    frame_state_load(st[fb], f0 + (wave * FB + fb) * FR + l32, F, h, first, cand, cM, cflag);
   __syncthreads();
 
-  floatx16 acc[NCB];
+  floatx16 acc[FB][NCB];
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) acc[cb] = floatx16{0};
-  const float* xw = xs + (wave * FR + l32) * DS;
+  for (int fb = 0; fb < FB; ++fb)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[fb][cb] = floatx16{0};
+  const float* xw = xs + (wave * FB * FR + l32) * DS;
   for (int q = 0; q < nq; ++q) {
     const int cur = q & 1;
     if (q + 1 < nq) gload(q + 1);
@@ -136,58 +215,22 @@ k_frame_tile(const float* __restrict__ X, int64_t F, int D, const float* __restr
     for (int s = 0; s < 4; ++s) {
       const uint32_t pr = ((s < 2) ? pw0 : pw1) >> ((s & 1) * 16);
       const int a = pr & 0xff, b = (pr >> 8) & 0xff;
-      const float bv = xw[a] * xw[b];
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        const float av = (s == 0) ? wv[cb].x : (s == 1) ? wv[cb].y : (s == 2) ? wv[cb].z : wv[cb].w;
-        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[cb], 0, 0, 0);
+      for (int fb = 0; fb < FB; ++fb) {
+        const float* xf = xw + fb * FR * DS;
+        const float bv = xf[a] * xf[b];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const float av = (s == 0) ? wv[cb].x : (s == 1) ? wv[cb].y : (s == 2) ? wv[cb].z : wv[cb].w;
+          acc[fb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[fb][cb], 0, 0, 0);
+        }
       }
     }
     if (q + 1 < nq) sstore(cur ^ 1);
     __syncthreads();
   }
-  // epilogue: lane holds frame l32 and rows 8*(r/4) + 4*h + r%4 of each
-  // 32-component block; its partner lane (lane ^ 32) holds the other rows
-  float vmax = -INFINITY;
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) vmax = fmaxf(vmax, acc[cb][r]);
-  const float lmax = vmax;
-  vmax = fmaxf(vmax, __shfl_xor(vmax, 32));
-  M = fmaxf(M, vmax);
-  const float thr = M - margin;
-  if (valid && lmax >= thr) {
-    // two unrolled passes with small bodies keep acc[] in registers:
-    // count this tile's hits, make room once, then store them
-    int nh = 0;
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) nh += (acc[cb][r] >= thr) ? 1 : 0;
-    if (cnt + nh > CAPL) cnt = compact_cands(lst, thr);
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float v = acc[cb][r];
-        const int comp = c0 + cb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        if (v >= thr && comp < C) {
-          if (cnt < CAPL) {
-            lst[cnt] = make_int2(comp, __float_as_int(v));
-            ++cnt;
-          } else {
-            ov = true;
-          }
-        }
-      }
-  }
-  const int ovi = ov ? 1 : 0;
-  const int ovp = __shfl_xor(ovi, 32);
-  if (valid && h == 0) {
-    cM[g] = M;
-    cflag[g] = ovi | ovp;
-  }
+  for (int fb = 0; fb < FB; ++fb) frame_epilogue<NCB>(acc[fb], st[fb], h, c0, C, margin, cM, cflag);
 }
 
 // ---------------------------------------------------------------- BF16 form
@@ -203,8 +246,8 @@ constexpr int WB16 = 40;  // LDS row stride (bf16) of a staged comp: 16 hi, 16 l
 
 // W16 layout (k_ubm_prepare): [Kpad/16][Cpad][32] bf16, per component 16 hi
 // then 16 lo coefficients of the chunk.
-template <int NCB>
-__global__ void __launch_bounds__(256, 2)
+template <int NCB, int FB>
+__global__ void __launch_bounds__(256, FB == 1 ? 2 : 1)
 k_frame_tile_bf16(const float* __restrict__ X, int64_t F, int D, const float* __restrict__ shift,
                   const __bf16* __restrict__ W16, int C, int Cpad, int Kpad,
                   const uint16_t* __restrict__ pairs, float margin, int c0, int first,
@@ -213,26 +256,21 @@ k_frame_tile_bf16(const float* __restrict__ X, int64_t F, int D, const float* __
   constexpr int CT = 32 * NCB;   // components per launch
   constexpr int TPC = 256 / CT;  // threads per staged component
   constexpr int NV = 4 / TPC;    // uint4 (8 bf16) per thread and chunk
+  constexpr int FTB = FT * FB;   // frames per workgroup
   extern __shared__ float smem[];
   if (Fdev && (int64_t)Fdev[0] < F) F = Fdev[0];
-  if ((int64_t)blockIdx.x * FT >= F) return;  // whole workgroup, before any barrier
+  if ((int64_t)blockIdx.x * FTB >= F) return;  // whole workgroup, before any barrier
   const int DS = D + 1;
   __bf16* Ws = reinterpret_cast<__bf16*>(smem);                  // [2][CT][WB16]
-  float* xs = smem + (2 * CT * WB16) / 2;                         // [FT][DS]
-  uint32_t* prs = reinterpret_cast<uint32_t*>(xs + FT * DS);      // [Kpad/2]
+  float* xs = smem + (2 * CT * WB16) / 2;                         // [FTB][DS]
+  uint32_t* prs = reinterpret_cast<uint32_t*>(xs + FTB * DS);     // [Kpad/2]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t f0 = (int64_t)blockIdx.x * FT;
+  const int64_t f0 = (int64_t)blockIdx.x * FTB;
   const int nq = Kpad / 16;
 
   for (int i = tid; i < Kpad / 2; i += 256) prs[i] = reinterpret_cast<const uint32_t*>(pairs)[i];
-  for (int i = tid; i < FT * DS; i += 256) {
-    const int fr = i / DS, a = i - fr * DS;
-    const int64_t g = f0 + fr;
-    float v = (a == 0) ? 1.0f : 0.0f;
-    if (a > 0 && g < F) v = X[g * D + (a - 1)] - shift[a - 1];
-    xs[i] = v;
-  }
+  load_frames(xs, FTB, DS, X, f0, F, D, shift);
   // chunk loader: TPC threads stage the 32 bf16 (64 B) of one component
   const int lc = tid / TPC, part = tid % TPC;
   uint4 r0, r1, r2, r3;  // named registers (see k_frame_tile)
@@ -259,42 +297,36 @@ k_frame_tile_bf16(const float* __restrict__ X, int64_t F, int D, const float* __
   sstore(0);
 
   const int h = lane >> 5, l32 = lane & 31;
-  const int64_t g = f0 + wave * FR + l32;
-  const bool valid = g < F;
-  int2* lst = cand + (valid ? g : 0) * KP + h * CAPL;
-  float M = -INFINITY;
-  int cnt = 0;
-  bool ov = false;
-  if (valid) {
-    if (first) {
-      for (int s = 0; s < CAPL; ++s) lst[s] = make_int2(-1, 0);
-    } else {
-      M = cM[g];
-      ov = cflag[g] != 0;
-      for (int s = 0; s < CAPL; ++s)
-        if (lst[s].x >= 0) cnt = s + 1;
-    }
-  }
+  FrameState st[FB];
+#pragma unroll
+  for (int fb = 0; fb < FB; ++fb)
+    frame_state_load(st[fb], f0 + (wave * FB + fb) * FR + l32, F, h, first, cand, cM, cflag);
   __syncthreads();
 
-  floatx16 acc[NCB];
+  floatx16 acc[FB][NCB];
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) acc[cb] = floatx16{0};
-  const float* xw = xs + (wave * FR + l32) * DS;
+  for (int fb = 0; fb < FB; ++fb)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[fb][cb] = floatx16{0};
+  const float* xw = xs + (wave * FB * FR + l32) * DS;
   for (int q = 0; q < nq; ++q) {
     const int cur = q & 1;
     if (q + 1 < nq) gload(q + 1);
     // B operand: products for k = 16 q + 8 h + e, e = 0..7, split hi / lo
     const uint4 pw = *reinterpret_cast<const uint4*>(prs + 8 * q + 4 * h);
-    bf16x8 bh, bl;
+    bf16x8 bh[FB], bl[FB];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const uint32_t w32 = (e < 2) ? pw.x : (e < 4) ? pw.y : (e < 6) ? pw.z : pw.w;
-      const uint32_t pr = w32 >> ((e & 1) * 16);
-      const float v = xw[pr & 0xff] * xw[(pr >> 8) & 0xff];
-      const __bf16 hi = (__bf16)v;
-      bh[e] = hi;
-      bl[e] = (__bf16)(v - (float)hi);
+    for (int fb = 0; fb < FB; ++fb) {
+      const float* xf = xw + fb * FR * DS;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t w32 = (e < 2) ? pw.x : (e < 4) ? pw.y : (e < 6) ? pw.z : pw.w;
+        const uint32_t pr = w32 >> ((e & 1) * 16);
+        const float v = xf[pr & 0xff] * xf[(pr >> 8) & 0xff];
+        const __bf16 hi = (__bf16)v;
+        bh[fb][e] = hi;
+        bl[fb][e] = (__bf16)(v - (float)hi);
+      }
     }
     const __bf16* wb = Ws + (cur * CT + l32) * WB16 + 8 * h;
     bf16x8 wh[NCB], wl[NCB];
@@ -304,55 +336,22 @@ k_frame_tile_bf16(const float* __restrict__ X, int64_t F, int D, const float* __
       wl[cb] = *reinterpret_cast<const bf16x8*>(wb + cb * 32 * WB16 + 16);
     }
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-      acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[cb], bh, acc[cb], 0, 0, 0);
+    for (int fb = 0; fb < FB; ++fb) {
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-      acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[cb], bl, acc[cb], 0, 0, 0);
+      for (int cb = 0; cb < NCB; ++cb)
+        acc[fb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[cb], bh[fb], acc[fb][cb], 0, 0, 0);
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-      acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl[cb], bh, acc[cb], 0, 0, 0);
+      for (int cb = 0; cb < NCB; ++cb)
+        acc[fb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[cb], bl[fb], acc[fb][cb], 0, 0, 0);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        acc[fb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl[cb], bh[fb], acc[fb][cb], 0, 0, 0);
+    }
     if (q + 1 < nq) sstore(cur ^ 1);
     __syncthreads();
   }
-  float vmax = -INFINITY;
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) vmax = fmaxf(vmax, acc[cb][r]);
-  const float lmax = vmax;
-  vmax = fmaxf(vmax, __shfl_xor(vmax, 32));
-  M = fmaxf(M, vmax);
-  const float thr = M - margin;
-  if (valid && lmax >= thr) {
-    int nh = 0;
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) nh += (acc[cb][r] >= thr) ? 1 : 0;
-    if (cnt + nh > CAPL) cnt = compact_cands(lst, thr);
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float v = acc[cb][r];
-        const int comp = c0 + cb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        if (v >= thr && comp < C) {
-          if (cnt < CAPL) {
-            lst[cnt] = make_int2(comp, __float_as_int(v));
-            ++cnt;
-          } else {
-            ov = true;
-          }
-        }
-      }
-  }
-  const int ovi = ov ? 1 : 0;
-  const int ovp = __shfl_xor(ovi, 32);
-  if (valid && h == 0) {
-    cM[g] = M;
-    cflag[g] = ovi | ovp;
-  }
+  for (int fb = 0; fb < FB; ++fb) frame_epilogue<NCB>(acc[fb], st[fb], h, c0, C, margin, cM, cflag);
 }
 
 __global__ void __launch_bounds__(256)
@@ -459,39 +458,39 @@ __global__ void k_scatter_gamma(int64_t F, int C, const int* __restrict__ post_i
   if (c >= 0) gamma[(i / KP) * C + c] = post_val[i];
 }
 
-template <int NCB>
+template <int NCB, int FB>
 size_t frame_lds_bf16(int D, int Kpad) {
-  return sizeof(__bf16) * 2 * (32 * NCB) * WB16 + sizeof(float) * (size_t)FT * (D + 1) +
+  return sizeof(__bf16) * 2 * (32 * NCB) * WB16 + sizeof(float) * (size_t)FT * FB * (D + 1) +
          sizeof(uint16_t) * Kpad;
 }
-template <int NCB>
+template <int NCB, int FB>
 size_t frame_lds_f32(int D, int Kpad) {
-  return sizeof(float) * (2 * (32 * NCB) * WLD + (size_t)FT * (D + 1)) + sizeof(uint16_t) * Kpad;
+  return sizeof(float) * (2 * (32 * NCB) * WLD + (size_t)FT * FB * (D + 1)) +
+         sizeof(uint16_t) * Kpad;
 }
 
-template <int NCB>
+template <int NCB, int FB>
 void frame_launches(ivx_ctx* ctx, const float* X, int64_t F, int prec, hipStream_t s,
                     const int* Fdev) {
   constexpr int CT = 32 * NCB;
-  const unsigned nblk = (unsigned)((F + FT - 1) / FT);
+  const unsigned nblk = (unsigned)((F + FT * FB - 1) / (FT * FB));
   if (prec == IVX_BF16) {
-    const size_t lds = frame_lds_bf16<NCB>(ctx->D, ctx->Kpad);
+    const size_t lds = frame_lds_bf16<NCB, FB>(ctx->D, ctx->Kpad);
     for (int c0 = 0; c0 < ctx->Cpad; c0 += CT) {
       ProfScope ps(ctx, PK_FRAME_SELECT, s);
-      k_frame_tile_bf16<NCB><<<nblk, 256, lds, s>>>(X, F, ctx->D, ctx->shift, ctx->W16, ctx->C,
-                                                    ctx->Cpad, ctx->Kpad, ctx->pairs,
-                                                    ctx->margin_bf16, c0, c0 == 0 ? 1 : 0,
-                                                    ctx->cand, ctx->cM, ctx->cflag, Fdev);
+      k_frame_tile_bf16<NCB, FB><<<nblk, 256, lds, s>>>(
+          X, F, ctx->D, ctx->shift, ctx->W16, ctx->C, ctx->Cpad, ctx->Kpad, ctx->pairs,
+          ctx->margin_bf16, c0, c0 == 0 ? 1 : 0, ctx->cand, ctx->cM, ctx->cflag, Fdev);
     }
     return;
   }
-  const size_t lds = frame_lds_f32<NCB>(ctx->D, ctx->Kpad);
+  const size_t lds = frame_lds_f32<NCB, FB>(ctx->D, ctx->Kpad);
   for (int c0 = 0; c0 < ctx->Cpad; c0 += CT) {
     ProfScope ps(ctx, PK_FRAME_SELECT, s);
-    k_frame_tile<NCB><<<nblk, 256, lds, s>>>(X, F, ctx->D, ctx->shift, ctx->Wexp, ctx->C,
-                                             ctx->Cpad, ctx->Kpad, ctx->pairs, ctx->margin, c0,
-                                             c0 == 0 ? 1 : 0, ctx->cand, ctx->cM, ctx->cflag,
-                                             Fdev);
+    k_frame_tile<NCB, FB><<<nblk, 256, lds, s>>>(X, F, ctx->D, ctx->shift, ctx->Wexp, ctx->C,
+                                                 ctx->Cpad, ctx->Kpad, ctx->pairs, ctx->margin,
+                                                 c0, c0 == 0 ? 1 : 0, ctx->cand, ctx->cM,
+                                                 ctx->cflag, Fdev);
   }
 }
 
@@ -505,21 +504,28 @@ bool frame_set_attributes(const ivx_ctx* ctx) {
     ok = ok && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
                    hipSuccess;
   };
-  set(reinterpret_cast<const void*>(&k_frame_tile_bf16<8>), frame_lds_bf16<8>(ctx->D, ctx->Kpad));
-  set(reinterpret_cast<const void*>(&k_frame_tile_bf16<4>), frame_lds_bf16<4>(ctx->D, ctx->Kpad));
-  set(reinterpret_cast<const void*>(&k_frame_tile<8>), frame_lds_f32<8>(ctx->D, ctx->Kpad));
-  set(reinterpret_cast<const void*>(&k_frame_tile<4>), frame_lds_f32<4>(ctx->D, ctx->Kpad));
+  const int D = ctx->D, Kp = ctx->Kpad;
+  set(reinterpret_cast<const void*>(&k_frame_tile_bf16<8, 1>), frame_lds_bf16<8, 1>(D, Kp));
+  set(reinterpret_cast<const void*>(&k_frame_tile_bf16<4, 1>), frame_lds_bf16<4, 1>(D, Kp));
+  set(reinterpret_cast<const void*>(&k_frame_tile_bf16<4, 2>), frame_lds_bf16<4, 2>(D, Kp));
+  set(reinterpret_cast<const void*>(&k_frame_tile<8, 1>), frame_lds_f32<8, 1>(D, Kp));
+  set(reinterpret_cast<const void*>(&k_frame_tile<4, 1>), frame_lds_f32<4, 1>(D, Kp));
+  set(reinterpret_cast<const void*>(&k_frame_tile<4, 2>), frame_lds_f32<4, 2>(D, Kp));
   return ok;
 }
 
 void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, int prec, hipStream_t s,
                          const int* Fdev) {
   if (F <= 0) return;
+  // frame_ncb: 8 (256 components per launch, one 32-frame block per wave),
+  // 4 (128 components), or 2 (128 components, two frame blocks per wave)
   const int ncb = (prec == IVX_BF16) ? ctx->tune.frame_ncb_bf16 : ctx->tune.frame_ncb;
   if (ncb == 4)
-    frame_launches<4>(ctx, X, F, prec, s, Fdev);
+    frame_launches<4, 1>(ctx, X, F, prec, s, Fdev);
+  else if (ncb == 2)
+    frame_launches<4, 2>(ctx, X, F, prec, s, Fdev);
   else
-    frame_launches<8>(ctx, X, F, prec, s, Fdev);
+    frame_launches<8, 1>(ctx, X, F, prec, s, Fdev);
 }
 
 void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int prec, int* post_idx,

@@ -167,46 +167,69 @@ k_mlp_nt(const float* __restrict__ X, int D, const float* __restrict__ mean,
   }
 }
 
-// z = W3 h2 + b3 chunk by chunk, with a running top-k and log-sum-exp per
-// frame.  Thread t scans frame t % 128 over the half (t / 128) of each chunk;
-// the two halves' lists are merged at the end.  Writes for frame g = row0 + f:
-// prop[g][0..k) (largest first, ties to the lower index), mass[g] =
-// sum over the proposals of softmax(z), fb[g] = mass < min_mass, and appends
-// fallback frames to fb_list (counters[0]); counters[1] += k per kept frame.
-// Zout (optional) receives z [rows][C].
+// z = W3 h2 + b3 chunk by chunk (128 components), with a running top-KM and
+// log-sum-exp per frame.  The components are the MFMA's M operand and the
+// frames its N operand, so lane (wave wm, wn; half h; l32) ends every chunk
+// holding, for its frames f_j = wn*64 + j*32 + l32 (j = 0, 1), the 32 logits
+// of components wm*64 + i*32 + 8*(r/4) + 4h + r%4 (i = 0, 1; r = 0..15), in
+// increasing component order.  Each of a frame's four holders (wm, h) keeps
+// a sorted top-KM list of its own components in registers (a logit enters
+// only above the holder's current KM-th, so after the first chunks inserts
+// are rare; equal logits keep the lower component first) and an online
+// log-sum-exp.  At the end the four lists go to LDS and every entry's rank
+// in the union is counted; ranks below k give the proposals.
+// Writes for frame g = row0 + m0 + f: prop[g][0..k) (largest first, ties to
+// the lower index), mass[g] = sum over the proposals of softmax(z), fb[g] =
+// mass < min_mass, and appends fallback frames to fb_list (counters[0]);
+// counters[1] += k per kept frame.  Zout (optional) receives z [rows][C].
+template <int KM>
 __global__ void __launch_bounds__(256)
 k_mlp_l3(const __bf16* __restrict__ H2, int64_t rows, int64_t row0, int K,
          const __bf16* __restrict__ W3, const float* __restrict__ b3, int C, int Cpad, int k,
          float min_mass, int* __restrict__ prop, float* __restrict__ mass, int* __restrict__ fb,
          int* __restrict__ fb_list, int* __restrict__ counters, float* __restrict__ Zout) {
   extern __shared__ float smem[];
-  // region 0 (reused): GEMM stages [2][MT*LDK] + [2][NT*LDK] bf16, or the
-  // logit chunk [MT][ZS] floats
-  float* Zs = smem;
+  // GEMM stages (bf16): [2][128 * LDK] components, then [2][128 * LDK] frames;
+  // after the last chunk the same memory holds the lists [4][128][KM]
   __bf16* As0 = reinterpret_cast<__bf16*>(smem);
-  __bf16* Bs0 = As0 + 2 * MT * LDK;
-  float* lz = smem + MT * ZS;                                // [k][256]
-  int* lc = reinterpret_cast<int*>(lz + k * 256);            // [k][256]
-  float* xm = reinterpret_cast<float*>(lc + k * 256);        // [256] running max
-  float* xs = xm + 256;                                      // [256] running sum
-  int* xn = reinterpret_cast<int*>(xs + 256);                // [256] list length
-  int* wg = xn + 256;                                        // [2] fallback count, base
-  const int tid = threadIdx.x;
-  const int64_t m0 = (int64_t)blockIdx.x * MT;
-  const int f = tid & (MT - 1), half = tid >> 7;
-  const bool frow = m0 + f < rows;
-  float run_m = -INFINITY, run_s = 0.0f, thr = -INFINITY;
-  int n = 0;
-  if (tid == 0) wg[0] = 0;
-
-  const int lane = tid & 63, wave = tid >> 6;
+  __bf16* Bs0 = As0 + 2 * NT * LDK;
+  float* lvs = smem;                                          // [4][MT][KM]
+  int* lis = reinterpret_cast<int*>(lvs + 4 * MT * KM);       // [4][MT][KM]
+  float* lse_p = reinterpret_cast<float*>(lis + 4 * MT * KM); // [4][MT][2] (max, sum)
+  float* mpart = lse_p + 4 * MT * 2;                          // [4][MT]
+  int* wg = reinterpret_cast<int*>(mpart + 4 * MT);           // [2]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1, h = lane >> 5, l32 = lane & 31;
+  const int64_t m0 = (int64_t)blockIdx.x * MT;
+  float lv[2][KM];
+  int li[2][KM];
+  float rm[2], rs[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    rm[j] = -INFINITY;
+    rs[j] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) {
+      lv[j][q] = -INFINITY;
+      li[j][q] = -1;
+    }
+  }
   const int nk = K / KT;
   for (int c0 = 0; c0 < Cpad; c0 += NT) {
+    // biases of this lane's 32 components of the chunk, loaded before the K
+    // loop so that their latency hides behind it (padding components: -inf)
+    float bb[2][16];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int c = c0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        bb[i][r] = (c < C) ? b3[c] : -INFINITY;
+      }
     RowLoader la, lb;
     auto load = [&](int kk) {
-      la.load_bf16(H2, K, m0, rows, kk);
-      lb.load_bf16(W3, K, c0, Cpad, kk);
+      la.load_bf16(W3, K, c0, Cpad, kk);
+      lb.load_bf16(H2, K, m0, rows, kk);
     };
     floatx16 acc[2][2];
 #pragma unroll
@@ -220,111 +243,149 @@ k_mlp_l3(const __bf16* __restrict__ H2, int64_t rows, int64_t row0, int K,
     for (int it = 0; it < nk; ++it) {
       const int cur = it & 1;
       if (it + 1 < nk) load((it + 1) * KT);
-      mma_stage(As0 + cur * MT * LDK, Bs0 + cur * NT * LDK, acc);
+      mma_stage(As0 + cur * NT * LDK, Bs0 + cur * MT * LDK, acc);
       if (it + 1 < nk) {
-        la.store(As0 + (cur ^ 1) * MT * LDK);
-        lb.store(Bs0 + (cur ^ 1) * NT * LDK);
+        la.store(As0 + (cur ^ 1) * NT * LDK);
+        lb.store(Bs0 + (cur ^ 1) * MT * LDK);
       }
       __syncthreads();
     }
-    // logits of the chunk to LDS (padding components: -inf)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int nl = wn * 64 + j * 32 + l32;
-      const int c = c0 + nl;
-      const float bc = (c < C) ? b3[c] : 0.0f;
+      const int64_t fr = m0 + wn * 64 + j * 32 + l32;
+      if (fr >= rows) continue;
+      // the chunk's 32 logits of this holder; log-sum-exp rescaled once
+      float vv[2][16];
+      float cmax = -INFINITY;
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int ml = wm * 64 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-          const float v = (c < C) ? acc[i][j][r] + bc : -INFINITY;
-          Zs[ml * ZS + nl] = v;
-          if (Zout && c < C && m0 + ml < rows) Zout[(m0 + ml) * C + c] = v;
+          vv[i][r] = acc[i][j][r] + bb[i][r];
+          cmax = fmaxf(cmax, vv[i][r]);
         }
-    }
-    __syncthreads();
-    if (frow) {
-      const float* zr = Zs + f * ZS + half * 64;
-      const int cb = c0 + half * 64;
-      const int ne = min(64, C - cb);
-      for (int e = 0; e < ne; ++e) {
-        const float v = zr[e];
-        if (v > run_m) {
-          run_s = run_s * __expf(run_m - v) + 1.0f;
-          run_m = v;
-        } else {
-          run_s += __expf(v - run_m);
-        }
-        if (n < k || v > thr) {
-          int pos = (n < k) ? n : k - 1;
-          while (pos > 0) {
-            const float pz = lz[(pos - 1) * 256 + tid];
-            if (pz >= v) break;
-            lz[pos * 256 + tid] = pz;
-            lc[pos * 256 + tid] = lc[(pos - 1) * 256 + tid];
-            --pos;
+      if (Zout) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int c = c0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+            if (c < C) Zout[fr * C + c] = vv[i][r];
           }
-          lz[pos * 256 + tid] = v;
-          lc[pos * 256 + tid] = cb + e;
-          if (n < k) ++n;
-          thr = (n == k) ? lz[(k - 1) * 256 + tid] : -INFINITY;
+      }
+      if (cmax > -INFINITY) {
+        const float nm = fmaxf(rm[j], cmax);
+        float add = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) add += __expf(vv[i][r] - nm);
+        rs[j] = rs[j] * __expf(rm[j] - nm) + add;
+        rm[j] = nm;
+      }
+      // only a chunk whose best logit beats the holder's KM-th can change
+      // the list
+      if (cmax > lv[j][KM - 1]) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const float v = vv[i][r];
+            const int c = c0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+            if (v > lv[j][KM - 1]) {
+              // compare-shift insert; every comparison reads the old list
+#pragma unroll
+              for (int q = KM - 1; q > 0; --q) {
+                // values, not addresses, are selected (a select between two
+                // array addresses would move the lists to scratch memory)
+                const float vp = lv[j][q - 1], vq = lv[j][q];
+                const int ip = li[j][q - 1], iq = li[j][q];
+                const bool up = v > vp;
+                const bool at = v > vq;
+                lv[j][q] = up ? vp : (at ? v : vq);
+                li[j][q] = up ? ip : (at ? c : iq);
+              }
+              if (v > lv[j][0]) {
+                lv[j][0] = v;
+                li[j][0] = c;
+              }
+            }
+          }
+      }
+    }
+  }
+  // lists and log-sum-exp partials of the four holders to LDS (the GEMM
+  // stages are dead: the loop ended with a barrier)
+  const int hold = wm * 2 + h;
+  if (tid == 0) wg[0] = 0;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int f = wn * 64 + j * 32 + l32;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) {
+      lvs[(hold * MT + f) * KM + q] = lv[j][q];
+      lis[(hold * MT + f) * KM + q] = li[j][q];
+    }
+    lse_p[(hold * MT + f) * 2] = rm[j];
+    lse_p[(hold * MT + f) * 2 + 1] = rs[j];
+  }
+  __syncthreads();
+  // rank of each own entry among the four lists; entries ranked below k are
+  // the proposals
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int f = wn * 64 + j * 32 + l32;
+    const int64_t fr = m0 + f;
+    float M = -INFINITY;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) M = fmaxf(M, lse_p[(o * MT + f) * 2]);
+    float S = 0.0f;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      const float mo = lse_p[(o * MT + f) * 2], so = lse_p[(o * MT + f) * 2 + 1];
+      if (so > 0.0f) S += so * __expf(mo - M);
+    }
+    const float lse = M + __logf(S);
+    float ms = 0.0f;
+    if (fr < rows) {
+#pragma unroll
+      for (int q = 0; q < KM; ++q) {
+        const float v = lv[j][q];
+        const int c = li[j][q];
+        if (c < 0) continue;  // list shorter than KM (fewer components)
+        int rank = q;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+          if (o == hold) continue;
+          const float* ov = lvs + (o * MT + f) * KM;
+          const int* oi = lis + (o * MT + f) * KM;
+          for (int p = 0; p < KM; ++p) {
+            const int oc = oi[p];
+            if (oc < 0) break;
+            const float ow = ov[p];
+            if (ow > v || (ow == v && oc < c))
+              ++rank;
+            else
+              break;  // the other list is sorted: no later entry beats v
+          }
+        }
+        if (rank < k) {
+          prop[(row0 + fr) * k + rank] = c;
+          ms += __expf(v - lse);
         }
       }
     }
-    __syncthreads();  // the next chunk's stages overwrite Zs
+    mpart[hold * MT + f] = ms;
   }
-  xm[tid] = run_m;
-  xs[tid] = run_s;
-  xn[tid] = n;
   __syncthreads();
   int local = -1;
-  int64_t g = m0 + f;
-  if (half == 0 && frow) {
-    const int o = tid + 128;
-    const int na = n, nb = xn[o];
-    const float mb = xm[o], sb = xs[o];
-    const float M = fmaxf(run_m, mb);
-    const float S = run_s * __expf(run_m - M) + sb * __expf(mb - M);
-    const float lse = M + __logf(S);
-    int ia = 0, ib = 0;
-    float ms = 0.0f;
-    int outc[32];
-#pragma unroll
-    for (int s = 0; s < 32; ++s) {
-      if (s >= k) break;
-      if (ia >= na && ib >= nb) {  // fewer than k components in all
-        outc[s] = -1;
-        continue;
-      }
-      bool takeA;
-      if (ia >= na) {
-        takeA = false;
-      } else if (ib >= nb) {
-        takeA = true;
-      } else {
-        const float za = lz[ia * 256 + tid], zb = lz[ib * 256 + o];
-        const int ca = lc[ia * 256 + tid], cbb = lc[ib * 256 + o];
-        takeA = (za > zb) || (za == zb && ca < cbb);
-      }
-      float zv;
-      if (takeA) {
-        zv = lz[ia * 256 + tid];
-        outc[s] = lc[ia * 256 + tid];
-        ++ia;
-      } else {
-        zv = lz[ib * 256 + o];
-        outc[s] = lc[ib * 256 + o];
-        ++ib;
-      }
-      ms += __expf(zv - lse);
-    }
-#pragma unroll
-    for (int s = 0; s < 32; ++s)
-      if (s < k) prop[(row0 + g) * k + s] = outc[s];
-    mass[row0 + g] = ms;
+  if (tid < MT && m0 + tid < rows) {
+    const int f = tid;
+    const float ms = mpart[f] + mpart[MT + f] + mpart[2 * MT + f] + mpart[3 * MT + f];
+    const int64_t g = row0 + m0 + f;
+    mass[g] = ms;
     const bool isfb = !(ms >= min_mass);
-    fb[row0 + g] = isfb ? 1 : 0;
+    fb[g] = isfb ? 1 : 0;
     if (isfb) local = atomicAdd(&wg[0], 1);
   }
   __syncthreads();
@@ -335,7 +396,7 @@ k_mlp_l3(const __bf16* __restrict__ H2, int64_t rows, int64_t row0, int K,
     atomicAdd(&counters[1], (nrow - nfb) * k);
   }
   __syncthreads();
-  if (local >= 0) fb_list[wg[1] + local] = (int)(row0 + g);
+  if (local >= 0) fb_list[wg[1] + local] = (int)(row0 + m0 + tid);
 }
 
 // hist[b][c]: proposals of component c among the kept frames of block b
@@ -703,18 +764,28 @@ __global__ void k_inv_std(const float* __restrict__ stdv, int D, float* __restri
   }
 }
 
-size_t l3_lds_bytes(int k) {
-  const size_t region = std::max(sizeof(float) * MT * ZS,
-                                 sizeof(__bf16) * 2 * (MT + NT) * LDK);
-  return region + sizeof(float) * 2 * k * 256 + sizeof(float) * 3 * 256 + 2 * sizeof(int);
+size_t l3_lds_bytes(int km) {
+  const size_t stages = sizeof(__bf16) * 2 * (MT + NT) * LDK;
+  const size_t lists = sizeof(float) * 4 * MT * km * 2 + sizeof(float) * 4 * MT * 3 + 2 * sizeof(int);
+  return std::max(stages, lists);
 }
+
+int l3_km(int k) { return k <= 8 ? 8 : (k <= 20 ? 20 : 32); }
 
 }  // namespace
 
 bool select_set_attributes() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_l3),
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)l3_lds_bytes(kMaxProposals)) == hipSuccess;
+  bool ok = true;
+  ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_l3<8>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)l3_lds_bytes(8)) == hipSuccess;
+  ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_l3<20>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)l3_lds_bytes(20)) == hipSuccess;
+  ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_l3<32>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)l3_lds_bytes(32)) == hipSuccess;
+  return ok;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -751,10 +822,19 @@ void launch_selector_mlp(ivx_ctx* ctx, const float* X, int64_t F, uint16_t* h1_o
       k_mlp_nt<false><<<dim3(S.H2 / NT, mb), 256, 0, s>>>(nullptr, ctx->D, nullptr, nullptr,
                                                           S.h1b, rows, S.H1, S.W2b,
                                                           S.param + S.ob2, S.H2, S.h2b);
-      k_mlp_l3<<<mb, 256, l3_lds_bytes(S.k), s>>>(S.h2b, rows, r0, S.H2, S.W3b, S.b3p, ctx->C,
-                                                   ctx->Cpad, S.k, S.min_mass, S.prop, S.mass,
-                                                   S.fb, S.fb_list, S.counters,
-                                                   z_out ? z_out + r0 * ctx->C : nullptr);
+      const int km = l3_km(S.k);
+      float* zo = z_out ? z_out + r0 * ctx->C : nullptr;
+#define IVX_L3(KMV)                                                                          \
+  k_mlp_l3<KMV><<<mb, 256, l3_lds_bytes(KMV), s>>>(S.h2b, rows, r0, S.H2, S.W3b, S.b3p, ctx->C, \
+                                                   ctx->Cpad, S.k, S.min_mass, S.prop, S.mass, \
+                                                   S.fb, S.fb_list, S.counters, zo)
+      if (km == 8)
+        IVX_L3(8);
+      else if (km == 20)
+        IVX_L3(20);
+      else
+        IVX_L3(32);
+#undef IVX_L3
     }
     if (h1_out)
       hipMemcpyAsync(h1_out + r0 * S.H1, S.h1b, sizeof(uint16_t) * rows * S.H1,

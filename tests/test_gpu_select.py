@@ -302,3 +302,77 @@ def test_out_of_range_training_frame_is_reported():
     with pytest.raises(ivx.IvxError, match="EINVAL"):
         ctx.sync_status()
 
+
+
+def test_trained_selector_gains_over_the_untrained_one():
+    """Trains the selector on the GPU, by the library's own forward and
+    backward kernels, on exact all-component posteriors of 500 utterances of
+    the shape-6 workload (frames near their components), and evaluates it on
+    100 held-out utterances against the untrained network and against the
+    plain all-component form: how many frames leave the all-component path,
+    how much exact-posterior mass the kept frames' proposals miss, how much
+    scoring work remains, and how far the i-vectors move.  Correctness never
+    depends on the network (fallback frames are exact, kept frames are exact
+    over their proposals); the gain does."""
+    from paper_1906_08556_amd import ivx
+    wl = synth.make(6, n_utts=600)
+    C, D, R = wl.shape.C, wl.shape.D, wl.shape.R
+    ctx = make_ctx(wl)
+    ctx.init_tv(dev(wl.T_init))
+    X = dev(wl.X)
+    F = wl.F
+    Utr = 500
+    Ftr = int(wl.utt_off[Utr])
+    Fe = F - Ftr
+    pi = torch.empty((F, 16), dtype=torch.int32, device="cuda")
+    pv = torch.empty((F, 16), dtype=torch.float32, device="cuda")
+    ctx.ubm_posteriors(X, post_idx=pi, post_val=pv)
+    mean, std = ctx.feature_stats(X[:Ftr])
+    B = 4096
+    ctx.selector_set(dev(synth.mlp_init(D, H1, H2, C, seed=0)), mean, std, H1=H1, H2=H2, k=K,
+                     min_mass=0.99, max_train_batch=B)
+    Xe, off_e = X[Ftr:], dev(wl.utt_off[Utr:] - wl.utt_off[Utr])
+    g_all = _dense_from_lists(pi[Ftr:].cpu().numpy(), pv[Ftr:].cpu().numpy(), C)
+
+    def evaluate():
+        mass = torch.empty(Fe, dtype=torch.float32, device="cuda")
+        prop = torch.empty((Fe, K), dtype=torch.int32, device="cuda")
+        ctx.selector_forward(Xe, prop=prop, mass=mass)
+        miss = 1.0 - np.take_along_axis(g_all, prop.cpu().numpy().astype(np.int64), 1).sum(1)
+        fb = mass.cpu().numpy() < 0.99
+        return fb, miss
+
+    fb0, _ = evaluate()
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    losses = []
+    steps = 3000
+    for step in range(steps):
+        fidx = dev(synth.sample_frames(Ftr, B, seed=step))
+        ctx.selector_train_step(X, fidx, pi, pv, 1e-3 if step < 0.7 * steps else 3e-4, loss=loss)
+        if step % 500 == 0 or step == steps - 1:
+            losses.append(loss.item())
+    ctx.sync_status()
+    fb1, miss = evaluate()
+    ctx.extract_ivectors(Xe, off_e, torch.empty((wl.U - Utr, R), dtype=torch.float32,
+                                                device="cuda"), sel=ivx.IVX_SEL_LEARNED)
+    nfb, pairs = ctx.selector_counts()
+    phi_a = torch.empty((wl.U - Utr, R), dtype=torch.float32, device="cuda")
+    phi_l = torch.empty_like(phi_a)
+    ctx.extract_ivectors(Xe, off_e, phi_a)
+    ctx.extract_ivectors(Xe, off_e, phi_l, sel=ivx.IVX_SEL_LEARNED)
+    ctx.sync_status()
+    a, b = phi_a.cpu().numpy().astype(np.float64), phi_l.cpu().numpy().astype(np.float64)
+    cos = np.sum(a * b, 1) / np.linalg.norm(a, axis=1) / np.linalg.norm(b, axis=1)
+    # scoring work per frame relative to all components: network + proposals
+    # of kept frames + all components for fallback frames (FLOP counts)
+    work = (Fe * 2.683e6 + pairs * 3.7e3 + nfb * 7.746e6) / (Fe * 7.746e6)
+    kept = ~fb1
+    print(f"losses {['%.3f' % v for v in losses]}")
+    print(f"fallback untrained {fb0.mean():.3f} trained {fb1.mean():.3f}; kept-frame missed "
+          f"mass mean {miss[kept].mean():.3e}, median {np.median(miss[kept]):.2e}; "
+          f"work vs all components {work:.3f}; i-vector cosine min {cos.min():.6f} "
+          f"median {np.median(cos):.8f}")
+    assert losses[-1] < 0.25 * losses[0]
+    assert fb0.mean() >= 0.99
+    assert fb1.mean() <= 0.8
+    assert work < 1.0

@@ -45,7 +45,7 @@ def test_autotune_returns_a_valid_tuning(setup):
     ivx, wl, ctx, X, off = setup
     t = ctx.autotune(X, off)
     print("tuning", t)
-    assert t["frame_ncb"] in (4, 8) and t["frame_ncb_bf16"] in (4, 8)
+    assert t["frame_ncb"] in (2, 4, 8) and t["frame_ncb_bf16"] in (2, 4, 8)
     assert t["nf_block"] in (128, 256) and t["b_split"] >= 1
     assert ctx.tuning_get() == t
 
@@ -55,8 +55,8 @@ def test_every_launch_shape_gives_the_same_results(setup, prec):
     ivx, wl, ctx, X, off = setup
     ctx.tuning_set(frame_ncb=8, frame_ncb_bf16=8, nf_block=256, b_split=0)
     ref = _run(ctx, wl, X, off, prec)
-    for kw in (dict(frame_ncb=4, frame_ncb_bf16=4), dict(nf_block=128), dict(b_split=1),
-               dict(b_split=16)):
+    for kw in (dict(frame_ncb=4, frame_ncb_bf16=4), dict(frame_ncb=2, frame_ncb_bf16=2),
+               dict(nf_block=128), dict(b_split=1), dict(b_split=16)):
         ctx.tuning_set(**kw)
         out = _run(ctx, wl, X, off, prec)
         np.testing.assert_array_equal(out[0], ref[0])
