@@ -1,9 +1,10 @@
 // Dense FP32 GEMM on MFMA (v_mfma_f32_32x32x2_f32) for the E-step and M-step
 // contractions: C = op(A) op(B), M x N x K.
 //
-//  * 128 x 128 output tile per 256-thread workgroup, 2 x 2 waves of 64 x 64
-//    (2 x 2 blocks of 32 x 32 per wave), K staged 16 at a time through LDS
-//    with a register double buffer for the next global tile.
+//  * 256 x 128 output tile per 256-thread workgroup, 2 x 2 waves of 128 x 64
+//    (4 x 2 blocks of 32 x 32 per wave: eight independent accumulators), K
+//    staged 16 at a time through LDS with a register double buffer for the
+//    next global tile.
 //  * op(A)(m, k) = A[m*lda + k] (TA = false) or A[k*lda + m] (TA = true);
 //    op(B)(k, n) = B[k*ldb + n] (TB = false) or B[n*ldb + k] (TB = true).
 //  * blockIdx.z = batch * ksplit + split; split s covers K range
@@ -20,15 +21,16 @@ namespace {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef floatx16 floatx16_t;
 
-constexpr int BM = 128, BN = 128, BK = 16;
-constexpr int LDSW = BM + 32;  // LDS row stride (floats) of the [k][m] / [k][n] tiles
+constexpr int BM = 256, BN = 128, BK = 16;
+constexpr int LDA_S = BM + 32;  // LDS row stride (floats) of the [k][m] tile
+constexpr int LDB_S = BN + 32;  // LDS row stride (floats) of the [k][n] tile
 
 template <bool TA, bool TB, int EPI>
 __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs g) {
-  __shared__ float As[2][BK][LDSW];
-  __shared__ float Bs[2][BK][LDSW];
+  __shared__ float As[2][BK][LDA_S];
+  __shared__ float Bs[2][BK][LDB_S];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave >> 1, wn = wave & 1;  // wave tile: 128 rows x 64 columns
   const int h = lane >> 5, l32 = lane & 31;
   const int batch = blockIdx.z / g.ksplit, split = blockIdx.z % g.ksplit;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
@@ -42,26 +44,26 @@ __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs g) {
   const int kb = split * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
 
-  // global tile loader: 8 elements of A and 8 of B per thread
-  float ra[8], rb[8];
+  // global tile loader: 16 elements of A and 8 of B per thread
+  float ra[16], rb[8];
   auto load = [&](int k0) {
-    if (!TA) {  // rows m, 16 consecutive k
-      const int m = m0 + (tid >> 1), kk = k0 + (tid & 1) * 8;
+    if (!TA) {  // row m = tid, 16 consecutive k
+      const int m = m0 + tid;
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
-        ra[e] = (m < g.M && kk + e < ke) ? A[(int64_t)m * g.lda + kk + e] : 0.0f;
-    } else {    // rows k, 128 consecutive m
-      const int k = k0 + (tid >> 4), mm = m0 + (tid & 15) * 8;
+      for (int e = 0; e < 16; ++e)
+        ra[e] = (m < g.M && k0 + e < ke) ? A[(int64_t)m * g.lda + k0 + e] : 0.0f;
+    } else {    // row k = tid / 16, 16 consecutive m
+      const int k = k0 + (tid >> 4), mm = m0 + (tid & 15) * 16;
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
+      for (int e = 0; e < 16; ++e)
         ra[e] = (k < ke && mm + e < g.M) ? A[(int64_t)k * g.lda + mm + e] : 0.0f;
     }
-    if (!TB) {  // rows k, 128 consecutive n
+    if (!TB) {  // row k = tid / 16, 8 consecutive n
       const int k = k0 + (tid >> 4), nn = n0 + (tid & 15) * 8;
 #pragma unroll
       for (int e = 0; e < 8; ++e)
         rb[e] = (k < ke && nn + e < g.N) ? B[(int64_t)k * g.ldb + nn + e] : 0.0f;
-    } else {    // rows n, 16 consecutive k
+    } else {    // row n = tid / 2, 8 consecutive k
       const int n = n0 + (tid >> 1), kk = k0 + (tid & 1) * 8;
 #pragma unroll
       for (int e = 0; e < 8; ++e)
@@ -70,13 +72,12 @@ __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs g) {
   };
   auto store = [&](int buf) {
     if (!TA) {
-      const int m = tid >> 1, kk = (tid & 1) * 8;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) As[buf][kk + e][m] = ra[e];
+      for (int e = 0; e < 16; ++e) As[buf][e][tid] = ra[e];
     } else {
-      const int k = tid >> 4, mm = (tid & 15) * 8;
+      const int k = tid >> 4, mm = (tid & 15) * 16;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) As[buf][k][mm + e] = ra[e];
+      for (int e = 0; e < 16; ++e) As[buf][k][mm + e] = ra[e];
     }
     if (!TB) {
       const int k = tid >> 4, nn = (tid & 15) * 8;
@@ -89,9 +90,9 @@ __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs g) {
     }
   };
 
-  floatx16 acc[2][2];
+  floatx16 acc[4][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{0};
 
@@ -107,13 +108,13 @@ __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs g) {
 #pragma unroll
     for (int s = 0; s < BK / 2; ++s) {
       const int k = 2 * s + h;
-      float av[2], bv[2];
+      float av[4], bv[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) av[i] = As[cur][k][wm * 64 + i * 32 + l32];
+      for (int i = 0; i < 4; ++i) av[i] = As[cur][k][wm * 128 + i * 32 + l32];
 #pragma unroll
       for (int j = 0; j < 2; ++j) bv[j] = Bs[cur][k][wn * 64 + j * 32 + l32];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
@@ -124,13 +125,13 @@ __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs g) {
 
   // epilogue: acc[i][j][r] is C[m][n] with m = mbase + 8*(r/4) + 4*h + r%4, n = nbase + l32
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int n = n0 + wn * 64 + j * 32 + l32;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        const int m = m0 + wm * 128 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
         if (m >= g.M || n >= g.N) continue;
         const float v = acc[i][j][r];
         if (EPI == GEMM_STORE) {
