@@ -33,6 +33,9 @@ from .tv import (  # noqa: F401
     realign_means,
     extract,
     em_iteration,
+    diag_frame_loglik,
+    preselect,
+    pruned_posteriors,
 )
 from .mlp import (  # noqa: F401
     feature_stats,

@@ -293,3 +293,44 @@ def em_iteration(X, utt_off, ubm, tv, update_sigma=True, mindiv_method="chol",
     mu1 = realign_means(T1, p1) if realign else mu.copy()
     return dict(gamma=gamma, lse=lse, n=n, f=f, S=S, estep=e, acc=acc, objective=obj,
                 T=T1, Sigma=S1, p=p1, mu=mu1, mstep_info=info, mindiv=aux)
+
+
+# --------------------------------------------------------------------------
+# Kaldi-style pruned alignment (Sec. 4.2): a diagonal-covariance UBM picks
+# the 20 best components per frame, the full-covariance UBM scores only
+# those, and posteriors below 0.025 are dropped before renormalising.
+# --------------------------------------------------------------------------
+def diag_frame_loglik(X, w, mu, cov):
+    """log( w_c N(x_t; mu_c, diag(cov_c)) ) for every frame and component, the
+    diagonal UBM taken as the diagonal of the full-covariance one."""
+    X = np.asarray(X, dtype=np.float64)
+    var = np.stack([np.diag(c) for c in cov])               # [C, D]
+    D = X.shape[1]
+    ll = np.empty((X.shape[0], len(w)))
+    for c in range(len(w)):
+        d = X - mu[c]
+        ll[:, c] = (np.log(w[c]) - 0.5 * D * LOG2PI - 0.5 * np.sum(np.log(var[c]))
+                    - 0.5 * np.sum(d * d / var[c], axis=1))
+    return ll
+
+
+def preselect(ll_diag, k):
+    """The k best components of every frame by the diagonal UBM, best first,
+    equal scores ordered by the lower component index."""
+    order = np.argsort(-ll_diag, axis=1, kind="stable")
+    return order[:, :k]
+
+
+def pruned_posteriors(X, w, mu, cov, idx, prune=0.025):
+    """Full-covariance posteriors restricted to the preselected components
+    idx [F, k] and renormalised over them; entries below `prune` are then
+    dropped and the rest renormalised.  Returns the dense [F, C] posteriors
+    and the per-frame log-likelihood over the preselected set."""
+    ll = frame_loglik(X, w, mu, cov)
+    sub = np.take_along_axis(ll, idx, axis=1)
+    g_sub, lse = posteriors(sub)
+    g_sub = np.where(g_sub < prune, 0.0, g_sub)
+    g_sub = g_sub / g_sub.sum(axis=1, keepdims=True)
+    gamma = np.zeros_like(ll)
+    np.put_along_axis(gamma, idx, g_sub, axis=1)
+    return gamma, lse
