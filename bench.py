@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--learned-steps", type=int, default=3000,
                     help="training steps of the learned selector (0: skip the learned form)")
     ap.add_argument("--learned-batch", type=int, default=4096)
+    ap.add_argument("--no-pruned", action="store_true",
+                    help="skip the pruned alignment (diagonal-UBM top-20, drop < 0.025)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of timing the candidates")
     return ap.parse_args()
@@ -390,6 +392,25 @@ def main():
         graph = {"utts_per_s": round(U * K / elg, 3), "ms_per_step": round(elg * 1e3 / K, 3)}
         log(f"[bench] graph replay: {graph}")
 
+    pruned = None
+    if not args.no_pruned:
+        ctx.pruned_set(20, 0.025)
+        elp, php, profp = timed(0, K, args.warmup, sel=ivx.IVX_SEL_PRUNED)
+        outs = []
+        for sel in (ivx.IVX_SEL_ALL, ivx.IVX_SEL_PRUNED):
+            reset_model()
+            step(0, sel=sel)
+            ctx.sync_status()
+            outs.append(phi.double().cpu().numpy())
+        a, b = outs
+        cos = (a * b).sum(1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1))
+        pruned = {"utts_per_s": round(U * K / elp, 3), "ms_per_step": round(elp * 1e3 / K, 3),
+                  "frame_posteriors_per_s": round(F * K / (php["frame"] / 1e3), 1),
+                  "diag_select_ms_per_step": round(profp["sel_mlp"][0] / K, 3),
+                  "scoring_ms_per_step": round(profp["sel_score"][0] / K, 3),
+                  "vs_plain_first_iteration": {"ivector_min_cosine": float(cos.min())}}
+        log(f"[bench] pruned alignment: {pruned}")
+
     learned = None
     if args.learned_steps > 0:
         learned = learned_form(args, ctx, wl, X, step, timed, reset_model, phi, K, dev)
@@ -427,6 +448,7 @@ def main():
         "tuning": tuning,
         "bf16_form": bf16,
         "graph_replay": graph,
+        "pruned_alignment": pruned,
         "learned_selection": learned,
         "cpu_baseline": cpu,
     }

@@ -65,8 +65,15 @@ typedef enum { IVX_FP32 = 0, IVX_BF16 = 1 } ivx_precision;
  *                    network's softmax falls back to IVX_SEL_ALL.  This stands
  *                    where the paper's diagonal-UBM preselection of 20
  *                    components stands (Sec. 4.2); the network is not from the
- *                    paper. */
-typedef enum { IVX_SEL_ALL = 0, IVX_SEL_LEARNED = 1 } ivx_selection;
+ *                    paper.
+ *   IVX_SEL_PRUNED   the paper's pruned alignment (Sec. 4.2, ivx_pruned_set):
+ *                    the k best components of a diagonal-covariance UBM (the
+ *                    diagonal of the full one) are scored with the full
+ *                    covariances, posteriors are computed over them, those
+ *                    below `prune` are dropped and the rest renormalised.
+ *                    The precision argument does not apply (FP32 diagonal
+ *                    scores and filter, FP64 exact scores). */
+typedef enum { IVX_SEL_ALL = 0, IVX_SEL_LEARNED = 1, IVX_SEL_PRUNED = 2 } ivx_selection;
 
 /* Problem dimensions, fixed for the life of a context.
  *   C  UBM components (>= 1), D feature dimension (1..63), R latent
@@ -306,6 +313,14 @@ ivx_status ivx_selector_grad(ivx_ctx* ctx, const float* X, int64_t F, const int6
 ivx_status ivx_selector_train_step(ivx_ctx* ctx, const float* X, int64_t F,
                                    const int64_t* frame_idx, int32_t B, const int32_t* post_idx,
                                    const float* post_val, float lr, double* loss, void* stream);
+
+/* Sets up the pruned alignment (IVX_SEL_PRUNED): k (1..min(32, C)) best
+ * diagonal-UBM components per frame, pruning threshold in [0, 0.5) (the paper
+ * uses k = 20 and 0.025).  Synchronises `stream`; allocates about
+ * maxF * 20 k bytes of workspace.  The diagonal coefficients follow the
+ * current UBM (recomputed by every pruned pass).  If more than 16 of a
+ * frame's posteriors reach the threshold, IVX_ECAPACITY is recorded. */
+ivx_status ivx_pruned_set(ivx_ctx* ctx, int32_t k, float prune, void* stream);
 
 /* Counters of the last learned-selection pass (synchronises `stream`):
  * frames that fell back to all components, and the (frame, proposal) pairs

@@ -116,6 +116,7 @@ void ivx_destroy(ivx_ctx* ctx) {
     prof_free(ctx);
   }
   selector_free(ctx);
+  presel_free(ctx);
   void* ptrs[] = {ctx->w, ctx->mu, ctx->cov, ctx->shift, ctx->Wexp, ctx->W16, ctx->linv,
                   ctx->linv32r, ctx->cst,
                   ctx->pairs, ctx->T, ctx->Sigma, ctx->p, ctx->cand, ctx->cM, ctx->cflag, ctx->post_idx,
@@ -357,9 +358,10 @@ static ivx_status check_frame_args(ivx_ctx* ctx, const char* fn, const float* X,
             (long long)F, (long long)ctx->maxF);
   IVX_CHECK(F == 0 || X, "%s: null X", fn);
   IVX_CHECK(prec == IVX_FP32 || prec == IVX_BF16, "%s: unknown precision %d", fn, (int)prec);
-  IVX_CHECK(sel == IVX_SEL_ALL || sel == IVX_SEL_LEARNED, "%s: unknown selection %d", fn,
-            (int)sel);
-  IVX_CHECK(sel == IVX_SEL_ALL || ctx->sel, "%s: IVX_SEL_LEARNED needs ivx_selector_set", fn);
+  IVX_CHECK(sel == IVX_SEL_ALL || sel == IVX_SEL_LEARNED || sel == IVX_SEL_PRUNED,
+            "%s: unknown selection %d", fn, (int)sel);
+  IVX_CHECK(sel != IVX_SEL_LEARNED || ctx->sel, "%s: IVX_SEL_LEARNED needs ivx_selector_set", fn);
+  IVX_CHECK(sel != IVX_SEL_PRUNED || ctx->presel, "%s: IVX_SEL_PRUNED needs ivx_pruned_set", fn);
   return IVX_OK;
 }
 

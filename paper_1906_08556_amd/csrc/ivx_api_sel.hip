@@ -3,6 +3,7 @@
 // bw_stats and extract_ivectors when they are called with IVX_SEL_LEARNED.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "ivx_internal.h"
 
@@ -23,10 +24,24 @@ void selector_free(ivx_ctx* ctx) {
   ctx->sel = nullptr;
 }
 
-// Posterior lists for frames [0, F): every component, or the learned
-// selection with the all-component fallback.
+void presel_free(ivx_ctx* ctx) {
+  if (!ctx || !ctx->presel) return;
+  Presel* P = ctx->presel;
+  void* ptrs[] = {P->Wd, P->pairs, P->prop, P->score, P->hist, P->coff, P->ent};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  delete P;
+  ctx->presel = nullptr;
+}
+
+// Posterior lists for frames [0, F): every component, the learned selection
+// with the all-component fallback, or the pruned alignment.
 void launch_posteriors(ivx_ctx* ctx, const float* X, int64_t F, int prec, int sel, int* post_idx,
                        float* post_val, double* frame_ll, hipStream_t s) {
+  if (sel == IVX_SEL_PRUNED) {
+    launch_select_pruned(ctx, X, F, post_idx, post_val, frame_ll, s);
+    return;
+  }
   if (sel == IVX_SEL_LEARNED) {
     launch_select_learned(ctx, X, F, prec, post_idx, post_val, frame_ll, s);
     return;
@@ -183,6 +198,54 @@ ivx_status ivx_selector_set(ivx_ctx* ctx, const ivx_selector_dims* sd, const flo
   launch_selector_inv_std(ctx, s);
   launch_selector_pack(ctx, s);
   return after_launch("ivx_selector_set");
+}
+
+ivx_status ivx_pruned_set(ivx_ctx* ctx, int32_t k, float prune, void* stream) {
+  SEL_CHECK(ctx, "ivx_pruned_set: null context");
+  SEL_CHECK(k >= 1 && k <= kMaxProposals && k <= ctx->C,
+            "ivx_pruned_set: k=%d outside [1, min(%d, C)]", k, kMaxProposals);
+  SEL_CHECK(prune >= 0.0f && prune < 0.5f, "ivx_pruned_set: prune outside [0, 0.5)");
+  if (set_device(ctx) != IVX_OK) return IVX_EDEVICE;
+  if (hipStreamSynchronize(as_stream(stream)) != hipSuccess) {
+    set_error("ivx_pruned_set: stream synchronisation failed");
+    return IVX_EDEVICE;
+  }
+  presel_free(ctx);
+  Presel* P = new Presel();
+  ctx->presel = P;
+  const int64_t D = ctx->D, C = ctx->C, Cpad = ctx->Cpad, maxF = ctx->maxF;
+  P->k = k;
+  P->prune = prune;
+  P->margin = selection_margin(k);
+  P->Kd8 = (int)((1 + 2 * D + 7) / 8 * 8);
+  bool ok = true;
+  auto A = [&](bool r) { ok = ok && r; };
+  A(salloc(&P->Wd, (int64_t)P->Kd8 * Cpad));
+  A(salloc(&P->pairs, P->Kd8));
+  A(salloc(&P->prop, maxF * k));
+  A(salloc(&P->score, maxF * k));
+  A(salloc(&P->hist, (maxF / 8192 + 1) * C));
+  A(salloc(&P->coff, C + 1));
+  A(salloc(&P->ent, maxF * k));
+  if (!ok) {
+    presel_free(ctx);
+    hipGetLastError();
+    set_error("ivx_pruned_set: device allocation failed");
+    return IVX_ENOMEM;
+  }
+  // feature pairs (a | b << 8) over x~ = [1, x']: (0,0), (0,d), (d,d)
+  std::vector<uint16_t> pr(P->Kd8, 0);
+  for (int d = 1; d <= D; ++d) {
+    pr[d] = (uint16_t)(0 | (d << 8));
+    pr[D + d] = (uint16_t)(d | (d << 8));
+  }
+  if (hipMemcpy(P->pairs, pr.data(), sizeof(uint16_t) * P->Kd8, hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    presel_free(ctx);
+    set_error("ivx_pruned_set: upload failed");
+    return IVX_EDEVICE;
+  }
+  return IVX_OK;
 }
 
 ivx_status ivx_selector_get(ivx_ctx* ctx, float* params, void* stream) {

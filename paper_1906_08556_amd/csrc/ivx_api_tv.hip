@@ -208,8 +208,9 @@ ivx_status extract_ivectors(ivx_ctx* ctx, const float* X, const int64_t* utt_off
             (long long)ctx->maxF);
   IVX_CHECK(utt_off && phi && (F == 0 || X), "extract_ivectors: null argument");
   IVX_CHECK(prec == IVX_FP32 || prec == IVX_BF16, "extract_ivectors: unknown precision");
-  IVX_CHECK(sel == IVX_SEL_ALL || (sel == IVX_SEL_LEARNED && ctx->sel),
-            "extract_ivectors: unknown selection, or IVX_SEL_LEARNED without ivx_selector_set");
+  IVX_CHECK(sel == IVX_SEL_ALL || (sel == IVX_SEL_LEARNED && ctx->sel) ||
+                (sel == IVX_SEL_PRUNED && ctx->presel),
+            "extract_ivectors: unknown selection, or a selection that was not set up");
   if (hipSetDevice(ctx->device) != hipSuccess) {
     set_error("extract_ivectors: hipSetDevice failed");
     return IVX_EDEVICE;

@@ -103,6 +103,22 @@ struct Selector {
   double* loss_part = nullptr;  // [Bmax]
 };
 
+// State of the pruned alignment (Sec. 4.2): diagonal-UBM coefficients and
+// the scoring workspace.  Owned by the context.
+struct Presel {
+  int k = 20;
+  float prune = 0.025f;
+  float margin = 0.0f;
+  int Kd8 = 0;              // 1 + 2D features rounded up to 8
+  float* Wd = nullptr;      // [Kd8/8][Cpad][8] diagonal coefficients, chunk-major
+  uint16_t* pairs = nullptr;  // [Kd8] feature index pairs (1, x_d, x_d^2)
+  int* prop = nullptr;      // [maxF][k]
+  float* score = nullptr;   // [maxF][k]
+  int* hist = nullptr;      // [maxF / 8192 + 1][C]
+  int* coff = nullptr;      // [C + 1]
+  int2* ent = nullptr;      // [maxF * k]
+};
+
 // Records a message for ivx_last_error() (printf-style).
 void set_error(const char* fmt, ...);
 
@@ -206,6 +222,8 @@ struct ivx_ctx {
 
   // learned Gaussian selection (ivx_selector_set), null until set
   ivx::Selector* sel = nullptr;
+  // pruned alignment (ivx_pruned_set), null until set
+  ivx::Presel* presel = nullptr;
 
   // event profiler (off unless ivx_profile_enable)
   bool prof_on = false;
@@ -260,6 +278,7 @@ ivx_status ensure_tv_ready(ivx_ctx* ctx, hipStream_t s);
 
 // ---- ivx_api_sel.hip
 void selector_free(ivx_ctx* ctx);
+void presel_free(ivx_ctx* ctx);
 void launch_posteriors(ivx_ctx* ctx, const float* X, int64_t F, int prec, int sel, int* post_idx,
                        float* post_val, double* frame_ll, hipStream_t s);
 
@@ -273,6 +292,8 @@ void launch_selector_mlp(ivx_ctx* ctx, const float* X, int64_t F, uint16_t* h1_o
                          uint16_t* h2_out, float* z_out, hipStream_t s);
 void launch_select_learned(ivx_ctx* ctx, const float* X, int64_t F, int prec, int* post_idx,
                            float* post_val, double* frame_ll, hipStream_t s);
+void launch_select_pruned(ivx_ctx* ctx, const float* X, int64_t F, int* post_idx, float* post_val,
+                          double* frame_ll, hipStream_t s);
 bool launch_selector_grad(ivx_ctx* ctx, const float* X, int64_t F, const int64_t* fidx, int B,
                           const int* post_idx, const float* post_val, double* loss,
                           hipStream_t s);

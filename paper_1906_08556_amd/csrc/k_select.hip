@@ -399,6 +399,176 @@ k_mlp_l3(const __bf16* __restrict__ H2, int64_t rows, int64_t row0, int K,
   if (local >= 0) fb_list[wg[1] + local] = (int)(row0 + m0 + tid);
 }
 
+// ------------------------------------------------- pruned alignment (Sec. 4.2)
+// Diagonal-UBM log-likelihoods as one expanded-feature product per (frame,
+// component): with x' = x - shift and mu' = mu - shift,
+//   log w_c N(x; mu_c, diag(Sigma_c)) = g_c + sum_d b_cd x'_d + sum_d a_cd x'_d^2,
+//   a = -1 / (2 s^2), b = mu' / s^2,
+//   g = log w_c - D/2 log 2pi - 1/2 sum_d log s^2_cd - 1/2 sum_d mu'^2 / s^2,
+// over the features (1, x'_1..x'_D, x'_1^2..x'_D^2).  Coefficients are stored
+// chunk-major like the full-covariance ones: (c, k) at ((k/8) Cpad + c) 8 + k%8.
+__global__ void k_diag_prepare(const double* __restrict__ w, const double* __restrict__ mu,
+                               const double* __restrict__ cov, const float* __restrict__ shift,
+                               int C, int Cpad, int D, int Kd8, float* __restrict__ Wd) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Cpad) return;
+  auto at = [&](int k) -> float& { return Wd[((size_t)(k >> 3) * Cpad + c) * 8 + (k & 7)]; };
+  if (c >= C) {  // padding components: never among the best
+    for (int k = 0; k < Kd8; ++k) at(k) = (k == 0) ? -1e30f : 0.0f;
+    return;
+  }
+  double g = log(w[c]) - 0.5 * D * 1.8378770664093454836;
+  for (int d = 0; d < D; ++d) {
+    const double s2 = cov[((size_t)c * D + d) * D + d];
+    const double m = mu[(size_t)c * D + d] - (double)shift[d];
+    g -= 0.5 * log(s2) + 0.5 * m * m / s2;
+    at(1 + d) = (float)(m / s2);
+    at(1 + D + d) = (float)(-0.5 / s2);
+  }
+  at(0) = (float)g;
+  for (int k = 1 + 2 * D; k < Kd8; ++k) at(k) = 0.0f;
+}
+
+// Diagonal-UBM scores of every (frame, component) on FP32 MFMA and the k best
+// components per frame (ties to the lower index).  One workgroup per 128
+// frames loops over all components 256 at a time (W chunks of 8 features
+// staged through LDS as in k_frame_tile); after each 256-component tile the
+// two lane-halves holding a frame insert the tile's scores that beat their
+// KM-th into a sorted list in registers; at the end the two lists are merged
+// by counting ranks in LDS.  prop[t][0..k): the k best, best first.
+template <int KM>
+__global__ void __launch_bounds__(256)
+k_diag_topk(const float* __restrict__ X, int64_t F, int D, const float* __restrict__ shift,
+            const float* __restrict__ Wd, int C, int Cpad, int Kd8,
+            const uint16_t* __restrict__ pairs, int k, int* __restrict__ prop) {
+  constexpr int FR = 32, FTD = 128, CTD = 128, NCBD = CTD / 32, WLDD = 12;
+  extern __shared__ float smem[];
+  float* Ws = smem;                                            // [2][CTD][WLDD]
+  float* xs = smem + 2 * CTD * WLDD;                           // [FTD][D+1]
+  uint32_t* prs = reinterpret_cast<uint32_t*>(xs + FTD * (D + 1));
+  float* lvs = smem;                                           // after the loop: [2][FTD][KM]
+  int* lis = reinterpret_cast<int*>(lvs + 2 * FTD * KM);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int DS = D + 1;
+  const int64_t f0 = (int64_t)blockIdx.x * FTD;
+  const int nq = Kd8 / 8;
+  for (int i = tid; i < Kd8 / 2; i += 256) prs[i] = reinterpret_cast<const uint32_t*>(pairs)[i];
+  for (int i = tid; i < FTD * DS; i += 256) {
+    const int fr = i / DS, a = i - fr * DS;
+    const int64_t g = f0 + fr;
+    float v = (a == 0) ? 1.0f : 0.0f;
+    if (a > 0 && g < F) v = X[g * D + (a - 1)] - shift[a - 1];
+    xs[i] = v;
+  }
+  float lv[KM];
+  int li[KM];
+#pragma unroll
+  for (int q = 0; q < KM; ++q) {
+    lv[q] = -INFINITY;
+    li[q] = -1;
+  }
+  const float* xw = xs + (wave * FR + l32) * DS;
+  for (int c0 = 0; c0 < Cpad; c0 += CTD) {
+    // two threads stage the 8 coefficients of one component
+    float4 r0;
+    auto gload = [&](int q) {
+      r0 = *reinterpret_cast<const float4*>(Wd + ((size_t)q * Cpad + c0 + (tid >> 1)) * 8 +
+                                             (tid & 1) * 4);
+    };
+    auto sstore = [&](int buf) {
+      *reinterpret_cast<float4*>(Ws + (buf * CTD + (tid >> 1)) * WLDD + (tid & 1) * 4) = r0;
+    };
+    __syncthreads();  // the previous tile's stages are consumed
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    floatx16 acc[NCBD];
+#pragma unroll
+    for (int cb = 0; cb < NCBD; ++cb) acc[cb] = floatx16{0};
+    for (int q = 0; q < nq; ++q) {
+      const int cur = q & 1;
+      if (q + 1 < nq) gload(q + 1);
+      const float* wb = Ws + (cur * CTD + l32) * WLDD + 4 * h;
+      float4 wv[NCBD];
+#pragma unroll
+      for (int cb = 0; cb < NCBD; ++cb) wv[cb] = *reinterpret_cast<const float4*>(wb + cb * 32 * WLDD);
+      const uint32_t pw0 = prs[4 * q + 2 * h], pw1 = prs[4 * q + 2 * h + 1];
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const uint32_t pr = ((s2 < 2) ? pw0 : pw1) >> ((s2 & 1) * 16);
+        const float bv = xw[pr & 0xff] * xw[(pr >> 8) & 0xff];
+#pragma unroll
+        for (int cb = 0; cb < NCBD; ++cb) {
+          const float av = (s2 == 0) ? wv[cb].x : (s2 == 1) ? wv[cb].y : (s2 == 2) ? wv[cb].z : wv[cb].w;
+          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[cb], 0, 0, 0);
+        }
+      }
+      if (q + 1 < nq) sstore(cur ^ 1);
+      __syncthreads();
+    }
+    float tmax = -INFINITY;
+#pragma unroll
+    for (int cb = 0; cb < NCBD; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) tmax = fmaxf(tmax, acc[cb][r]);
+    if (tmax > lv[KM - 1]) {
+#pragma unroll
+      for (int cb = 0; cb < NCBD; ++cb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float v = acc[cb][r];
+          const int c = c0 + cb * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+          if (c < C && v > lv[KM - 1]) {
+#pragma unroll
+            for (int q = KM - 1; q > 0; --q) {
+              const float vp = lv[q - 1], vq = lv[q];
+              const int ip = li[q - 1], iq = li[q];
+              const bool up = v > vp;
+              const bool atq = v > vq;
+              lv[q] = up ? vp : (atq ? v : vq);
+              li[q] = up ? ip : (atq ? c : iq);
+            }
+            if (v > lv[0]) {
+              lv[0] = v;
+              li[0] = c;
+            }
+          }
+        }
+    }
+  }
+  __syncthreads();  // stages dead: the lists reuse the memory
+  const int f = wave * FR + l32;
+#pragma unroll
+  for (int q = 0; q < KM; ++q) {
+    lvs[(h * FTD + f) * KM + q] = lv[q];
+    lis[(h * FTD + f) * KM + q] = li[q];
+  }
+  __syncthreads();
+  const int64_t g = f0 + f;
+  if (g < F) {
+    const float* ov = lvs + ((h ^ 1) * FTD + f) * KM;
+    const int* oi = lis + ((h ^ 1) * FTD + f) * KM;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) {
+      const float v = lv[q];
+      const int c = li[q];
+      if (c < 0) continue;
+      int rank = q;
+      for (int p = 0; p < KM; ++p) {
+        const int oc = oi[p];
+        if (oc < 0) break;
+        const float ow = ov[p];
+        if (ow > v || (ow == v && oc < c))
+          ++rank;
+        else
+          break;
+      }
+      if (rank < k) prop[g * k + rank] = c;
+    }
+  }
+}
+
 // hist[b][c]: proposals of component c among the kept frames of block b
 __global__ void __launch_bounds__(256)
 k_sel_hist(int64_t F, int k, int C, const int* __restrict__ prop, const int* __restrict__ fb,
@@ -410,7 +580,7 @@ k_sel_hist(int64_t F, int k, int C, const int* __restrict__ prop, const int* __r
   const int64_t e0 = (int64_t)b * HBS * k;
   const int64_t e1 = min(F * k, e0 + (int64_t)HBS * k);
   for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-    if (fb[e / k]) continue;
+    if (fb && fb[e / k]) continue;
     const int c = prop[e];
     if (c >= 0 && c < C) atomicAdd(&hl[c], 1);
   }
@@ -428,7 +598,7 @@ k_sel_scatter(int64_t F, int k, int C, const int* __restrict__ prop, const int* 
   const int64_t e0 = (int64_t)b * HBS * k;
   const int64_t e1 = min(F * k, e0 + (int64_t)HBS * k);
   for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-    if (fb[e / k]) continue;
+    if (fb && fb[e / k]) continue;
     const int c = prop[e];
     if (c >= 0 && c < C) {
       const int pos = atomicAdd(&cur[c], 1);
@@ -499,7 +669,7 @@ k_sel_finalize(const float* __restrict__ X, int64_t F, int D, int C, int k,
                const int* __restrict__ prop, const int* __restrict__ fb,
                const float* __restrict__ score, const double* __restrict__ mu,
                const double* __restrict__ linv, const double* __restrict__ cst, float margin,
-               int* __restrict__ post_idx, float* __restrict__ post_val,
+               float prune, int* __restrict__ post_idx, float* __restrict__ post_val,
                double* __restrict__ frame_ll, int* __restrict__ err) {
   __shared__ double dsh[4][64];
   __shared__ double lsh[4][32];
@@ -507,7 +677,7 @@ k_sel_finalize(const float* __restrict__ X, int64_t F, int D, int C, int k,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t g = (int64_t)blockIdx.x * 4 + wave;
   if (g >= F) return;  // wave-uniform
-  if (fb[g]) return;
+  if (fb && fb[g]) return;
   const int Dp = D * (D + 1) / 2;
   const double xd = (lane < D) ? (double)X[g * D + lane] : 0.0;
   int c = -1;
@@ -544,9 +714,27 @@ k_sel_finalize(const float* __restrict__ X, int64_t F, int D, int C, int k,
   const double mx = (m > 0) ? lsh[wave][0] : -INFINITY;
   for (int s = 0; s < m; ++s) se += exp(lsh[wave][s] - mx);
   const double lse = mx + log(se);
+  // pruning (prune > 0): posteriors below `prune` are dropped and the rest
+  // renormalised; the list is sorted, so the kept entries are a prefix
+  int mk = m < KP ? m : KP;
+  double norm = 1.0;
+  if (prune > 0.0f) {
+    int np = 0;
+    double kept = 0.0;
+    for (int s = 0; s < m; ++s) {
+      const double gs = exp(lsh[wave][s] - lse);
+      if (gs >= (double)prune) {
+        ++np;
+        kept += gs;
+      }
+    }
+    if (lane == 0 && np > KP) raise_error(err, IVX_ECAPACITY, PK_SEL_SCORE, (int)g);
+    mk = np < KP ? np : KP;
+    norm = kept;
+  }
   if (lane == 0) {
     if (!isfinite(lse)) raise_error(err, IVX_ENUMERIC, PK_SEL_SCORE, (int)g);
-    if (m > KP) {
+    if (prune <= 0.0f && m > KP) {
       double kept = 0.0;
       for (int s = 0; s < KP; ++s) kept += exp(lsh[wave][s] - lse);
       if (1.0 - kept > kMaxDroppedMass) raise_error(err, IVX_ECAPACITY, PK_SEL_SCORE, (int)g);
@@ -555,9 +743,9 @@ k_sel_finalize(const float* __restrict__ X, int64_t F, int D, int C, int k,
   if (lane < KP) {
     int id = -1;
     float v = 0.0f;
-    if (lane < m) {
+    if (lane < mk) {
       id = ish[wave][lane];
-      v = (float)exp(lsh[wave][lane] - lse);
+      v = (float)(exp(lsh[wave][lane] - lse) / norm);
     }
     if (post_idx) post_idx[g * KP + lane] = id;
     if (post_val) post_val[g * KP + lane] = v;
@@ -772,10 +960,25 @@ size_t l3_lds_bytes(int km) {
 
 int l3_km(int k) { return k <= 8 ? 8 : (k <= 20 ? 20 : 32); }
 
+size_t diag_lds_bytes(int D, int Kd8, int km) {
+  const size_t stage = sizeof(float) * (2 * 128 * 12 + 128 * (D + 1)) + sizeof(uint16_t) * Kd8;
+  const size_t lists = sizeof(float) * 2 * 128 * km * 2;
+  return std::max(stage, lists);
+}
+
 }  // namespace
 
 bool select_set_attributes() {
   bool ok = true;
+  ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_diag_topk<32>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)diag_lds_bytes(63, 128, 32)) == hipSuccess;
+  ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_diag_topk<20>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)diag_lds_bytes(63, 128, 20)) == hipSuccess;
+  ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_diag_topk<8>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)diag_lds_bytes(63, 128, 8)) == hipSuccess;
   ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_l3<8>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)l3_lds_bytes(8)) == hipSuccess;
@@ -862,12 +1065,51 @@ void launch_select_learned(ivx_ctx* ctx, const float* X, int64_t F, int prec, in
         X, ctx->D, S.k, S.coff, ctx->C, S.ent, cap, ctx->mu, ctx->linv32r, ctx->cst, S.score);
     k_sel_finalize<<<(unsigned)((F + 3) / 4), 256, 0, s>>>(
         X, F, ctx->D, ctx->C, S.k, S.prop, S.fb, S.score, ctx->mu, ctx->linv, ctx->cst, S.margin,
-        post_idx, post_val, frame_ll, ctx->dev_err);
+        0.0f, post_idx, post_val, frame_ll, ctx->dev_err);
   }
   // fallback frames: all components, results written at their own rows
   k_gather_rows<<<2048, 256, 0, s>>>(X, ctx->D, S.fb_list, S.counters, F, S.xfb);
   launch_frame_select(ctx, S.xfb, F, prec, s, S.counters);
   launch_rescore(ctx, S.xfb, F, prec, post_idx, post_val, frame_ll, s, S.counters, S.fb_list);
+}
+
+// Pruned alignment (Sec. 4.2) for frames [0, F): diagonal-UBM top-k,
+// full-covariance scores of the k (FP32 filter, FP64 within the margin),
+// posteriors over them, entries below `prune` dropped, the rest renormalised.
+void launch_select_pruned(ivx_ctx* ctx, const float* X, int64_t F, int* post_idx, float* post_val,
+                          double* frame_ll, hipStream_t s) {
+  if (F <= 0) return;
+  Presel& P = *ctx->presel;
+  {
+    ProfScope ps(ctx, PK_SEL_MLP, s);
+    k_diag_prepare<<<(ctx->Cpad + 255) / 256, 256, 0, s>>>(ctx->w, ctx->mu, ctx->cov, ctx->shift,
+                                                           ctx->C, ctx->Cpad, ctx->D, P.Kd8, P.Wd);
+    const int km = l3_km(P.k);
+    const unsigned nb = (unsigned)((F + 127) / 128);
+    const size_t lds = diag_lds_bytes(ctx->D, P.Kd8, km);
+#define IVX_DIAG(KMV)                                                                          \
+  k_diag_topk<KMV><<<nb, 256, lds, s>>>(X, F, ctx->D, ctx->shift, P.Wd, ctx->C, ctx->Cpad,      \
+                                        P.Kd8, P.pairs, P.k, P.prop)
+    if (km == 8)
+      IVX_DIAG(8);
+    else if (km == 20)
+      IVX_DIAG(20);
+    else
+      IVX_DIAG(32);
+#undef IVX_DIAG
+  }
+  ProfScope ps(ctx, PK_SEL_SCORE, s);
+  const int nb = (int)((F + HBS - 1) / HBS);
+  const size_t ldsc = sizeof(int) * ctx->C;
+  k_sel_hist<<<nb, 256, ldsc, s>>>(F, P.k, ctx->C, P.prop, nullptr, P.hist);
+  launch_hist_scan(nb, ctx->C, P.hist, P.coff, s);
+  k_sel_scatter<<<nb, 256, ldsc, s>>>(F, P.k, ctx->C, P.prop, nullptr, P.hist, P.ent);
+  const int64_t cap = F * P.k;
+  k_sel_score<<<(unsigned)((cap + 255) / 256), 256, 0, s>>>(
+      X, ctx->D, P.k, P.coff, ctx->C, P.ent, cap, ctx->mu, ctx->linv32r, ctx->cst, P.score);
+  k_sel_finalize<<<(unsigned)((F + 3) / 4), 256, 0, s>>>(
+      X, F, ctx->D, ctx->C, P.k, P.prop, nullptr, P.score, ctx->mu, ctx->linv, ctx->cst, P.margin,
+      P.prune, post_idx, post_val, frame_ll, ctx->dev_err);
 }
 
 // Gradients of the soft-target cross-entropy over a batch of B frames into

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libivx.so")
 
 IVX_FP32, IVX_BF16 = 0, 1
-IVX_SEL_ALL, IVX_SEL_LEARNED = 0, 1
+IVX_SEL_ALL, IVX_SEL_LEARNED, IVX_SEL_PRUNED = 0, 1, 2
 KP = 16  # posterior list capacity per frame
 
 STATUS = {0: "IVX_OK", -1: "IVX_EINVAL", -2: "IVX_ENOMEM", -3: "IVX_ENOTPD", -4: "IVX_EDEVICE",
@@ -84,6 +84,7 @@ PROTOTYPES = {
     "ivx_feature_stats": (_I32, [_P, _P, _I64, _P, _P, _P]),
     "ivx_selector_set": (_I32, [_P, ctypes.POINTER(SelectorDims), _P, _P, _P, _P]),
     "ivx_selector_param_count": (_I64, [_P]),
+    "ivx_pruned_set": (_I32, [_P, _I32, ctypes.c_float, _P]),
     "ivx_selector_get": (_I32, [_P, _P, _P]),
     "ivx_selector_forward": (_I32, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     "ivx_selector_grad": (_I32, [_P, _P, _I64, _P, _I32, _P, _P, _P, _P, _P]),
@@ -292,6 +293,9 @@ class Context:
         self._check(self.lib.ivx_selector_set(self.h, ctypes.byref(self.sel_dims),
                                               self._p(params, f, "params"), self._p(mean, f, "mean"),
                                               self._p(std, f, "std"), _stream(stream)))
+
+    def pruned_set(self, k=20, prune=0.025, stream=None):
+        self._check(self.lib.ivx_pruned_set(self.h, int(k), float(prune), _stream(stream)))
 
     def selector_param_count(self) -> int:
         return int(self.lib.ivx_selector_param_count(self.h))
