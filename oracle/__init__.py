@@ -36,6 +36,10 @@ from .tv import (  # noqa: F401
     diag_frame_loglik,
     preselect,
     pruned_posteriors,
+    init_tv_standard,
+    center_stats,
+    mindiv_standard,
+    em_iteration_standard,
 )
 from .mlp import (  # noqa: F401
     feature_stats,

@@ -334,3 +334,67 @@ def pruned_posteriors(X, w, mu, cov, idx, prune=0.025):
     gamma = np.zeros_like(ll)
     np.put_along_axis(gamma, idx, g_sub, axis=1)
     return gamma, lse
+
+
+# --------------------------------------------------------------------------
+# Standard formulation (Sec. 2.1): mu_c(u) = m_c + T_c omega(u), omega ~ N(0, I),
+# first- and second-order statistics centred on the bias m_c, prior offset 0.
+# --------------------------------------------------------------------------
+def init_tv_standard(mu, cov, T_rand):
+    """T_c <- N(0, 1) draws, m_c <- UBM means, Sigma_c <- UBM covariances,
+    p = 0 (Sec. 2.1)."""
+    R = T_rand.shape[2]
+    return (np.array(T_rand, dtype=np.float64), np.array(cov, dtype=np.float64), np.zeros(R),
+            np.array(mu, dtype=np.float64))
+
+
+def center_stats(n, f, S, m):
+    """Centred statistics: f~_c(u) = f_c(u) - n_c(u) m_c and
+    S~_c = sum_u sum_t gamma_tc (x_t - m_c)(x_t - m_c)^T
+         = S_c - F_c m_c^T - m_c F_c^T + N_c m_c m_c^T,
+    with F_c = sum_u f_c(u), N_c = sum_u n_c(u)."""
+    fc = f - n[:, :, None] * m[None, :, :]
+    F = f.sum(axis=0)
+    N = n.sum(axis=0)
+    Sc = (S - np.einsum("cd,ce->cde", F, m) - np.einsum("cd,ce->cde", m, F)
+          + N[:, None, None] * np.einsum("cd,ce->cde", m, m))
+    return fc, Sc
+
+
+def mindiv_standard(h, H, T, m):
+    """Minimum divergence in the standard formulation: the latent vectors
+    have mean h and covariance G = H - h h^T, with G = L_G L_G^T; writing
+    omega = h + L_G omega' keeps every model mean m_c + T_c omega while
+    omega' is standard normal:  m_c <- m_c + T_c h,  T_c <- T_c L_G."""
+    G = H - np.outer(h, h)
+    L = np.linalg.cholesky(G)
+    m1 = m + np.einsum("cdr,r->cd", T, h)
+    T1 = np.einsum("cdr,rs->cds", T, L)
+    return T1, m1
+
+
+def em_iteration_standard(X, utt_off, ubm, tv, update_sigma=True, mindiv=True, stats=None):
+    """One training iteration of the standard formulation: posteriors from
+    the UBM, statistics centred on m, E-step with p = 0, accumulators, the
+    objective at the incoming parameters, M-step (T, optionally Sigma) and
+    optionally minimum divergence with the bias update.  tv = (T, Sigma, p, m)
+    with p = 0; returns the updated (T, Sigma, m) and the intermediates."""
+    w, mu, cov = ubm
+    T, Sigma, p, m = tv
+    if stats is None:
+        gamma, lse = posteriors(frame_loglik(X, w, mu, cov))
+        n, f, S = bw_stats(X, utt_off, gamma)
+    else:
+        n, f, S = stats
+    fc, Sc = center_stats(n, f, S, m)
+    e = estep(n, fc, T, Sigma, p)
+    acc = accumulate(n, fc, e["phi"], e["Phi"])
+    obj = objective(acc["N"], Sc, Sigma, e["ll_u"].sum())
+    T1, S1, info = mstep(acc, Sc, T, Sigma, update_sigma=update_sigma)
+    m1 = m.copy()
+    if mindiv:
+        h = acc["hsum"] / acc["count"]
+        H = acc["Hsum"] / acc["count"]
+        T1, m1 = mindiv_standard(h, H, T1, m)
+    return dict(n=n, f=f, S=S, fc=fc, Sc=Sc, estep=e, acc=acc, objective=obj, T=T1, Sigma=S1,
+                m=m1, mstep_info=info)
