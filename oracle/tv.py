@@ -361,24 +361,35 @@ def center_stats(n, f, S, m):
     return fc, Sc
 
 
-def mindiv_standard(h, H, T, m):
-    """Minimum divergence in the standard formulation: the latent vectors
-    have mean h and covariance G = H - h h^T, with G = L_G L_G^T; writing
-    omega = h + L_G omega' keeps every model mean m_c + T_c omega while
-    omega' is standard normal:  m_c <- m_c + T_c h,  T_c <- T_c L_G."""
+def mindiv_standard(h, H, T, m, method="chol", update_mean=False):
+    """Minimum divergence in the standard formulation (Sec. 3.1): G = H - h h^T
+    is whitened by P1 (Cholesky: P1^{-1} = L_G with G = L_G L_G^T; eig:
+    P1^{-1} = Q Lambda^{1/2} with G = Q Lambda Q^T) and T_c <- T_c P1^{-1};
+    that update alone is the standard form's re-estimation.  With
+    update_mean, the bias also absorbs the i-vector mean first (Sec. 5):
+    m_c <- m_c + T_c h, so that m_c + T_c omega is kept for omega = h + P1^{-1} omega'.
+    Returns (T_upd, m_upd)."""
     G = H - np.outer(h, h)
-    L = np.linalg.cholesky(G)
-    m1 = m + np.einsum("cdr,r->cd", T, h)
-    T1 = np.einsum("cdr,rs->cds", T, L)
+    if method == "chol":
+        P1inv = np.linalg.cholesky(G)
+    elif method == "eig":
+        lam, Q = np.linalg.eigh(G)
+        P1inv = Q * np.sqrt(lam)[None, :]
+    else:
+        raise ValueError(method)
+    m1 = m + np.einsum("cdr,r->cd", T, h) if update_mean else np.array(m, copy=True)
+    T1 = np.einsum("cdr,rs->cds", T, P1inv)
     return T1, m1
 
 
-def em_iteration_standard(X, utt_off, ubm, tv, update_sigma=True, mindiv=True, stats=None):
+def em_iteration_standard(X, utt_off, ubm, tv, update_sigma=True, mindiv=True,
+                          update_mean=False, method="chol", stats=None):
     """One training iteration of the standard formulation: posteriors from
     the UBM, statistics centred on m, E-step with p = 0, accumulators, the
     objective at the incoming parameters, M-step (T, optionally Sigma) and
-    optionally minimum divergence with the bias update.  tv = (T, Sigma, p, m)
-    with p = 0; returns the updated (T, Sigma, m) and the intermediates."""
+    optionally minimum divergence (with the bias update if update_mean).
+    tv = (T, Sigma, p, m) with p = 0; returns the updated (T, Sigma, m) and
+    the intermediates."""
     w, mu, cov = ubm
     T, Sigma, p, m = tv
     if stats is None:
@@ -391,10 +402,10 @@ def em_iteration_standard(X, utt_off, ubm, tv, update_sigma=True, mindiv=True, s
     acc = accumulate(n, fc, e["phi"], e["Phi"])
     obj = objective(acc["N"], Sc, Sigma, e["ll_u"].sum())
     T1, S1, info = mstep(acc, Sc, T, Sigma, update_sigma=update_sigma)
-    m1 = m.copy()
+    m1 = np.array(m, copy=True)
     if mindiv:
         h = acc["hsum"] / acc["count"]
         H = acc["Hsum"] / acc["count"]
-        T1, m1 = mindiv_standard(h, H, T1, m)
+        T1, m1 = mindiv_standard(h, H, T1, m, method=method, update_mean=update_mean)
     return dict(n=n, f=f, S=S, fc=fc, Sc=Sc, estep=e, acc=acc, objective=obj, T=T1, Sigma=S1,
                 m=m1, mstep_info=info)

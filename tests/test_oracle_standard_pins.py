@@ -109,7 +109,7 @@ def test_mindiv_standard_preserves_the_supervector_distribution():
     B = rng.standard_normal((R, R + 2))
     G = B @ B.T / (R + 2) + 0.2 * np.eye(R)
     H = G + np.outer(h, h)
-    T1, m1 = oracle.mindiv_standard(h, H, T, m)
+    T1, m1 = oracle.mindiv_standard(h, H, T, m, update_mean=True)
     Ts, Ts1 = T.reshape(C * D, R), T1.reshape(C * D, R)
     np.testing.assert_allclose(m1.reshape(-1), m.reshape(-1) + Ts @ h, rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(Ts1 @ Ts1.T, Ts @ G @ Ts.T, rtol=1e-11, atol=1e-11)
@@ -127,17 +127,40 @@ def test_mindiv_standard_at_the_prior_is_the_identity():
     rng = np.random.default_rng(12)
     T = rng.standard_normal((2, 3, 4))
     m = rng.standard_normal((2, 3))
-    T1, m1 = oracle.mindiv_standard(np.zeros(4), np.eye(4), T, m)
+    for method in ("chol", "eig"):
+        T1, m1 = oracle.mindiv_standard(np.zeros(4), np.eye(4), T, m, method=method,
+                                        update_mean=True)
+        np.testing.assert_allclose(np.einsum("cdr,cer->cde", T1, T1),
+                                   np.einsum("cdr,cer->cde", T, T), atol=1e-13)
+        np.testing.assert_allclose(m1, m, atol=1e-15)
+    T1, _ = oracle.mindiv_standard(np.zeros(4), np.eye(4), T, m)
     np.testing.assert_allclose(T1, T, atol=1e-15)
-    np.testing.assert_allclose(m1, m, atol=1e-15)
+
+
+@pytest.mark.parametrize("method", ["chol", "eig"])
+def test_mindiv_standard_without_mean_update_whitens_with_G_and_keeps_m(method):
+    """The P1-only update (the standard form's re-estimation): the bias is
+    kept and the loading covariance becomes T G T^T for either whitening."""
+    rng = np.random.default_rng(13)
+    C, D, R = 2, 5, 4
+    T = rng.standard_normal((C, D, R))
+    m = rng.standard_normal((C, D))
+    h = rng.standard_normal(R)
+    B = rng.standard_normal((R, R + 3))
+    G = B @ B.T / (R + 3) + 0.1 * np.eye(R)
+    T1, m1 = oracle.mindiv_standard(h, G + np.outer(h, h), T, m, method=method)
+    np.testing.assert_array_equal(m1, m)
+    Ts, Ts1 = T.reshape(C * D, R), T1.reshape(C * D, R)
+    np.testing.assert_allclose(Ts1 @ Ts1.T, Ts @ G @ Ts.T, rtol=1e-11, atol=1e-11)
 
 
 @pytest.mark.parametrize("update_sigma,mindiv", [(True, True), (True, False), (False, True),
                                                  (False, False)])
 def test_standard_em_is_monotone_at_fixed_statistics(update_sigma, mindiv):
     """Each iteration maximises the EM auxiliary function (in T, Sigma and,
-    with minimum divergence, the prior's mean and covariance), so the
-    objective at fixed alignments cannot decrease."""
+    with minimum divergence and the bias update, the prior's mean and
+    covariance), so the objective at fixed alignments cannot decrease.  The
+    P1-only update drops h and is not such a step, so it is not asserted."""
     wl = synth.make(1, n_utts=12, D=6, C=8, R=4, U=12, lengths="uniform:20:40")
     X = wl.X.astype(np.float64)
     ubm = (wl.w, wl.mu, wl.cov)
@@ -147,7 +170,8 @@ def test_standard_em_is_monotone_at_fixed_statistics(update_sigma, mindiv):
     objs = []
     for _ in range(6):
         r = oracle.em_iteration_standard(X, wl.utt_off, ubm, (T, Sigma, p, m),
-                                         update_sigma=update_sigma, mindiv=mindiv, stats=stats)
+                                         update_sigma=update_sigma, mindiv=mindiv,
+                                         update_mean=True, stats=stats)
         objs.append(r["objective"])
         T, Sigma, m = r["T"], r["Sigma"], r["m"]
     d = np.diff(objs)
@@ -162,7 +186,8 @@ def test_standard_mindiv_whitens_the_posterior_moments_of_a_recentred_model():
     X = wl.X.astype(np.float64)
     ubm = (wl.w, wl.mu, wl.cov)
     T, Sigma, p, m = oracle.init_tv_standard(wl.mu, wl.cov, 0.4 * wl.T_init)
-    r = oracle.em_iteration_standard(X, wl.utt_off, ubm, (T, Sigma, p, m), mindiv=True)
+    r = oracle.em_iteration_standard(X, wl.utt_off, ubm, (T, Sigma, p, m), mindiv=True,
+                                     update_mean=True)
     acc = r["acc"]
     h = acc["hsum"] / acc["count"]
     H = acc["Hsum"] / acc["count"]
