@@ -139,6 +139,25 @@ ivx_status ivx_set_ubm(ivx_ctx* ctx, const double* w, const double* mu, const do
  * mu_c / p0, Sigma_c <- UBM covariance, p <- p0 e_1.  Requires ivx_set_ubm. */
 ivx_status ivx_init_tv(ivx_ctx* ctx, const double* T_rand, double p0, void* stream);
 
+/* Standard initialisation (Sec. 2.1): T_c <- T_rand_c (device, FP64
+ * [C][D][R], N(0,1) draws supplied by the caller), Sigma_c <- UBM covariance,
+ * p <- 0 and the bias m_c <- UBM mean mu_c.  Puts the context in the standard
+ * formulation: from then on bw_stats and extract_ivectors centre their
+ * statistics on m (Sec. 2), tv_mindiv whitens only (Sec. 3.1) and
+ * ubm_update_means is refused.  ivx_init_tv returns it to the augmented one.
+ * Requires ivx_set_ubm. */
+ivx_status ivx_init_tv_standard(ivx_ctx* ctx, const double* T_rand, void* stream);
+
+/* Sets the bias m [C][D] (device, FP64; copied) and puts the context in the
+ * standard formulation; m = NULL returns it to the augmented formulation.
+ * The prior offset p is not changed: the standard formulation needs p = 0
+ * (ivx_set_tv). */
+ivx_status ivx_set_bias(ivx_ctx* ctx, const double* m, void* stream);
+
+/* Reads the bias m [C][D] (device, FP64).  IVX_EINVAL in the augmented
+ * formulation. */
+ivx_status ivx_get_bias(ivx_ctx* ctx, double* m, void* stream);
+
 /* Sets / reads the TV model: T [C][D][R], Sigma [C][D][D], p [R] (device,
  * FP64).  ivx_get_tv also returns the current UBM means mu [C][D]; any output
  * pointer may be NULL. */
@@ -166,7 +185,10 @@ ivx_status ubm_posteriors(ivx_ctx* ctx, const float* X, int64_t F, ivx_precision
                           ivx_selection sel, float* gamma, int32_t* post_idx, float* post_val,
                           int32_t K, double* frame_ll, void* stream);
 
-/* Uncentred Baum-Welch statistics of U utterances (Sec. 2):
+/* Baum-Welch statistics of U utterances (Sec. 2), uncentred in the augmented
+ * formulation; in the standard formulation every term is centred on the bias
+ * first: f~_c(u) = sum_t gamma_tc (x_t - m_c), S~_c = sum_t gamma_tc
+ * (x_t - m_c)(x_t - m_c)^T (n and ll_acc are the same in both).
  *   X        [F][D] FP32 device frames, utterances concatenated.
  *   utt_off  [U+1] int64 device offsets: utt_off[0] = 0, non-decreasing,
  *            utt_off[U] = F (checked by a kernel).
@@ -199,7 +221,8 @@ ivx_status tv_mstep_accumulate(ivx_ctx* ctx, const float* n, const float* f, con
                                const float* Phi, int64_t U, const ivx_accum* acc, void* stream);
 
 /* i-vector extraction (Sec. 3.2, last paragraph): posteriors against the
- * current (possibly realigned) UBM, n and f, then eq. (4).
+ * current (possibly realigned) UBM, n and f (centred on the bias in the
+ * standard formulation), then eq. (4).
  *   phi [U][R] FP32.  X, utt_off as in bw_stats. */
 ivx_status extract_ivectors(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_t U,
                             int64_t F, ivx_precision prec, ivx_selection sel, float* phi,
@@ -225,11 +248,23 @@ ivx_status tv_mstep_solve(ivx_ctx* ctx, const ivx_accum* acc, const double* S, i
 /* Minimum-divergence re-estimation, augmented formulation (eqs. (6)-(12)),
  * from acc->h, acc->H, acc->count: G = H/U - (h/U)(h/U)^T, P1 = L_G^{-1}
  * (Cholesky whitening, method 0; other methods return IVX_EINVAL),
- * Householder P2, T_c <- T_c P1^{-1} P2^{-1}, p <- P2 P1 h. */
+ * Householder P2, T_c <- T_c P1^{-1} P2^{-1}, p <- P2 P1 h.  In the standard
+ * formulation: T_c <- T_c P1^{-1} only (see tv_mindiv_standard). */
 ivx_status tv_mindiv(ivx_ctx* ctx, const ivx_accum* acc, int method, void* stream);
 
+/* Standard-formulation minimum divergence (Sec. 3.1), from acc->h, acc->H,
+ * acc->count: G = H/U - (h/U)(h/U)^T = L_G L_G^T (method 0, Cholesky; other
+ * methods return IVX_EINVAL) and T_c <- T_c L_G (= T_c P1^{-1}).  With
+ * update_mean != 0 the bias first absorbs the i-vector mean (Sec. 5):
+ * m_c <- m_c + T_c h/U with the incoming T_c.  If G is not positive definite
+ * nothing changes and IVX_ENOTPD is recorded.  IVX_EINVAL in the augmented
+ * formulation.  tv_mindiv on a standard context equals update_mean = 0. */
+ivx_status tv_mindiv_standard(ivx_ctx* ctx, const ivx_accum* acc, int method, int update_mean,
+                              void* stream);
+
 /* Realignment (Sec. 3.2 step 5): mu_c <- p[0] * T_c[:, 0], then re-derives
- * the UBM quantities used by ubm_posteriors. */
+ * the UBM quantities used by ubm_posteriors.  Augmented formulation only
+ * (IVX_EINVAL in the standard one). */
 ivx_status ubm_update_means(ivx_ctx* ctx, void* stream);
 
 /* -------------------------------------------------------- iteration graphs */
@@ -241,6 +276,8 @@ typedef struct ivx_graph ivx_graph;
  * then bw_stats, tv_estep (with the TV precompute), tv_mstep_accumulate,
  * tv_mstep_solve (objective at the incoming parameters into objective[0]),
  * tv_mindiv (Cholesky whitening) and, if realign != 0, ubm_update_means.
+ * The formulation (augmented or standard) is the one the context holds at
+ * capture time; realign != 0 needs the augmented one.
  * Every pointer is caller-owned device memory with the layout of the
  * corresponding call; it is bound at capture time and must stay valid for
  * the life of the graph.  Capture runs on a private stream and executes

@@ -119,7 +119,7 @@ void ivx_destroy(ivx_ctx* ctx) {
   presel_free(ctx);
   void* ptrs[] = {ctx->w, ctx->mu, ctx->cov, ctx->shift, ctx->Wexp, ctx->W16, ctx->linv,
                   ctx->linv32r, ctx->cst,
-                  ctx->pairs, ctx->T, ctx->Sigma, ctx->p, ctx->cand, ctx->cM, ctx->cflag, ctx->post_idx,
+                  ctx->pairs, ctx->T, ctx->Sigma, ctx->p, ctx->bias, ctx->bias32, ctx->cand, ctx->cM, ctx->cflag, ctx->post_idx,
                   ctx->post_val, ctx->frame_ll, ctx->hist, ctx->coff, ctx->ent, ctx->partial,
                   ctx->Y32, ctx->V32, ctx->Utp, ctx->Psig, ctx->sig_logdet, ctx->Lbuf, ctx->Wbuf, ctx->Psi64,
                   ctx->bpart, ctx->bvec, ctx->llu, ctx->n_ws, ctx->f_ws, ctx->Tnew, ctx->obj_part,
@@ -177,6 +177,8 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   A(dalloc(&c->T, C * D * R));
   A(dalloc(&c->Sigma, C * D * D));
   A(dalloc(&c->p, R));
+  A(dalloc(&c->bias, C * D));
+  A(dalloc(&c->bias32, C * D));
   A(dalloc(&c->cand, F * KP));
   A(dalloc(&c->cM, F));
   A(dalloc(&c->cflag, F));
@@ -319,7 +321,43 @@ ivx_status ivx_init_tv(ivx_ctx* ctx, const double* T_rand, double p0, void* stre
   launch_init_tv(ctx, T_rand, p0, as_stream(stream));
   ctx->tv_set = true;
   ctx->tv_dirty = true;
+  ctx->standard = false;
   return after_launch("ivx_init_tv");
+}
+
+ivx_status ivx_init_tv_standard(ivx_ctx* ctx, const double* T_rand, void* stream) {
+  IVX_CHECK(ctx && T_rand, "ivx_init_tv_standard: null argument");
+  IVX_CHECK(ctx->ubm_set, "ivx_init_tv_standard: call ivx_set_ubm first");
+  if (set_device(ctx) != IVX_OK) return IVX_EDEVICE;
+  launch_init_tv_standard(ctx, T_rand, as_stream(stream));
+  ctx->tv_set = true;
+  ctx->tv_dirty = true;
+  ctx->standard = true;
+  return after_launch("ivx_init_tv_standard");
+}
+
+ivx_status ivx_set_bias(ivx_ctx* ctx, const double* m, void* stream) {
+  IVX_CHECK(ctx, "ivx_set_bias: null context");
+  if (set_device(ctx) != IVX_OK) return IVX_EDEVICE;
+  if (!m) {
+    ctx->standard = false;
+    return IVX_OK;
+  }
+  hipStream_t s = as_stream(stream);
+  IVX_HIP(hipMemcpyAsync(ctx->bias, m, sizeof(double) * ctx->C * ctx->D, hipMemcpyDeviceToDevice,
+                         s));
+  launch_bias32(ctx, s);
+  ctx->standard = true;
+  return after_launch("ivx_set_bias");
+}
+
+ivx_status ivx_get_bias(ivx_ctx* ctx, double* m, void* stream) {
+  IVX_CHECK(ctx && m, "ivx_get_bias: null argument");
+  IVX_CHECK(ctx->standard, "ivx_get_bias: the context holds the augmented formulation (no bias)");
+  if (set_device(ctx) != IVX_OK) return IVX_EDEVICE;
+  IVX_HIP(hipMemcpyAsync(m, ctx->bias, sizeof(double) * ctx->C * ctx->D, hipMemcpyDeviceToDevice,
+                         as_stream(stream)));
+  return IVX_OK;
 }
 
 ivx_status ivx_set_tv(ivx_ctx* ctx, const double* T, const double* Sigma, const double* p,
@@ -445,6 +483,8 @@ ivx_status ivx_profile_read(ivx_ctx* ctx, double* ms, int64_t* calls, int32_t n)
 ivx_status ubm_update_means(ivx_ctx* ctx, void* stream) {
   IVX_CHECK(ctx, "ubm_update_means: null context");
   IVX_CHECK(ctx->ubm_set && ctx->tv_set, "ubm_update_means: UBM and TV model required");
+  IVX_CHECK(!ctx->standard,
+            "ubm_update_means: realignment reads the augmented model (first columns of T_c)");
   if (set_device(ctx) != IVX_OK) return IVX_EDEVICE;
   {
     ProfScope ps(ctx, PK_UBM, as_stream(stream));

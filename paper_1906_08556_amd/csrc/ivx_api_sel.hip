@@ -17,7 +17,7 @@ void selector_free(ivx_ctx* ctx) {
   void* ptrs[] = {S->param, S->grad, S->adam_m, S->adam_v, S->mean, S->stdv, S->istd, S->W1b,
                   S->W2b, S->W3b, S->b3p, S->h1b, S->h2b, S->prop, S->mass, S->fb, S->fb_list,
                   S->counters, S->score, S->hist, S->coff, S->ent, S->xfb, S->xs, S->a1, S->h1,
-                  S->a2, S->h2, S->z, S->dz, S->dh1, S->dh2, S->loss_part};
+                  S->a2, S->h2, S->z, S->dz, S->dh1, S->dh2, S->loss_part, S->colpart};
   for (void* p : ptrs)
     if (p) hipFree(p);
   delete S;
@@ -176,6 +176,7 @@ ivx_status ivx_selector_set(ivx_ctx* ctx, const ivx_selector_dims* sd, const flo
     A(salloc(&S->dh1, B * H1));
     A(salloc(&S->dh2, B * H2));
     A(salloc(&S->loss_part, B));
+    A(salloc(&S->colpart, 32 * std::max<int64_t>(C, std::max(H1, H2))));
   }
   if (!ok) {
     selector_free(ctx);

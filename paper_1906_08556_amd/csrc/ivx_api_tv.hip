@@ -259,10 +259,30 @@ ivx_status tv_mindiv(ivx_ctx* ctx, const ivx_accum* acc, int method, void* strea
   }
   {
     ProfScope ps(ctx, PK_MINDIV, as_stream(stream));
-    launch_mindiv(ctx, acc, as_stream(stream));
+    launch_mindiv(ctx, acc, ctx->standard, false, as_stream(stream));
   }
   ctx->tv_dirty = true;
   return after_launch("tv_mindiv");
+}
+
+ivx_status tv_mindiv_standard(ivx_ctx* ctx, const ivx_accum* acc, int method, int update_mean,
+                              void* stream) {
+  IVX_CHECK(ctx && acc, "tv_mindiv_standard: null argument");
+  IVX_CHECK(ctx->tv_set, "tv_mindiv_standard: no TV model");
+  IVX_CHECK(ctx->standard, "tv_mindiv_standard: the context holds the augmented formulation");
+  IVX_CHECK(acc->h && acc->H && acc->count, "tv_mindiv_standard: null accumulator");
+  IVX_CHECK(method == 0, "tv_mindiv_standard: method %d not available (0 = Cholesky whitening)",
+            method);
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    set_error("tv_mindiv_standard: hipSetDevice failed");
+    return IVX_EDEVICE;
+  }
+  {
+    ProfScope ps(ctx, PK_MINDIV, as_stream(stream));
+    launch_mindiv(ctx, acc, true, update_mean != 0, as_stream(stream));
+  }
+  ctx->tv_dirty = true;
+  return after_launch("tv_mindiv_standard");
 }
 
 }  // extern "C"

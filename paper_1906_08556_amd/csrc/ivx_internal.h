@@ -101,6 +101,7 @@ struct Selector {
   float* dh1 = nullptr;     // [Bmax][H1]
   float* dh2 = nullptr;     // [Bmax][H2]
   double* loss_part = nullptr;  // [Bmax]
+  float* colpart = nullptr;     // [32][max(C, H1, H2)] column-sum partials
 };
 
 // State of the pruned alignment (Sec. 4.2): diagonal-UBM coefficients and
@@ -166,6 +167,10 @@ struct ivx_ctx {
   double* T = nullptr;      // [C][D][R]
   double* Sigma = nullptr;  // [C][D][D]
   double* p = nullptr;      // [R]
+  // standard formulation (Sec. 2.1): bias m_c, statistics centred on it
+  bool standard = false;
+  double* bias = nullptr;   // [C][D]
+  float* bias32 = nullptr;  // [C][D] FP32 copy for the first-order centring
 
   // frame-stage workspace
   int2* cand = nullptr;       // [maxF][KP] candidate (component, FP32 score bits)
@@ -250,6 +255,8 @@ namespace ivx {
 // ---- k_ubm.hip
 void launch_ubm_prepare(ivx_ctx* ctx, hipStream_t s);
 void launch_init_tv(ivx_ctx* ctx, const double* T_rand, double p0, hipStream_t s);
+void launch_init_tv_standard(ivx_ctx* ctx, const double* T_rand, hipStream_t s);
+void launch_bias32(ivx_ctx* ctx, hipStream_t s);
 void launch_update_means(ivx_ctx* ctx, hipStream_t s);
 
 // ---- k_frame.hip

@@ -11,6 +11,10 @@
 //  k_mindiv_setup     one workgroup: G = H/U - (h/U)(h/U)^T = L_G L_G^T,
 //                     g = L_G^{-1} h/U, Householder vector a, p = P2 g and
 //                     M = P1^{-1} P2^{-1} = L_G P2.
+//                     Standard formulation (Sec. 3.1): M = P1^{-1} = L_G
+//                     alone, p stays 0.
+//  k_bias_update      standard formulation, optional (Sec. 5):
+//                     m_c <- m_c + T_c h/U with the T of the M-step.
 //  k_apply_M          T_c <- T_c M for all c (FP64 GEMM, LDS tiles).
 #include <cmath>
 
@@ -180,12 +184,13 @@ k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
 //   G = H/U - (h/U)(h/U)^T (tile-packed) = L_G L_G^T  (chol_tp64, MFMA)
 //   g = L_G^{-1} h/U, Householder vector a from g, p = P2 g,
 //   M = P1^{-1} P2^{-1} = L_G P2 = L_G - 2 (L_G a) a^T   ([R][R] row-major).
-// On failure M = I and p is left unchanged.
+// Standard formulation: M = L_G and nothing else (p is not touched).
+// On failure M = I, p is left unchanged and h/U (vec[0..R)) is set to 0.
 __global__ void __launch_bounds__(256)
 k_mindiv_setup(int R, int nb, const double* __restrict__ hsum, const double* __restrict__ Htp,
-               const double* __restrict__ count, double* __restrict__ G, double* __restrict__ Winv,
-               double* __restrict__ M, double* __restrict__ vec, double* __restrict__ p,
-               int* __restrict__ err) {
+               const double* __restrict__ count, int standard, double* __restrict__ G,
+               double* __restrict__ Winv, double* __restrict__ M, double* __restrict__ vec,
+               double* __restrict__ p, int* __restrict__ err) {
   extern __shared__ double sm[];
   double* dg = sm;          // [256]
   double* pan = sm + 256;   // [(nb - 1) * 256]
@@ -219,6 +224,14 @@ k_mindiv_setup(int R, int nb, const double* __restrict__ hsum, const double* __r
   if (bad) {  // leave T and p unchanged: M = I
     if (tid == 0) raise_error(err, IVX_ENOTPD, PK_MINDIV, bad - 1);
     for (int e = tid; e < R * R; e += 256) M[e] = (e / R == e % R) ? 1.0 : 0.0;
+    for (int i = tid; i < R; i += 256) hb[i] = 0.0;
+    return;
+  }
+  if (standard) {  // M = P1^{-1} = L_G
+    for (int e = tid; e < R * R; e += 256) {
+      const int i = e / R, j = e - i * R;
+      M[e] = (j <= i) ? G[tp_off(i >> 4, j >> 4) + (i & 15) * 16 + (j & 15)] : 0.0;
+    }
     return;
   }
   // g = L^{-1} hb, blocked: g_k = W_k r_k, then r_i -= L_ik g_k (i > k)
@@ -292,6 +305,20 @@ k_mindiv_setup(int R, int nb, const double* __restrict__ hsum, const double* __r
     const double lij = (j <= i) ? G[tp_off(i >> 4, j >> 4) + (i & 15) * 16 + (j & 15)] : 0.0;
     M[e] = lij - 2.0 * v[i] * a[j];
   }
+}
+
+// bias[row] += T[row, :] . hb over rows = C * D, one wave per row
+__global__ void __launch_bounds__(256)
+k_bias_update(const double* __restrict__ T, const double* __restrict__ hb, int64_t rows, int R,
+              double* __restrict__ bias) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const double* t = T + row * R;
+  double s = 0.0;
+  for (int r = lane; r < R; r += 64) s += t[r] * hb[r];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) bias[row] += s;
 }
 
 // Tn[rows x R] = T[rows x R] * M[R x R], 64 x 64 tiles, 4 x 4 outputs per thread
@@ -371,12 +398,18 @@ void launch_mstep_solve(ivx_ctx* ctx, const ivx_accum* acc, const double* S, int
       ctx->Sigma, ctx->Winv, status, ctx->dev_err);
 }
 
-void launch_mindiv(ivx_ctx* ctx, const ivx_accum* acc, hipStream_t s) {
+void launch_mindiv(ivx_ctx* ctx, const ivx_accum* acc, bool standard, bool update_mean,
+                   hipStream_t s) {
   const int nb = (ctx->R + 15) / 16;
   k_mindiv_setup<<<1, 256, sizeof(double) * 256 * nb, s>>>(
-      ctx->R, nb, acc->h, acc->H, acc->count, ctx->Gmat, ctx->Winv, ctx->Mmat, ctx->mvec, ctx->p,
-      ctx->dev_err);
+      ctx->R, nb, acc->h, acc->H, acc->count, standard ? 1 : 0, ctx->Gmat, ctx->Winv, ctx->Mmat,
+      ctx->mvec, ctx->p, ctx->dev_err);
   const int64_t rows = (int64_t)ctx->C * ctx->D;
+  if (standard && update_mean) {  // reads T before the whitened copy replaces it
+    k_bias_update<<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(ctx->T, ctx->mvec, rows, ctx->R,
+                                                            ctx->bias);
+    launch_bias32(ctx, s);
+  }
   dim3 grid((unsigned)((ctx->R + 63) / 64), (unsigned)((rows + 63) / 64));
   k_apply_M<<<grid, 256, 0, s>>>(ctx->T, ctx->Mmat, rows, ctx->R, ctx->Tnew);
   // copy back on the stream (no host-side pointer swap, so a captured graph

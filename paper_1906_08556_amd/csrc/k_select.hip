@@ -886,11 +886,24 @@ __global__ void k_relu_grad(float* __restrict__ d, const float* __restrict__ a, 
     if (!(a[i] > 0.0f)) d[i] = 0.0f;
 }
 
-__global__ void k_colsum(const float* __restrict__ d, int B, int N, float* __restrict__ out) {
+// Column sums of d [B][N] in two deterministic passes: 32 row blocks write
+// partial sums, then one thread per column adds them.
+constexpr int CS_PARTS = 32;
+__global__ void k_colsum_part(const float* __restrict__ d, int B, int N, float* __restrict__ part) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int p = blockIdx.y;
+  const int b0 = (int)((int64_t)B * p / CS_PARTS), b1 = (int)((int64_t)B * (p + 1) / CS_PARTS);
+  float s = 0.0f;
+  for (int b = b0; b < b1; ++b) s += d[(int64_t)b * N + n];
+  part[(int64_t)p * N + n] = s;
+}
+
+__global__ void k_colsum_final(const float* __restrict__ part, int N, float* __restrict__ out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
   float s = 0.0f;
-  for (int b = 0; b < B; ++b) s += d[(int64_t)b * N + n];
+  for (int p = 0; p < CS_PARTS; ++p) s += part[(int64_t)p * N + n];
   out[n] = s;
 }
 
@@ -1122,6 +1135,10 @@ bool launch_selector_grad(ivx_ctx* ctx, const float* X, int64_t F, const int64_t
   float* P = S.param;
   float* G = S.grad;
   ProfScope ps(ctx, PK_SEL_TRAIN, s);
+  auto colsum = [&](const float* d, int N, float* out) {
+    k_colsum_part<<<dim3((N + 255) / 256, CS_PARTS), 256, 0, s>>>(d, B, N, S.colpart);
+    k_colsum_final<<<(N + 255) / 256, 256, 0, s>>>(S.colpart, N, out);
+  };
   k_train_gather<<<256, 256, 0, s>>>(X, D, fidx, B, F, S.mean, S.istd, S.xs, ctx->dev_err);
   bool ok = true;
   auto gemm = [&](const float* A, int64_t lda, bool ta, const float* Bm, int64_t ldb, bool tb,
@@ -1149,15 +1166,15 @@ bool launch_selector_grad(ivx_ctx* ctx, const float* X, int64_t F, const int64_t
                                              S.loss_part);
   // backward
   gemm(S.dz, C, true, S.h2, H2, false, G + S.oW3, H2, C, H2, B);        // dW3 = dz^T h2
-  k_colsum<<<(C + 255) / 256, 256, 0, s>>>(S.dz, B, C, G + S.ob3);
+  colsum(S.dz, C, G + S.ob3);
   gemm(S.dz, C, false, P + S.oW3, H2, false, S.dh2, H2, B, H2, C);      // dh2 = dz W3
   k_relu_grad<<<512, 256, 0, s>>>(S.dh2, S.a2, (int64_t)B * H2);
   gemm(S.dh2, H2, true, S.h1, H1, false, G + S.oW2, H1, H2, H1, B);     // dW2 = da2^T h1
-  k_colsum<<<(H2 + 255) / 256, 256, 0, s>>>(S.dh2, B, H2, G + S.ob2);
+  colsum(S.dh2, H2, G + S.ob2);
   gemm(S.dh2, H2, false, P + S.oW2, H1, false, S.dh1, H1, B, H1, H2);   // dh1 = da2 W2
   k_relu_grad<<<512, 256, 0, s>>>(S.dh1, S.a1, (int64_t)B * H1);
   gemm(S.dh1, H1, true, S.xs, D, false, G + S.oW1, D, H1, D, B);        // dW1 = da1^T xs
-  k_colsum<<<(H1 + 255) / 256, 256, 0, s>>>(S.dh1, B, H1, G + S.ob1);
+  colsum(S.dh1, H1, G + S.ob1);
   if (loss) {
     k_zero_f64<<<1, 64, 0, s>>>(loss);
     launch_sum_f64(ctx, S.loss_part, B, loss, s);

@@ -7,6 +7,10 @@
 //    posterior entries are bucketed by component with a counting sort
 //    (per-block histograms, a scan, a scatter); one workgroup per component
 //    then accumulates the packed upper triangle in FP64 registers.
+//  Standard formulation (Sec. 2): with a bias m set, every term is centred
+//    before it is accumulated, f~_c(u) = sum_t gamma_tc (x_t - m_c) and
+//    S~_c = sum_t gamma_tc (x_t - m_c)(x_t - m_c)^T, so no large uncentred
+//    sums are formed and cancelled afterwards.
 #include "ivx_internal.h"
 
 namespace ivx {
@@ -19,7 +23,8 @@ template <int NFB>
 __global__ void __launch_bounds__(256)
 k_stats_nf(const float* __restrict__ X, const int64_t* __restrict__ utt_off, int64_t U, int64_t F,
            int D, int C, const int* __restrict__ post_idx, const float* __restrict__ post_val,
-           float* __restrict__ n, float* __restrict__ f, int* __restrict__ err) {
+           const float* __restrict__ mb, float* __restrict__ n, float* __restrict__ f,
+           int* __restrict__ err) {
   extern __shared__ float acc[];  // [NFB][D+1]: n at column 0, f at 1..D
   const int DS = D + 1;
   const int64_t u = blockIdx.x;
@@ -46,7 +51,9 @@ k_stats_nf(const float* __restrict__ X, const int64_t* __restrict__ utt_off, int
       mask &= mask - 1;
       const int c = __shfl(id, s);
       const float gm = __shfl(gv, s);
-      if (lane <= D) atomicAdd(&acc[(c - c0) * DS + lane], gm * xv);
+      // centred term x - m_c (FP32 copy of the bias; lane 0 carries the count)
+      const float xc = (mb && lane >= 1 && lane <= D) ? xv - mb[(size_t)c * D + lane - 1] : xv;
+      if (lane <= D) atomicAdd(&acc[(c - c0) * DS + lane], gm * xc);
     }
   }
   __syncthreads();
@@ -135,12 +142,15 @@ k_scatter(int64_t F, int C, const int* __restrict__ post_idx, const float* __res
 }
 
 // S_c += sum over the component's entries of gamma x x^T, packed upper
-// triangle (i <= j, row by row), FP64.
+// triangle (i <= j, row by row), FP64.  ST = float stages the frames as they
+// are; ST = double stages x - m_c (bias mb, FP64) for the centred form.
 constexpr int SB = 32;  // entries staged per step
+template <typename ST>
 __global__ void __launch_bounds__(256)
 k_S_accum(const float* __restrict__ X, int D, const int* __restrict__ coff,
-          const int2* __restrict__ ent, double* __restrict__ S_acc) {
-  extern __shared__ float xsm[];  // [SB][D]
+          const int2* __restrict__ ent, const double* __restrict__ mb, double* __restrict__ S_acc) {
+  extern __shared__ __align__(8) unsigned char s_raw[];
+  ST* xsm = reinterpret_cast<ST*>(s_raw);  // [SB][D]
   __shared__ float gsm[SB];
   const int c = blockIdx.x;
   const int Dp = D * (D + 1) / 2;
@@ -166,13 +176,17 @@ k_S_accum(const float* __restrict__ X, int D, const int* __restrict__ coff,
     __syncthreads();
     for (int i = tid; i < ne * D; i += 256) {
       const int e = i / D, d = i - e * D;
-      xsm[i] = X[(int64_t)ent[eb + e].x * D + d];
+      const float x = X[(int64_t)ent[eb + e].x * D + d];
+      if constexpr (sizeof(ST) == sizeof(double))
+        xsm[i] = (double)x - mb[(size_t)c * D + d];
+      else
+        xsm[i] = x;
     }
     if (tid < ne) gsm[tid] = __int_as_float(ent[eb + tid].y);
     __syncthreads();
     for (int e = 0; e < ne; ++e) {
       const double g = (double)gsm[e];
-      const float* xe = xsm + e * D;
+      const ST* xe = xsm + e * D;
 #pragma unroll
       for (int m = 0; m < MAXM; ++m)
         acc[m] += g * ((double)xe[ii[m]] * (double)xe[jj[m]]);
@@ -218,19 +232,20 @@ __global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ pa
 void launch_stats_nf(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_t U, int64_t F,
                      float* n, float* f, hipStream_t s) {
   if (U <= 0) return;
+  const float* mb = ctx->standard ? ctx->bias32 : nullptr;
   if (ctx->tune.nf_block == 128) {
     constexpr int NFB = 128;
     dim3 grid((unsigned)U, (unsigned)((ctx->C + NFB - 1) / NFB));
     const size_t lds = sizeof(float) * NFB * (ctx->D + 1);
     k_stats_nf<NFB><<<grid, 256, lds, s>>>(X, utt_off, U, F, ctx->D, ctx->C, ctx->post_idx,
-                                           ctx->post_val, n, f, ctx->dev_err);
+                                           ctx->post_val, mb, n, f, ctx->dev_err);
     return;
   }
   constexpr int NFB = 256;
   dim3 grid((unsigned)U, (unsigned)((ctx->C + NFB - 1) / NFB));
   const size_t lds = sizeof(float) * NFB * (ctx->D + 1);
   k_stats_nf<NFB><<<grid, 256, lds, s>>>(X, utt_off, U, F, ctx->D, ctx->C, ctx->post_idx,
-                                    ctx->post_val, n, f, ctx->dev_err);
+                                         ctx->post_val, mb, n, f, ctx->dev_err);
 }
 
 void launch_stats_S(ivx_ctx* ctx, const float* X, int64_t F, double* S_acc, hipStream_t s) {
@@ -240,7 +255,12 @@ void launch_stats_S(ivx_ctx* ctx, const float* X, int64_t F, double* S_acc, hipS
   k_hist<<<nb, 256, ldsc, s>>>(F, ctx->C, ctx->post_idx, ctx->hist);
   k_hist_scan<<<1, 1024, 0, s>>>(nb, ctx->C, ctx->hist, ctx->coff);
   k_scatter<<<nb, 256, ldsc, s>>>(F, ctx->C, ctx->post_idx, ctx->post_val, ctx->hist, ctx->ent);
-  k_S_accum<<<ctx->C, 256, sizeof(float) * SB * ctx->D, s>>>(X, ctx->D, ctx->coff, ctx->ent, S_acc);
+  if (ctx->standard)
+    k_S_accum<double><<<ctx->C, 256, sizeof(double) * SB * ctx->D, s>>>(X, ctx->D, ctx->coff,
+                                                                       ctx->ent, ctx->bias, S_acc);
+  else
+    k_S_accum<float><<<ctx->C, 256, sizeof(float) * SB * ctx->D, s>>>(X, ctx->D, ctx->coff,
+                                                                     ctx->ent, nullptr, S_acc);
 }
 
 void launch_hist_scan(int nb, int C, int* hist, int* coff, hipStream_t s) {

@@ -175,6 +175,33 @@ __global__ void k_init_tv(const double* __restrict__ T_rand, const double* __res
   }
 }
 
+// Standard initialisation (Sec. 2.1): T <- T_rand, Sigma <- UBM covariances,
+// p <- 0, bias m <- UBM means (FP64 and its FP32 copy).
+__global__ void k_init_tv_standard(const double* __restrict__ T_rand,
+                                   const double* __restrict__ mu, const double* __restrict__ cov,
+                                   int C, int D, int R, double* __restrict__ T,
+                                   double* __restrict__ Sigma, double* __restrict__ p,
+                                   double* __restrict__ bias, float* __restrict__ bias32) {
+  const int64_t nT = (int64_t)C * D * R, nS = (int64_t)C * D * D;
+  const int64_t n = nT > nS ? nT : nS;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < nT) T[i] = T_rand[i];
+    if (i < nS) Sigma[i] = cov[i];
+    if (i < R) p[i] = 0.0;
+    if (i < (int64_t)C * D) {
+      bias[i] = mu[i];
+      bias32[i] = (float)mu[i];
+    }
+  }
+}
+
+__global__ void k_bias32(const double* __restrict__ bias, int64_t n, float* __restrict__ bias32) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bias32[i] = (float)bias[i];
+}
+
 __global__ void k_update_means(const double* __restrict__ T, const double* __restrict__ p, int C,
                                int D, int R, double* __restrict__ mu) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -194,6 +221,16 @@ void launch_ubm_prepare(ivx_ctx* ctx, hipStream_t s) {
 void launch_init_tv(ivx_ctx* ctx, const double* T_rand, double p0, hipStream_t s) {
   k_init_tv<<<1024, 256, 0, s>>>(T_rand, ctx->mu, ctx->cov, p0, ctx->C, ctx->D, ctx->R, ctx->T,
                                  ctx->Sigma, ctx->p);
+}
+
+void launch_init_tv_standard(ivx_ctx* ctx, const double* T_rand, hipStream_t s) {
+  k_init_tv_standard<<<1024, 256, 0, s>>>(T_rand, ctx->mu, ctx->cov, ctx->C, ctx->D, ctx->R,
+                                          ctx->T, ctx->Sigma, ctx->p, ctx->bias, ctx->bias32);
+}
+
+void launch_bias32(ivx_ctx* ctx, hipStream_t s) {
+  const int64_t n = (int64_t)ctx->C * ctx->D;
+  k_bias32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ctx->bias, n, ctx->bias32);
 }
 
 void launch_update_means(ivx_ctx* ctx, hipStream_t s) {

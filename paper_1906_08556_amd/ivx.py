@@ -66,6 +66,9 @@ PROTOTYPES = {
     "ivx_tp_size": (_I64, [_I32]),
     "ivx_set_ubm": (_I32, [_P, _P, _P, _P, _P]),
     "ivx_init_tv": (_I32, [_P, _P, _F64, _P]),
+    "ivx_init_tv_standard": (_I32, [_P, _P, _P]),
+    "ivx_set_bias": (_I32, [_P, _P, _P]),
+    "ivx_get_bias": (_I32, [_P, _P, _P]),
     "ivx_set_tv": (_I32, [_P, _P, _P, _P, _P]),
     "ivx_get_tv": (_I32, [_P, _P, _P, _P, _P, _P]),
     "ubm_posteriors": (_I32, [_P, _P, _I64, _I32, _I32, _P, _P, _P, _I32, _P, _P]),
@@ -75,6 +78,7 @@ PROTOTYPES = {
     "extract_ivectors": (_I32, [_P, _P, _P, _I64, _I64, _I32, _I32, _P, _P]),
     "tv_mstep_solve": (_I32, [_P, ctypes.POINTER(Accum), _P, ctypes.c_int, _P, _P, _P, _P]),
     "tv_mindiv": (_I32, [_P, ctypes.POINTER(Accum), ctypes.c_int, _P]),
+    "tv_mindiv_standard": (_I32, [_P, ctypes.POINTER(Accum), ctypes.c_int, ctypes.c_int, _P]),
     "ubm_update_means": (_I32, [_P, _P]),
     "ivx_graph_create_em": (_I32, [_P, _P, _P, _I64, _I64, _I32, _P, _P, _P, _P, _P,
                                    ctypes.POINTER(Accum), _P, _P, _P, ctypes.c_int, ctypes.c_int,
@@ -185,6 +189,21 @@ class Context:
         self._check(self.lib.ivx_init_tv(self.h, self._p(T_rand, torch.float64, "T_rand"),
                                          float(p0), _stream(stream)))
 
+    def init_tv_standard(self, T_rand, stream=None):
+        self._check(self.lib.ivx_init_tv_standard(
+            self.h, self._p(T_rand, torch.float64, "T_rand"), _stream(stream)))
+
+    def set_bias(self, m, stream=None):
+        """m [C][D] FP64 device tensor (standard formulation), or None (augmented)."""
+        self._check(self.lib.ivx_set_bias(self.h, self._p(m, torch.float64, "m"),
+                                          _stream(stream)))
+
+    def get_bias(self, stream=None):
+        m = torch.empty((self.C, self.D), dtype=torch.float64, device=self.device)
+        self._check(self.lib.ivx_get_bias(self.h, self._p(m, torch.float64, "m"),
+                                          _stream(stream)))
+        return m
+
     def set_tv(self, T, Sigma, p, stream=None):
         f = torch.float64
         self._check(self.lib.ivx_set_tv(self.h, self._p(T, f, "T"), self._p(Sigma, f, "Sigma"),
@@ -256,6 +275,11 @@ class Context:
     def tv_mindiv(self, acc: "Accumulators", method=0, stream=None):
         s = acc.struct()
         self._check(self.lib.tv_mindiv(self.h, ctypes.byref(s), int(method), _stream(stream)))
+
+    def tv_mindiv_standard(self, acc: "Accumulators", update_mean=False, method=0, stream=None):
+        s = acc.struct()
+        self._check(self.lib.tv_mindiv_standard(self.h, ctypes.byref(s), int(method),
+                                                int(bool(update_mean)), _stream(stream)))
 
     def ubm_update_means(self, stream=None):
         self._check(self.lib.ubm_update_means(self.h, _stream(stream)))
