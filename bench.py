@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--learned-steps", type=int, default=3000,
                     help="training steps of the learned selector (0: skip the learned form)")
     ap.add_argument("--learned-batch", type=int, default=4096)
+    ap.add_argument("--no-standard", action="store_true",
+                    help="skip the standard-formulation timing")
     ap.add_argument("--no-pruned", action="store_true",
                     help="skip the pruned alignment (diagonal-UBM top-20, drop < 0.025)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -259,11 +261,14 @@ def main():
     cov_d = torch.from_numpy(wl.cov).to(dev)
     T0_d = torch.from_numpy(wl.T_init).to(dev)
 
-    def reset_model():
+    def reset_model(form="augmented"):
         ctx.set_ubm(w_d, mu_d, cov_d)
-        ctx.init_tv(T0_d, 100.0)
+        if form == "standard":
+            ctx.init_tv_standard(T0_d)
+        else:
+            ctx.init_tv(T0_d, 100.0)
 
-    def step(prec, e=None, sel=ivx.IVX_SEL_ALL):
+    def step(prec, e=None, sel=ivx.IVX_SEL_ALL, form="augmented"):
         S.zero_()
         ll_frames.zero_()
         ll_utt.zero_()
@@ -276,21 +281,22 @@ def main():
         ctx.tv_estep(n, f, phi, Phi=Phi, ll_acc=ll_utt, prec=prec)
         ctx.tv_mstep_accumulate(n, f, phi, Phi, acc)
         ctx.tv_mstep_solve(acc, S, update_sigma=True, ll_sum=ll_utt, objective=obj)
-        ctx.tv_mindiv(acc)
-        ctx.ubm_update_means()
+        ctx.tv_mindiv(acc)          # the context's formulation decides the form
+        if form == "augmented":
+            ctx.ubm_update_means()
         if e is not None:
             e[2].record()
 
-    def timed(prec, steps, warmup, sel=ivx.IVX_SEL_ALL):
-        reset_model()
+    def timed(prec, steps, warmup, sel=ivx.IVX_SEL_ALL, form="augmented"):
+        reset_model(form)
         for _ in range(warmup):
-            step(prec, sel=sel)
+            step(prec, sel=sel, form=form)
         ctx.sync_status()
         ctx.profile_enable(8192)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(steps):
-            step(prec, ev[i], sel=sel)
+            step(prec, ev[i], sel=sel, form=form)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         phase = {"frame": sum(ev[i][0].elapsed_time(ev[i][1]) for i in range(steps)),
@@ -392,6 +398,20 @@ def main():
         graph = {"utts_per_s": round(U * K / elg, 3), "ms_per_step": round(elg * 1e3 / K, 3)}
         log(f"[bench] graph replay: {graph}")
 
+    standard = None
+    if not args.no_standard:
+        # Sec. 2.1 model with centred statistics, Sigma update and the
+        # P1-only minimum divergence; no realignment
+        els, phs, profs = timed(0, K, args.warmup, form="standard")
+        standard = {"utts_per_s": round(U * K / els, 3), "ms_per_step": round(els * 1e3 / K, 3),
+                    "tv_em_utts_per_s": round(U * K / (phs["em"] / 1e3), 3),
+                    "stats_S_ms_per_step": round(profs["stats_S"][0] / K, 3),
+                    "stats_nf_ms_per_step": round(profs["stats_nf"][0] / K, 3),
+                    "objective_after_last_step": obj.item(),
+                    "step": "posteriors+centred n/f/S+E-step(p=0)+accumulate+M-step(T,Sigma)"
+                            "+min-div(P1)"}
+        log(f"[bench] standard formulation: {standard}")
+
     pruned = None
     if not args.no_pruned:
         ctx.pruned_set(20, 0.025)
@@ -448,6 +468,7 @@ def main():
         "tuning": tuning,
         "bf16_form": bf16,
         "graph_replay": graph,
+        "standard_formulation": standard,
         "pruned_alignment": pruned,
         "learned_selection": learned,
         "cpu_baseline": cpu,

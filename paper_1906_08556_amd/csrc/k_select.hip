@@ -431,8 +431,8 @@ __global__ void k_diag_prepare(const double* __restrict__ w, const double* __res
 
 // Diagonal-UBM scores of every (frame, component) on FP32 MFMA and the k best
 // components per frame (ties to the lower index).  One workgroup per 128
-// frames loops over all components 256 at a time (W chunks of 8 features
-// staged through LDS as in k_frame_tile); after each 256-component tile the
+// frames loops over all components 128 at a time (W chunks of 8 features
+// staged through LDS as in k_frame_tile); after each 128-component tile the
 // two lane-halves holding a frame insert the tile's scores that beat their
 // KM-th into a sorted list in registers; at the end the two lists are merged
 // by counting ranks in LDS.  prop[t][0..k): the k best, best first.
