@@ -51,6 +51,11 @@ def parse():
     ap.add_argument("--learned-batch", type=int, default=4096)
     ap.add_argument("--no-standard", action="store_true",
                     help="skip the standard-formulation timing")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the streamed-from-host timing")
+    ap.add_argument("--stream-batch-utts", type=int, default=500)
+    ap.add_argument("--stream-batch-frames", type=int, default=600_000)
+    ap.add_argument("--stream-loaders", type=int, default=4)
     ap.add_argument("--no-pruned", action="store_true",
                     help="skip the pruned alignment (diagonal-UBM top-20, drop < 0.025)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -412,6 +417,65 @@ def main():
                             "+min-div(P1)"}
         log(f"[bench] standard formulation: {standard}")
 
+    streamed = None
+    if not args.no_stream:
+        # the same iteration with the frames left in host memory: batches of
+        # utterances stream through pinned slots while the previous batch
+        # computes; a context sized for one batch, not for the corpus
+        bu, bfr = args.stream_batch_utts, args.stream_batch_frames
+        ctx2 = ivx.Context(C, D, R, bu, bfr)
+        ctx2.tuning_set(**ctx.tuning_get())
+        st = ivx.Stream(ctx2, bu, bfr, loaders=args.stream_loaders, slots=4)
+        nb = len(ivx.plan_batches(wl.utt_off, bu, bfr)) - 1
+        S2 = torch.zeros_like(S)
+        llf2, llu2, obj2 = (torch.zeros(1, dtype=torch.float64, device=dev) for _ in range(3))
+        acc2 = ctx2.new_accum()
+
+        def reset2():
+            ctx2.set_ubm(w_d, mu_d, cov_d)
+            ctx2.init_tv(T0_d, 100.0)
+
+        def sstep():
+            S2.zero_()
+            llf2.zero_()
+            llu2.zero_()
+            acc2.zero_()
+            st.em_pass(wl.utt_off, acc2, X=wl.X, S_acc=S2, ll_frames=llf2, ll_utts=llu2)
+            ctx2.tv_mstep_solve(acc2, S2, update_sigma=True, ll_sum=llu2, objective=obj2)
+            ctx2.tv_mindiv(acc2)
+            ctx2.ubm_update_means()
+
+        reset2()
+        sstep()
+        ctx2.sync_status()
+        reset_model()
+        step(0)
+        ctx.sync_status()
+        obj_res, obj_str = obj.item(), obj2.item()
+        T_res, T_str = ctx.get_tv()[0], ctx2.get_tv()[0]
+        t_rel = ((T_str - T_res).norm() / T_res.norm()).item()
+        reset2()
+        for _ in range(args.warmup):
+            sstep()
+        ctx2.sync_status()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            sstep()
+        torch.cuda.synchronize()
+        els = time.perf_counter() - t0
+        ctx2.sync_status()
+        streamed = {"utts_per_s": round(U * K / els, 3), "ms_per_step": round(els * 1e3 / K, 3),
+                    "batches_per_step": nb, "batch_limits": {"utterances": bu, "frames": bfr},
+                    "loaders": args.stream_loaders, "host_bytes_per_step": int(wl.X.nbytes),
+                    "vs_resident_first_iteration": {
+                        "objective_rel_diff": abs(obj_str - obj_res) / abs(obj_res),
+                        "T_rel_diff": t_rel}}
+        log(f"[bench] streamed from host: {streamed}")
+        st.close()
+        del acc2, S2
+        ctx2.close()
+
     pruned = None
     if not args.no_pruned:
         ctx.pruned_set(20, 0.025)
@@ -469,6 +533,7 @@ def main():
         "bf16_form": bf16,
         "graph_replay": graph,
         "standard_formulation": standard,
+        "streamed_from_host": streamed,
         "pruned_alignment": pruned,
         "learned_selection": learned,
         "cpu_baseline": cpu,

@@ -408,6 +408,73 @@ ivx_status ivx_tuning_set(ivx_ctx* ctx, const ivx_tuning* t);
 ivx_status ivx_profile_enable(ivx_ctx* ctx, int32_t capacity);
 ivx_status ivx_profile_read(ivx_ctx* ctx, double* ms, int64_t* calls, int32_t n);
 
+/* ------------------------------------------------ streaming host pipeline */
+
+/* Data loaders and fixed-size batches of Sec. 4.2 (Fig. 1): utterances held
+ * in host memory (or produced on demand by a frame source) are cut into runs
+ * of consecutive utterances, copied by loader threads into pinned host slots,
+ * uploaded on a copy stream into one of two device buffers and processed on
+ * the caller's stream while the next batch is in flight.  Device memory is
+ * set by the batch limits, not by the corpus size. */
+
+/* Greedy batch plan (host only, no GPU needed): consecutive utterances are
+ * added to a batch until one more would exceed max_utts utterances or
+ * max_frames frames.  utt_off [U+1] host, utt_off[0] = 0, non-decreasing.
+ * starts [cap] receives the first utterance of each batch followed by U;
+ * *nbatches receives the number of batches (also when cap is too small, which
+ * returns IVX_EINVAL).  IVX_EINVAL if an utterance is longer than max_frames. */
+ivx_status ivx_plan_batches(const int64_t* utt_off, int64_t U, int32_t max_utts,
+                            int64_t max_frames, int64_t* starts, int64_t cap, int64_t* nbatches);
+
+typedef struct ivx_stream ivx_stream;
+
+/* max_batch_utts / max_batch_frames: batch limits, at most the context's
+ * max_batch_utts / max_batch_frames; loaders: host threads (1-64) filling
+ * slots; slots: pinned host buffers of one batch each (2-16). */
+typedef struct {
+  int32_t max_batch_utts;
+  int64_t max_batch_frames;
+  int32_t loaders;
+  int32_t slots;
+} ivx_stream_config;
+
+/* A frame source writes the frames of utterances [u0, u1) (host offsets
+ * utt_off as given to the pass) into X_dst, [utt_off[u1] - utt_off[u0]][D]
+ * FP32, and returns 0 (anything else stops the pass with IVX_EINVAL).  It is
+ * called from the loader threads, several at a time. */
+typedef int32_t (*ivx_frame_source)(void* user, int64_t u0, int64_t u1, const int64_t* utt_off,
+                                    float* X_dst);
+
+/* Allocates the pinned slots, the two device frame buffers and the per-batch
+ * n, f, phi, Phi workspace for `ctx` (which must outlive the stream object).
+ * IVX_EINVAL for limits outside the context's, IVX_ENOMEM if allocation fails. */
+ivx_status ivx_stream_create(ivx_ctx* ctx, const ivx_stream_config* cfg, ivx_stream** out);
+void ivx_stream_destroy(ivx_stream* st);
+
+/* Statistics, E-step and accumulation of one EM pass over host-resident
+ * utterances: per batch bw_stats (adding to S_acc and ll_frames), tv_estep
+ * (adding to ll_utts) and tv_mstep_accumulate (adding to acc), exactly the
+ * calls a caller would make, on `stream`.  The frames come from X [F][D] FP32
+ * host memory (F = utt_off[U]) or from `src` (exactly one of the two).
+ * phi_out [U][R] FP32 device receives every utterance's i-vector, or NULL.
+ * S_acc, ll_frames, ll_utts may be NULL as in the calls above.  Returns once
+ * every batch has been uploaded and issued (X is no longer read); results are
+ * complete when `stream` completes.  Follows the context's formulation and
+ * any selection set up on it.  Passes on one stream object are ordered among
+ * themselves on the GPU whatever streams they are issued on: a pass waits for
+ * the previous pass's batches before it reuses their device buffers. */
+ivx_status ivx_stream_em_pass(ivx_stream* st, const float* X, ivx_frame_source src,
+                              void* src_user, const int64_t* utt_off, int64_t U,
+                              ivx_precision prec, ivx_selection sel, double* S_acc,
+                              double* ll_frames, double* ll_utts, const ivx_accum* acc,
+                              float* phi_out, void* stream);
+
+/* i-vector extraction of host-resident utterances in batches (as
+ * extract_ivectors per batch): phi [U][R] FP32 device. */
+ivx_status ivx_stream_extract(ivx_stream* st, const float* X, ivx_frame_source src,
+                              void* src_user, const int64_t* utt_off, int64_t U,
+                              ivx_precision prec, ivx_selection sel, float* phi, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@ import ctypes
 import os
 from typing import Optional
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -54,8 +55,15 @@ class Accum(ctypes.Structure):
                 ("h", ctypes.c_void_p), ("H", ctypes.c_void_p), ("count", ctypes.c_void_p)]
 
 
+class StreamConfig(ctypes.Structure):
+    _fields_ = [("max_batch_utts", ctypes.c_int32), ("max_batch_frames", ctypes.c_int64),
+                ("loaders", ctypes.c_int32), ("slots", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _I32, _I64, _F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+# int32 (void* user, int64 u0, int64 u1, const int64* utt_off, float* X_dst)
+FrameSource = ctypes.CFUNCTYPE(ctypes.c_int32, _P, _I64, _I64, ctypes.POINTER(_I64), _P)
 
 # name -> (restype, argtypes)
 PROTOTYPES = {
@@ -97,6 +105,12 @@ PROTOTYPES = {
     "ivx_autotune": (_I32, [_P, _P, _P, _I64, _I64, ctypes.POINTER(Tuning), _P]),
     "ivx_tuning_get": (_I32, [_P, ctypes.POINTER(Tuning)]),
     "ivx_tuning_set": (_I32, [_P, ctypes.POINTER(Tuning)]),
+    "ivx_plan_batches": (_I32, [_P, _I64, _I32, _I64, _P, _I64, ctypes.POINTER(_I64)]),
+    "ivx_stream_create": (_I32, [_P, ctypes.POINTER(StreamConfig), ctypes.POINTER(_P)]),
+    "ivx_stream_destroy": (None, [_P]),
+    "ivx_stream_em_pass": (_I32, [_P, _P, FrameSource, _P, _P, _I64, _I32, _I32, _P, _P, _P,
+                                  ctypes.POINTER(Accum), _P, _P]),
+    "ivx_stream_extract": (_I32, [_P, _P, FrameSource, _P, _P, _I64, _I32, _I32, _P, _P]),
     "ivx_profile_enable": (_I32, [_P, _I32]),
     "ivx_profile_read": (_I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
 }
@@ -402,6 +416,92 @@ class EMGraph:
     def close(self):
         if getattr(self, "h", None):
             self.ctx.lib.ivx_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _host(a, dtype, name):
+    if not isinstance(a, np.ndarray) or a.dtype != dtype or not a.flags["C_CONTIGUOUS"]:
+        raise TypeError(f"{name}: expected a C-contiguous numpy array of {np.dtype(dtype)}")
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def plan_batches(utt_off: np.ndarray, max_utts: int, max_frames: int) -> np.ndarray:
+    """ivx_plan_batches (host only): first utterance of every batch, then U."""
+    lib = load()
+    U = len(utt_off) - 1
+    starts = np.zeros(max(U, 0) + 1, dtype=np.int64)
+    nb = ctypes.c_int64()
+    st = lib.ivx_plan_batches(_host(utt_off, np.int64, "utt_off"), U, int(max_utts),
+                              int(max_frames), ctypes.c_void_p(starts.ctypes.data), len(starts),
+                              ctypes.byref(nb))
+    if st != 0:
+        raise IvxError(st, lib.ivx_last_error().decode(errors="replace"))
+    return starts[:nb.value + 1].copy()
+
+
+class Stream:
+    """ivx_stream: batches of host-resident utterances through pinned slots,
+    uploaded and processed while the next batch loads."""
+
+    def __init__(self, ctx: Context, max_batch_utts: int, max_batch_frames: int, loaders=4,
+                 slots=4):
+        self.ctx = ctx
+        cfg = StreamConfig(max_batch_utts, max_batch_frames, loaders, slots)
+        h = ctypes.c_void_p()
+        ctx._check(ctx.lib.ivx_stream_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+
+    @staticmethod
+    def _source(fn, D):
+        """Wraps fn(u0, u1, out) (out: [frames, D] float32 view to fill) as a
+        frame source; an exception in fn stops the pass."""
+        if fn is None:
+            return FrameSource()
+
+        def cb(user, u0, u1, off, dst):
+            try:
+                nf = int(off[u1] - off[u0])
+                if nf > 0:
+                    buf = (ctypes.c_float * (nf * D)).from_address(dst)
+                    fn(int(u0), int(u1), np.frombuffer(buf, dtype=np.float32).reshape(nf, D))
+                return 0
+            except Exception:  # reported by the library as a failed source
+                return 1
+        return FrameSource(cb)
+
+    def em_pass(self, utt_off, acc: "Accumulators", X=None, source=None, S_acc=None,
+                ll_frames=None, ll_utts=None, phi_out=None, prec=IVX_FP32, sel=IVX_SEL_ALL,
+                stream=None):
+        c = self.ctx
+        U = len(utt_off) - 1
+        src = self._source(source, c.D)
+        s = acc.struct()
+        c._check(c.lib.ivx_stream_em_pass(
+            self.h, None if X is None else _host(X, np.float32, "X"), src, None,
+            _host(utt_off, np.int64, "utt_off"), U, prec, sel,
+            c._p(S_acc, torch.float64, "S_acc"), c._p(ll_frames, torch.float64, "ll_frames"),
+            c._p(ll_utts, torch.float64, "ll_utts"), ctypes.byref(s),
+            c._p(phi_out, torch.float32, "phi_out"), _stream(stream)))
+
+    def extract(self, utt_off, phi, X=None, source=None, prec=IVX_FP32, sel=IVX_SEL_ALL,
+                stream=None):
+        c = self.ctx
+        U = len(utt_off) - 1
+        src = self._source(source, c.D)
+        c._check(c.lib.ivx_stream_extract(
+            self.h, None if X is None else _host(X, np.float32, "X"), src, None,
+            _host(utt_off, np.int64, "utt_off"), U, prec, sel, c._p(phi, torch.float32, "phi"),
+            _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.ivx_stream_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -14,6 +14,8 @@ LIB = os.path.join(ROOT, "paper_1906_08556_amd", "libivx.so")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    # function-pointer typedefs (callback types) declare no symbol
+    src = re.sub(r"typedef\s+\w+\s*\(\s*\*\s*\w+\s*\)\s*\([^)]*\)\s*;", "", src)
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
                        src, flags=re.M)
     return sorted(set(n for n in names if n not in ("if", "while")))
