@@ -16,7 +16,9 @@ against something other than itself (brute-force densities, Gaussian
 conditioning of the joint, brute-force marginal likelihoods, finite
 differences of the EM auxiliary function, stated invariants).  The one
 learned-selection functions of ``mlp`` are pinned by finite differences,
-closed forms and the k = C special case.
+closed forms and the k = C special case.  The scoring back-end of ``backend``
+(whitening, length normalisation, LDA, two-covariance PLDA, EER) is pinned
+by closed forms, quadrature, brute force and invariants.
 """
 from .tv import (  # noqa: F401
     LOG2PI,
@@ -57,3 +59,4 @@ from .mlp import (  # noqa: F401
     learned_posteriors,
     missed_mass,
 )
+from . import backend  # noqa: F401,E402

@@ -207,3 +207,47 @@ def sample_frames(F, B, seed):
     """B distinct frame indices in [0, F), drawn without replacement."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([9002, seed])))
     return np.sort(rng.choice(F, size=B, replace=False)).astype(np.int64)
+
+
+def speakers(shape_id: int = 2, n_spk: int = 400, per_spk: int = 8, lengths: str = "uniform:200:600",
+             rho: float = 0.5, seed: int = 0):
+    """Speaker-labelled utterances under the model of workload ``shape_id``
+    (same UBM and T_true): every speaker draws y_s ~ N(0, I_R) and each of its
+    utterances w_u = sqrt(rho) y_s + sqrt(1 - rho) z_u, z_u ~ N(0, I_R), so
+    w_u ~ N(0, I_R) overall and rho is the between-speaker share of its
+    variance.  Frames as in ``make``.  Returns (Workload, labels [U] int32)."""
+    base = make(shape_id, seed=seed, n_utts=1)
+    sh = dataclasses.replace(base.shape, U=n_spk * per_spk, lengths=lengths)
+    C, D, R = sh.C, sh.D, sh.R
+    ss = np.random.SeedSequence([7001, shape_id, seed, n_spk, per_spk])
+    s_spk, s_lens, s_utts = ss.spawn(3)
+    Y = np.random.Generator(np.random.PCG64(s_spk)).standard_normal((n_spk, R))
+    U = n_spk * per_spk
+    lens = _lengths(lengths, U, np.random.Generator(np.random.PCG64(s_lens)))
+    labels = np.repeat(np.arange(n_spk, dtype=np.int32), per_spk)
+    utt_off = np.zeros(U + 1, dtype=np.int64)
+    utt_off[1:] = np.cumsum(lens)
+    chol = np.linalg.cholesky(base.cov)
+    cw = np.cumsum(base.w)
+    cw[-1] = 1.0
+    X = np.empty((int(utt_off[-1]), D), dtype=np.float32)
+    comp = np.empty(int(utt_off[-1]), dtype=np.int32)
+    T2 = base.T_true.reshape(C * D, R)
+    useeds = s_utts.spawn(U)
+    for c0 in range(0, U, 64):
+        c1 = min(U, c0 + 64)
+        draws = []
+        for u in range(c0, c1):
+            g = np.random.Generator(np.random.PCG64(useeds[u]))
+            wu = np.sqrt(rho) * Y[labels[u]] + np.sqrt(1.0 - rho) * g.standard_normal(R)
+            n = int(lens[u])
+            ct = np.minimum(np.searchsorted(cw, g.random(n), side="right"), C - 1)
+            draws.append((wu, ct, g.standard_normal((n, D))))
+        M = (T2 @ np.stack([d[0] for d in draws], axis=1)).reshape(C, D, c1 - c0)
+        for j, (wu, ct, zt) in enumerate(draws):
+            u = c0 + j
+            xt = base.mu[ct] + M[ct, :, j] + np.einsum("tde,te->td", chol[ct], zt)
+            X[utt_off[u]:utt_off[u + 1]] = xt.astype(np.float32)
+            comp[utt_off[u]:utt_off[u + 1]] = ct
+    wl = Workload(sh, seed, base.w, base.mu, base.cov, base.T_true, base.T_init, X, utt_off, comp)
+    return wl, labels
