@@ -16,9 +16,10 @@ gives no formulas:
     between- and within-class scatter of the training i-vectors) and the
     verification score the log-likelihood ratio of "same speaker" against
     "different speakers";
-  * EER: the smallest, over thresholds at the scores, of the larger of the
-    miss rate (targets below the threshold) and the false-alarm rate
-    (non-targets at or above it).
+  * EER: the crossing of P_miss = P_fa on the operating points of all
+    score thresholds (misses: targets below the threshold; false alarms:
+    non-targets at or above it) joined by straight segments, so that tied
+    target and non-target scores share the error evenly.
 """
 from __future__ import annotations
 
@@ -97,14 +98,22 @@ def plda_llr(Y1, Y2, mu, B, W):
 
 
 def eer(scores, is_target):
-    """min over thresholds t in the scores of max(P_miss(t), P_fa(t)) with
-    P_miss(t) = #(targets < t) / #targets, P_fa(t) = #(non-targets >= t) / #non-targets."""
+    """Equal error rate: the operating points (P_miss(t), P_fa(t)) at every
+    threshold t among the scores and above them, with
+    P_miss(t) = #(targets < t) / #targets and
+    P_fa(t) = #(non-targets >= t) / #non-targets, joined by straight
+    segments; the EER is where that polyline crosses P_miss = P_fa."""
     s = np.asarray(scores, dtype=np.float64)
     tgt = np.asarray(is_target, dtype=bool)
     st, sn = np.sort(s[tgt]), np.sort(s[~tgt])
-    best = 1.0
-    for t in np.unique(s):
+    pts = []
+    for t in list(np.unique(s)) + [np.inf]:
         pm = np.searchsorted(st, t, side="left") / len(st)
         pf = (len(sn) - np.searchsorted(sn, t, side="left")) / len(sn)
-        best = min(best, max(pm, pf))
-    return best
+        pts.append((pm, pf))
+    for (pm0, pf0), (pm1, pf1) in zip(pts[:-1], pts[1:]):
+        if pm0 <= pf0 and pm1 >= pf1:
+            d0, d1 = pf0 - pm0, pf1 - pm1
+            lam = d0 / (d0 - d1) if d0 != d1 else 0.0
+            return pm0 + lam * (pm1 - pm0)
+    raise AssertionError("the operating points always cross")

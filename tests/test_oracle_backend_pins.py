@@ -111,12 +111,16 @@ def test_plda_llr_symmetry_no_speaker_variability_and_mean_identity():
 
 
 def _eer_bruteforce(s, t):
-    best = 1.0
-    for th in s:
-        pm = sum(1 for x, y in zip(s, t) if y and x < th) / sum(t)
-        pf = sum(1 for x, y in zip(s, t) if not y and x >= th) / (len(t) - sum(t))
-        best = min(best, max(pm, pf))
-    return best
+    """Operating points by direct counting at every candidate threshold, then
+    the crossing of the straight segments between consecutive points."""
+    ths = sorted(set(s)) + [float("inf")]
+    nt, nn = sum(t), len(t) - sum(t)
+    pts = [(sum(1 for x, y in zip(s, t) if y and x < th) / nt,
+            sum(1 for x, y in zip(s, t) if not y and x >= th) / nn) for th in ths]
+    for (a, b), (c, d) in zip(pts, pts[1:]):
+        if a <= b and c >= d:
+            return a + (b - a) / ((b - a) - (d - c)) * (c - a) if (b - a) != (d - c) else a
+    raise AssertionError
 
 
 def test_eer_bruteforce_and_special_cases():
@@ -127,9 +131,10 @@ def test_eer_bruteforce_and_special_cases():
         t = rng.random(n) < 0.4
         if t.all() or not t.any():
             continue
-        assert be.eer(s, t) == _eer_bruteforce(list(s), list(t))
+        assert abs(be.eer(s, t) - _eer_bruteforce(list(s), list(t))) < 1e-12
     assert be.eer([3, 4, 5, 0, 1, 2], [1, 1, 1, 0, 0, 0]) == 0.0       # separable
     assert be.eer([0, 1, 2, 3, 4, 5], [1, 1, 1, 0, 0, 0]) == 1.0       # reversed
+    assert be.eer([1, 1, 1, 1], [1, 0, 1, 0]) == 0.5                   # a constant score
     n = 100000
     d = 1.5
     s = np.concatenate([d + rng.standard_normal(n), rng.standard_normal(n)])
