@@ -475,6 +475,78 @@ ivx_status ivx_stream_extract(ivx_stream* st, const float* X, ivx_frame_source s
                               void* src_user, const int64_t* utt_off, int64_t U,
                               ivx_precision prec, ivx_selection sel, float* phi, void* stream);
 
+/* ------------------------------------------------------- scoring back-end */
+
+/* The back-end of Sec. 4.1 (after extraction): i-vectors are centred,
+ * whitened when minimum divergence was not used, length-normalised, reduced
+ * by LDA (400 -> 200 in the paper) and scored by a Gaussian PLDA; accuracy is
+ * the equal error rate.  The paper gives no formulas for these steps; this
+ * library takes: whitening W = Lambda^{-1/2} Q^T of the covariance
+ * Q Lambda Q^T (divisor N); LDA from Sb v = lambda Sw v (between- and
+ * within-class scatter, divisor N) with V^T Sw V = I and decreasing
+ * eigenvalues; the two-covariance PLDA y = mu + s + e, s ~ N(0, B),
+ * e ~ N(0, W), with B = Sb and W = Sw of its training vectors, scored by the
+ * log-likelihood ratio of "same speaker" against "different speakers"; EER =
+ * the crossing of P_miss = P_fa on the operating points (P_miss(t), P_fa(t))
+ * of every threshold t among the scores and above them, joined by straight
+ * segments, misses being targets below t and false alarms non-targets at or
+ * above t.
+ * Symmetric eigenproblems are solved on the GPU by a one-workgroup Jacobi
+ * method in FP64.  Vectors are FP32 [n][dim] rows, matrices FP64 row-major,
+ * all on the device unless stated. */
+typedef struct ivx_backend ivx_backend;
+
+/* Workspace for up to max_n vectors of dimension <= max_dim (2..512) and up
+ * to max_classes classes.  IVX_ENOMEM if allocation fails. */
+ivx_status ivx_backend_create(int32_t max_dim, int64_t max_n, int32_t max_classes, int device,
+                              ivx_backend** out);
+void ivx_backend_destroy(ivx_backend* be);
+
+/* mean [dim] and whitening matrix W [dim][dim] of the rows of X [n][dim];
+ * synchronises `stream`.  IVX_ENOTPD if the covariance is singular
+ * (an eigenvalue below 1e-13 of the largest). */
+ivx_status ivx_backend_whitening(ivx_backend* be, const float* X, int64_t n, int32_t dim,
+                                 double* mean, double* W, void* stream);
+
+/* Y = W (X - mean) scaled to unit length per row; mean and W may be NULL
+ * (no centring / no whitening).  X, Y [n][dim]; asynchronous. */
+ivx_status ivx_backend_lnorm(ivx_backend* be, const float* X, int64_t n, int32_t dim,
+                             const double* mean, const double* W, float* Y, void* stream);
+
+/* LDA of X [n][dim] with labels [n] in [0, K): V [dim][out_dim] and its
+ * eigenvalues eigval [out_dim] (or NULL); synchronises `stream`.
+ * IVX_EINVAL for labels outside [0, K), IVX_ENOTPD if Sw is singular. */
+ivx_status ivx_backend_lda(ivx_backend* be, const float* X, int64_t n, int32_t dim,
+                           const int32_t* labels, int32_t K, int32_t out_dim, double* V,
+                           double* eigval, void* stream);
+
+/* Y [n][out_dim] = X [n][dim] V [dim][out_dim] (FP64 sums); asynchronous. */
+ivx_status ivx_backend_project(ivx_backend* be, const float* X, int64_t n, int32_t dim,
+                               const double* V, int32_t out_dim, float* Y, void* stream);
+
+/* Two-covariance PLDA of Y [n][d] with labels [n] in [0, K): mu [d] and the
+ * simultaneous diagonaliser A [d][d] (A^T W A = I, A^T B A = diag(psi)) with
+ * psi [d]; synchronises `stream`.  Errors as ivx_backend_lda. */
+ivx_status ivx_backend_plda_fit(ivx_backend* be, const float* Y, int64_t n, int32_t d,
+                                const int32_t* labels, int32_t K, double* mu, double* A,
+                                double* psi, void* stream);
+
+/* scores [T] FP32: the PLDA log-likelihood ratio of every trial
+ * (Y1[trials[2t]], Y2[trials[2t+1]]), trials [T][2] int32; Y1 [n1][d],
+ * Y2 [n2][d] (Y2 may equal Y1); asynchronous.  A trial index outside its set
+ * gives NaN and is reported by ivx_backend_status. */
+ivx_status ivx_backend_plda_score(ivx_backend* be, const double* mu, const double* A,
+                                  const double* psi, int32_t d, const float* Y1, int64_t n1,
+                                  const float* Y2, int64_t n2, const int32_t* trials, int64_t T,
+                                  float* scores, void* stream);
+
+/* Synchronises `stream`; IVX_EINVAL if a scored trial index was out of range. */
+ivx_status ivx_backend_status(ivx_backend* be, void* stream);
+
+/* Equal error rate of host scores [n] with host flags is_target [n] (0 / 1),
+ * as defined above.  Host only. */
+ivx_status ivx_eer(const float* scores, const uint8_t* is_target, int64_t n, double* eer);
+
 #ifdef __cplusplus
 }
 #endif

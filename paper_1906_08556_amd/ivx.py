@@ -111,6 +111,17 @@ PROTOTYPES = {
     "ivx_stream_em_pass": (_I32, [_P, _P, FrameSource, _P, _P, _I64, _I32, _I32, _P, _P, _P,
                                   ctypes.POINTER(Accum), _P, _P]),
     "ivx_stream_extract": (_I32, [_P, _P, FrameSource, _P, _P, _I64, _I32, _I32, _P, _P]),
+    "ivx_backend_create": (_I32, [_I32, _I64, _I32, ctypes.c_int, ctypes.POINTER(_P)]),
+    "ivx_backend_destroy": (None, [_P]),
+    "ivx_backend_whitening": (_I32, [_P, _P, _I64, _I32, _P, _P, _P]),
+    "ivx_backend_lnorm": (_I32, [_P, _P, _I64, _I32, _P, _P, _P, _P]),
+    "ivx_backend_lda": (_I32, [_P, _P, _I64, _I32, _P, _I32, _I32, _P, _P, _P]),
+    "ivx_backend_project": (_I32, [_P, _P, _I64, _I32, _P, _I32, _P, _P]),
+    "ivx_backend_plda_fit": (_I32, [_P, _P, _I64, _I32, _P, _I32, _P, _P, _P, _P]),
+    "ivx_backend_plda_score": (_I32, [_P, _P, _P, _P, _I32, _P, _I64, _P, _I64, _P, _I64, _P,
+                                      _P]),
+    "ivx_backend_status": (_I32, [_P, _P]),
+    "ivx_eer": (_I32, [_P, _P, _I64, ctypes.POINTER(ctypes.c_double)]),
     "ivx_profile_enable": (_I32, [_P, _I32]),
     "ivx_profile_read": (_I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
 }
@@ -502,6 +513,115 @@ class Stream:
     def close(self):
         if getattr(self, "h", None):
             self.ctx.lib.ivx_stream_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eer(scores: np.ndarray, is_target: np.ndarray) -> float:
+    """ivx_eer (host only)."""
+    lib = load()
+    s = np.ascontiguousarray(scores, dtype=np.float32)
+    t = np.ascontiguousarray(is_target, dtype=np.uint8)
+    out = ctypes.c_double()
+    st = lib.ivx_eer(ctypes.c_void_p(s.ctypes.data), ctypes.c_void_p(t.ctypes.data), len(s),
+                     ctypes.byref(out))
+    if st != 0:
+        raise IvxError(st, lib.ivx_last_error().decode(errors="replace"))
+    return out.value
+
+
+class Backend:
+    """ivx_backend: whitening, length norm, LDA, two-covariance PLDA and trial
+    scoring on device tensors."""
+
+    def __init__(self, max_dim: int, max_n: int, max_classes: int, device: int = 0):
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        self._check(self.lib.ivx_backend_create(max_dim, max_n, max_classes, device,
+                                                ctypes.byref(h)))
+        self.h = h
+
+    def _check(self, status):
+        if status != 0:
+            raise IvxError(status, self.lib.ivx_last_error().decode(errors="replace"))
+
+    def _p(self, t, dtype, name):
+        return _ptr(t, dtype, name, self.device)
+
+    def whitening(self, X, stream=None):
+        n, dim = X.shape
+        f64 = torch.float64
+        mean = torch.empty(dim, dtype=f64, device=self.device)
+        W = torch.empty((dim, dim), dtype=f64, device=self.device)
+        self._check(self.lib.ivx_backend_whitening(self.h, self._p(X, torch.float32, "X"), n, dim,
+                                                   self._p(mean, f64, "mean"),
+                                                   self._p(W, f64, "W"), _stream(stream)))
+        return mean, W
+
+    def lnorm(self, X, mean=None, W=None, stream=None):
+        n, dim = X.shape
+        Y = torch.empty_like(X)
+        self._check(self.lib.ivx_backend_lnorm(
+            self.h, self._p(X, torch.float32, "X"), n, dim, self._p(mean, torch.float64, "mean"),
+            self._p(W, torch.float64, "W"), self._p(Y, torch.float32, "Y"), _stream(stream)))
+        return Y
+
+    def lda(self, X, labels, K, out_dim, stream=None):
+        n, dim = X.shape
+        f64 = torch.float64
+        V = torch.empty((dim, out_dim), dtype=f64, device=self.device)
+        ev = torch.empty(out_dim, dtype=f64, device=self.device)
+        self._check(self.lib.ivx_backend_lda(
+            self.h, self._p(X, torch.float32, "X"), n, dim, self._p(labels, torch.int32, "labels"),
+            K, out_dim, self._p(V, f64, "V"), self._p(ev, f64, "eigval"), _stream(stream)))
+        return V, ev
+
+    def project(self, X, V, stream=None):
+        n, dim = X.shape
+        out_dim = V.shape[1]
+        Y = torch.empty((n, out_dim), dtype=torch.float32, device=self.device)
+        self._check(self.lib.ivx_backend_project(
+            self.h, self._p(X, torch.float32, "X"), n, dim, self._p(V, torch.float64, "V"),
+            out_dim, self._p(Y, torch.float32, "Y"), _stream(stream)))
+        return Y
+
+    def plda_fit(self, Y, labels, K, stream=None):
+        n, d = Y.shape
+        f64 = torch.float64
+        mu = torch.empty(d, dtype=f64, device=self.device)
+        A = torch.empty((d, d), dtype=f64, device=self.device)
+        psi = torch.empty(d, dtype=f64, device=self.device)
+        self._check(self.lib.ivx_backend_plda_fit(
+            self.h, self._p(Y, torch.float32, "Y"), n, d, self._p(labels, torch.int32, "labels"),
+            K, self._p(mu, f64, "mu"), self._p(A, f64, "A"), self._p(psi, f64, "psi"),
+            _stream(stream)))
+        return mu, A, psi
+
+    def plda_score(self, model, Y1, Y2, trials, stream=None):
+        mu, A, psi = model
+        d = mu.shape[0]
+        T = trials.shape[0]
+        scores = torch.empty(T, dtype=torch.float32, device=self.device)
+        f64 = torch.float64
+        self._check(self.lib.ivx_backend_plda_score(
+            self.h, self._p(mu, f64, "mu"), self._p(A, f64, "A"), self._p(psi, f64, "psi"), d,
+            self._p(Y1, torch.float32, "Y1"), Y1.shape[0], self._p(Y2, torch.float32, "Y2"),
+            Y2.shape[0], self._p(trials, torch.int32, "trials"), T,
+            self._p(scores, torch.float32, "scores"), _stream(stream)))
+        return scores
+
+    def status(self, stream=None):
+        self._check(self.lib.ivx_backend_status(self.h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ivx_backend_destroy(self.h)
             self.h = None
 
     def __del__(self):
