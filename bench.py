@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--stream-batch-utts", type=int, default=500)
     ap.add_argument("--stream-batch-frames", type=int, default=600_000)
     ap.add_argument("--stream-loaders", type=int, default=4)
+    ap.add_argument("--no-backend", action="store_true",
+                    help="skip the back-end timing on synthetic speakers")
     ap.add_argument("--no-pruned", action="store_true",
                     help="skip the pruned alignment (diagonal-UBM top-20, drop < 0.025)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -224,6 +226,76 @@ def learned_form(args, ctx, wl, X, step, timed, reset_model, phi, K, dev):
                             "frac": None if mlp_tflops is None else round(mlp_tflops / 2500.0, 4)},
         "vs_plain_first_iteration": {"ivector_min_cosine": float(cos.min())},
     }
+
+
+def backend_block(ctx, wl0, dev):
+    """Sec. 4.1 back-end at the paper's dimensions on synthetic speakers drawn
+    from a full-size model (D 60, C 2048, R 400): i-vectors extracted with it in the
+    standard formulation, centring + whitening + length norm, LDA 400 -> 200
+    and PLDA trained on half of the speakers, all pairs of the other half
+    scored, EER."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1906_08556_amd import ivx
+    t0 = time.time()
+    # the model of the T-std reading (shape 6): frames stay near their
+    # components, so UBM alignments follow the generating components
+    wl, lab = synth.speakers(6, n_spk=400, per_spk=8, lengths="uniform:200:600", rho=0.5)
+    gen_s = time.time() - t0
+    R = wl.shape.R
+    U = wl.U
+    X = torch.from_numpy(wl.X).to(dev)
+    off = torch.from_numpy(wl.utt_off).to(dev)
+    ctx.set_ubm(torch.from_numpy(wl.w).to(dev), torch.from_numpy(wl.mu).to(dev),
+                torch.from_numpy(wl.cov).to(dev))
+    ctx.set_tv(torch.from_numpy(wl.T_true).to(dev), torch.from_numpy(wl.cov).to(dev),
+               torch.zeros(R, dtype=torch.float64, device=dev))
+    ctx.set_bias(torch.from_numpy(wl.mu).to(dev))
+    phi = torch.empty((U, R), dtype=torch.float32, device=dev)
+    ctx.extract_ivectors(X, off, phi)        # warm-up (TV precompute)
+    ctx.sync_status()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx.extract_ivectors(X, off, phi)
+    torch.cuda.synchronize()
+    ext_s = time.perf_counter() - t
+    ctx.set_bias(None)
+    be = ivx.Backend(512, U, 400)
+    train = torch.from_numpy(lab < 200).to(dev)
+    lab_tr = torch.from_numpy(lab[lab < 200]).to(dev)
+    Xtr, Xte = phi[train].contiguous(), phi[~train].contiguous()
+    times = {}
+
+    def timed(name, fn):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        times[name] = round((time.perf_counter() - t1) * 1e3, 3)
+        return out
+
+    mean, W = timed("whitening_ms", lambda: be.whitening(Xtr))
+    Ytr = timed("lnorm_train_ms", lambda: be.lnorm(Xtr, mean, W))
+    Yte = be.lnorm(Xte, mean, W)
+    V, _ = timed("lda_400_to_200_ms", lambda: be.lda(Ytr, lab_tr, 200, 200))
+    Ptr, Pte = be.project(Ytr, V), be.project(Yte, V)
+    model = timed("plda_fit_ms", lambda: be.plda_fit(Ptr, lab_tr, 200))
+    lte = lab[lab >= 200]
+    i, j = np.triu_indices(len(lte), k=1)
+    trials = torch.from_numpy(np.stack([i, j], axis=1).astype(np.int32)).to(dev)
+    tgt = lte[i] == lte[j]
+    be.plda_score(model, Pte, Pte, trials)   # warm-up
+    scores = timed("score_ms", lambda: be.plda_score(model, Pte, Pte, trials))
+    be.status()
+    eer = ivx.eer(scores.cpu().numpy(), tgt)
+    be.close()
+    return {"speakers": 400, "utterances": U, "frames": int(wl.F), "rho": 0.5,
+            "extract_utts_per_s": round(U / ext_s, 1), "eer": round(eer, 5),
+            "trials": int(len(tgt)), "target_trials": int(tgt.sum()),
+            "score_trials_per_s": round(len(tgt) / (times["score_ms"] / 1e3), 1),
+            "times": times, "data_generation_s": round(gen_s, 1)}
 
 
 def main():
@@ -476,6 +548,11 @@ def main():
         del acc2, S2
         ctx2.close()
 
+    backend = None
+    if not args.no_backend:
+        backend = backend_block(ctx, wl, dev)
+        log(f"[bench] back-end on synthetic speakers: {backend}")
+
     pruned = None
     if not args.no_pruned:
         ctx.pruned_set(20, 0.025)
@@ -533,6 +610,7 @@ def main():
         "bf16_form": bf16,
         "graph_replay": graph,
         "standard_formulation": standard,
+        "backend_synthetic_speakers": backend,
         "streamed_from_host": streamed,
         "pruned_alignment": pruned,
         "learned_selection": learned,

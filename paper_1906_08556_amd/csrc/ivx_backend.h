@@ -15,8 +15,12 @@ void be_class_sums(const float* X, int64_t n, int dim, const int* labels, int K,
                    double* counts, int* bad, hipStream_t s);
 void be_scatter(const double* M2, const double* sums, const double* counts, int K, int dim,
                 double* Sw, double* Sb, double* mean, hipStream_t s);
-void be_jacobi(double* A, double* V, int n, int max_sweeps, double tol, double* w, int* sweeps,
-               hipStream_t s);
+// Eigendecomposition of the symmetric A [n][n] (n even; overwritten) into
+// w [n] and the columns of V [n][n]; synchronises s once per sweep.  rot
+// [n/2], part [128] workspace.  Returns the sweeps taken, -2 if max_sweeps
+// did not reach the tolerance, -1 on a HIP error.
+int be_jacobi(double* A, double* V, int n, int max_sweeps, double tol, double* w, double2* rot,
+              double* part, hipStream_t s);
 void be_dgemm(const void* A, bool a_float, int64_t lda, bool ta, const double* B, int64_t ldb,
               bool tb, void* C, int64_t ldc, bool c_float, int M, int N, int K,
               const double* colsub, hipStream_t s);

@@ -33,7 +33,10 @@ struct ivx_backend {
   float* Z1 = nullptr;       // [max_n][max_dim]
   float* Z2 = nullptr;       // [max_n][max_dim]
   int* idx = nullptr;        // [max_dim]
-  int* flags = nullptr;      // [4]: bad labels, singular whitening, bad trials, sweeps
+  double2* rot = nullptr;    // [nev / 2] Jacobi rotations of one step
+  double* part = nullptr;    // [128] Jacobi norm partials
+  int sweeps = 0;            // sweeps of the last Jacobi run (-1: HIP error)
+  int* flags = nullptr;      // [4]: bad labels, singular whitening, bad trials, unused
 };
 
 namespace {
@@ -63,7 +66,8 @@ int even(int n) { return n + (n & 1); }
 
 void be_free(ivx_backend* b) {
   void* ptrs[] = {b->sums, b->counts, b->M2, b->Sw, b->Sb, b->mean, b->Aj, b->Vj, b->wj,
-                  b->Wh, b->T1, b->T2, b->coef, b->muA, b->Z1, b->Z2, b->idx, b->flags};
+                  b->Wh, b->T1, b->T2, b->coef, b->muA, b->Z1, b->Z2, b->idx, b->flags,
+                  b->rot, b->part};
   for (void* p : ptrs)
     if (p) hipFree(p);
   delete b;
@@ -74,11 +78,22 @@ bool alloc(T** p, size_t n) {
   return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (n ? n : 1)) == hipSuccess;
 }
 
-// Reads and clears the flags after synchronising `s`.
+// Reads and clears the flags after synchronising `s`; also reports a Jacobi
+// run that failed or did not converge since the last call.
 ivx_status read_flags(ivx_backend* b, hipStream_t s, int out[4]) {
   BE_HIP(hipStreamSynchronize(s));
   BE_HIP(hipMemcpy(out, b->flags, sizeof(int) * 4, hipMemcpyDeviceToHost));
   BE_HIP(hipMemset(b->flags, 0, sizeof(int) * 4));
+  const int sw = b->sweeps;
+  b->sweeps = 0;
+  if (sw == -1) {
+    set_error("ivx_backend: HIP error in the Jacobi eigensolver");
+    return IVX_EDEVICE;
+  }
+  if (sw == -2) {
+    set_error("ivx_backend: Jacobi eigensolver did not converge in %d sweeps", kSweeps);
+    return IVX_ENUMERIC;
+  }
   return IVX_OK;
 }
 
@@ -98,7 +113,8 @@ void scatter(ivx_backend* b, const float* X, int64_t n, int dim, const int* labe
 void eig(ivx_backend* b, const double* S, int dim, hipStream_t s) {
   const int n = even(dim);
   be_pad_sym(S, dim, b->Aj, n, s);
-  be_jacobi(b->Aj, b->Vj, n, kSweeps, kTol, b->wj, b->flags + 3, s);
+  const int sw = be_jacobi(b->Aj, b->Vj, n, kSweeps, kTol, b->wj, b->rot, b->part, s);
+  if (b->sweeps >= 0) b->sweeps = sw < 0 ? sw : std::max(b->sweeps, sw);
 }
 
 // Wh = Q Lambda^{-1/2} of S (S = Q Lambda Q^T), so that Wh^T S Wh = I.
@@ -145,7 +161,8 @@ ivx_status ivx_backend_create(int32_t max_dim, int64_t max_n, int32_t max_classe
             alloc(&b->Wh, d2) && alloc(&b->T1, d2) && alloc(&b->T2, d2) &&
             alloc(&b->coef, 2 * d + 1) && alloc(&b->muA, d) &&
             alloc(&b->Z1, (size_t)max_n * d) && alloc(&b->Z2, (size_t)max_n * d) &&
-            alloc(&b->idx, d) && alloc(&b->flags, 4) &&
+            alloc(&b->idx, d) && alloc(&b->flags, 4) && alloc(&b->rot, ne / 2) &&
+            alloc(&b->part, 128) &&
             hipMemset(b->flags, 0, sizeof(int) * 4) == hipSuccess;
   if (!ok) {
     be_free(b);

@@ -4,20 +4,21 @@
 //  k_class_sums      per-class sums and counts (FP64 atomics)
 //  gemm64_tn         second moment X^T X (FP64 MFMA, k_gemm64.hip)
 //  k_scatter         Sw, Sb (divisor N) from the second moment and class sums
-//  k_jacobi          symmetric eigendecomposition, one workgroup: cyclic
-//                    Jacobi with round-robin ordering, n/2 disjoint rotations
-//                    per step (rows, then columns, then eigenvectors)
+//  k_jacobi_rows/cols  symmetric eigendecomposition by cyclic Jacobi with
+//                    round-robin ordering: n/2 disjoint rotations per step,
+//                    rows (one workgroup per pair) then columns and
+//                    eigenvectors (one workgroup per row); the host checks
+//                    the off-diagonal norm after every sweep
 //  k_dgemm           small FP64 products (n <= 512) through LDS tiles
 //  k_lnorm           y = W (x - mean) scaled to unit length, one wave per row
 //  k_plda_score      llr of (z1, z2) in the space where W = I and B = diag(psi)
+#include <algorithm>
 #include <cmath>
 
 #include "ivx_backend.h"
 
 namespace ivx {
 namespace {
-
-constexpr int JT = 1024;  // threads of the Jacobi workgroup
 
 __global__ void __launch_bounds__(256)
 k_class_sums(const float* __restrict__ X, int64_t n, int dim, const int* __restrict__ labels,
@@ -78,91 +79,96 @@ __device__ inline void rr_pair(int n, int r, int k, int& p, int& q) {
   }
 }
 
-// Eigendecomposition of the symmetric A [n][n] (n even, <= 512; overwritten,
-// its diagonal ends as the eigenvalues) with eigenvectors in the columns of
-// V [n][n].  Stops when the off-diagonal Frobenius norm is below
-// tol * ||A||_F or after max_sweeps sweeps; sweeps[0] receives the count.
-__global__ void __launch_bounds__(JT)
-k_jacobi(double* __restrict__ A, double* __restrict__ V, int n, int max_sweeps, double tol,
-         double* __restrict__ w, int* __restrict__ sweeps) {
-  __shared__ double cs[256], sn[256];
-  __shared__ int pp[256], qq[256];
-  __shared__ double red[JT];
-  __shared__ int s_done;
-  const int tid = threadIdx.x;
-  const int half = n / 2;
-  for (int64_t e = tid; e < (int64_t)n * n; e += JT) V[e] = (e / n == e % n) ? 1.0 : 0.0;
-  // ||A||_F
-  double s = 0.0;
-  for (int64_t e = tid; e < (int64_t)n * n; e += JT) s += A[e] * A[e];
-  red[tid] = s;
+// One step of the cyclic Jacobi method on the symmetric A [n][n] (n even):
+// the n/2 disjoint pairs of round-robin step r rotate at once,
+// A <- J^T A J, V <- V J.  k_jacobi_rows: one workgroup per pair computes its
+// rotation from the 2 x 2 block, stores it, and applies J^T to rows p and q.
+// k_jacobi_cols: one workgroup per row i applies every pair's rotation to
+// columns p and q of A and V.
+__global__ void __launch_bounds__(256)
+k_jacobi_rows(double* __restrict__ A, int n, int r, double2* __restrict__ rot) {
+  __shared__ double s_c, s_s;
+  int p, q;
+  rr_pair(n, r, blockIdx.x, p, q);
+  if (threadIdx.x == 0) {
+    const double apq = A[(size_t)p * n + q];
+    double c = 1.0, t = 0.0;
+    if (apq != 0.0) {
+      const double theta = (A[(size_t)q * n + q] - A[(size_t)p * n + p]) / (2.0 * apq);
+      t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      c = 1.0 / sqrt(t * t + 1.0);
+    }
+    s_c = c;
+    s_s = t * c;
+    rot[blockIdx.x] = make_double2(c, t * c);
+  }
   __syncthreads();
-  for (int o = JT / 2; o > 0; o >>= 1) {
-    if (tid < o) red[tid] += red[tid + o];
+  const double c = s_c, sv = s_s;
+  if (sv == 0.0) return;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double ap = A[(size_t)p * n + j], aq = A[(size_t)q * n + j];
+    A[(size_t)p * n + j] = c * ap - sv * aq;
+    A[(size_t)q * n + j] = sv * ap + c * aq;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_jacobi_cols(double* __restrict__ A, double* __restrict__ V, int n, int r,
+              const double2* __restrict__ rot) {
+  const int i = blockIdx.x;
+  for (int k = threadIdx.x; k < n / 2; k += 256) {
+    const double2 cs = rot[k];
+    if (cs.y == 0.0) continue;
+    int p, q;
+    rr_pair(n, r, k, p, q);
+    double* a = A + (size_t)i * n;
+    const double ap = a[p], aq = a[q];
+    a[p] = cs.x * ap - cs.y * aq;
+    a[q] = cs.y * ap + cs.x * aq;
+    double* v = V + (size_t)i * n;
+    const double vp = v[p], vq = v[q];
+    v[p] = cs.x * vp - cs.y * vq;
+    v[q] = cs.y * vp + cs.x * vq;
+  }
+}
+
+// part[b] = partial sums of the squared off-diagonal (and, with diag, all)
+// entries of A [n][n]; one value per workgroup, two slots per workgroup.
+__global__ void __launch_bounds__(256)
+k_offnorm_part(const double* __restrict__ A, int n, double* __restrict__ part) {
+  __shared__ double r0[256], r1[256];
+  double off = 0.0, all = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < (int64_t)n * n;
+       e += (int64_t)gridDim.x * 256) {
+    const double v = A[e] * A[e];
+    all += v;
+    if (e / n != e % n) off += v;
+  }
+  r0[threadIdx.x] = off;
+  r1[threadIdx.x] = all;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      r0[threadIdx.x] += r0[threadIdx.x + o];
+      r1[threadIdx.x] += r1[threadIdx.x + o];
+    }
     __syncthreads();
   }
-  const double fro = sqrt(red[0]);
-  __syncthreads();
-  int sweep = 0;
-  for (; sweep < max_sweeps; ++sweep) {
-    double off = 0.0;
-    for (int64_t e = tid; e < (int64_t)n * n; e += JT)
-      if (e / n != e % n) off += A[e] * A[e];
-    red[tid] = off;
-    __syncthreads();
-    for (int o = JT / 2; o > 0; o >>= 1) {
-      if (tid < o) red[tid] += red[tid + o];
-      __syncthreads();
-    }
-    if (tid == 0) s_done = !(sqrt(red[0]) > tol * fro);
-    __syncthreads();
-    if (s_done) break;
-    for (int r = 0; r < n - 1; ++r) {
-      if (tid < half) {
-        int p, q;
-        rr_pair(n, r, tid, p, q);
-        const double apq = A[(size_t)p * n + q];
-        double c = 1.0, t = 0.0;
-        if (apq != 0.0) {
-          const double theta = (A[(size_t)q * n + q] - A[(size_t)p * n + p]) / (2.0 * apq);
-          t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
-        }
-        cs[tid] = c;
-        sn[tid] = t * c;
-        pp[tid] = p;
-        qq[tid] = q;
-      }
-      __syncthreads();
-      // rows: (J^T A)
-      for (int e = tid; e < half * n; e += JT) {
-        const int k = e / n, j = e - k * n;
-        const int p = pp[k], q = qq[k];
-        const double c = cs[k], sv = sn[k];
-        const double ap = A[(size_t)p * n + j], aq = A[(size_t)q * n + j];
-        A[(size_t)p * n + j] = c * ap - sv * aq;
-        A[(size_t)q * n + j] = sv * ap + c * aq;
-      }
-      __threadfence_block();
-      __syncthreads();
-      // columns: (. J) on A, and V J
-      for (int e = tid; e < half * n; e += JT) {
-        const int k = e / n, i = e - k * n;
-        const int p = pp[k], q = qq[k];
-        const double c = cs[k], sv = sn[k];
-        const double ap = A[(size_t)i * n + p], aq = A[(size_t)i * n + q];
-        A[(size_t)i * n + p] = c * ap - sv * aq;
-        A[(size_t)i * n + q] = sv * ap + c * aq;
-        const double vp = V[(size_t)i * n + p], vq = V[(size_t)i * n + q];
-        V[(size_t)i * n + p] = c * vp - sv * vq;
-        V[(size_t)i * n + q] = sv * vp + c * vq;
-      }
-      __threadfence_block();
-      __syncthreads();
-    }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r0[0];
+    part[2 * blockIdx.x + 1] = r1[0];
   }
-  for (int i = tid; i < n; i += JT) w[i] = A[(size_t)i * n + i];
-  if (tid == 0) sweeps[0] = sweep;
+}
+
+__global__ void k_eye_diag(double* __restrict__ V, int n, const double* __restrict__ A,
+                           double* __restrict__ w, int mode) {
+  for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < (int64_t)n * n;
+       e += (int64_t)gridDim.x * 256) {
+    if (mode == 0)
+      V[e] = (e / n == e % n) ? 1.0 : 0.0;
+    else if (e < n)
+      w[e] = A[e * n + e];
+  }
 }
 
 // C[M][N] = sum_k op(A)[m][k] op(B)[k][n] - colsub[n], FP64 sums, 16 x 16 tiles.
@@ -380,9 +386,36 @@ void be_scatter(const double* M2, const double* sums, const double* counts, int 
   k_scatter<<<(unsigned)((e + 255) / 256), 256, 0, s>>>(M2, sums, counts, K, dim, Sw, Sb, mean);
 }
 
-void be_jacobi(double* A, double* V, int n, int max_sweeps, double tol, double* w, int* sweeps,
-               hipStream_t s) {
-  k_jacobi<<<1, JT, 0, s>>>(A, V, n, max_sweeps, tol, w, sweeps);
+constexpr int kOffParts = 64;
+
+int be_jacobi(double* A, double* V, int n, int max_sweeps, double tol, double* w, double2* rot,
+              double* part, hipStream_t s) {
+  const int64_t nn = (int64_t)n * n;
+  const unsigned gb = (unsigned)std::min<int64_t>((nn + 255) / 256, 1024);
+  k_eye_diag<<<gb, 256, 0, s>>>(V, n, A, w, 0);
+  double host[2 * kOffParts];
+  double fro = -1.0;
+  int sweep = 0;
+  for (;; ++sweep) {
+    k_offnorm_part<<<kOffParts, 256, 0, s>>>(A, n, part);
+    if (hipMemcpyAsync(host, part, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return -1;
+    double off = 0.0, all = 0.0;
+    for (int b = 0; b < kOffParts; ++b) {
+      off += host[2 * b];
+      all += host[2 * b + 1];
+    }
+    if (fro < 0.0) fro = std::sqrt(all);
+    if (!(std::sqrt(off) > tol * fro)) break;
+    if (sweep >= max_sweeps) return -2;
+    for (int r = 0; r < n - 1; ++r) {
+      k_jacobi_rows<<<n / 2, 256, 0, s>>>(A, n, r, rot);
+      k_jacobi_cols<<<n, 256, 0, s>>>(A, V, n, r, rot);
+    }
+  }
+  k_eye_diag<<<1, 256, 0, s>>>(V, n, A, w, 1);
+  return sweep;
 }
 
 void be_dgemm(const void* A, bool a_float, int64_t lda, bool ta, const double* B, int64_t ldb,

@@ -154,3 +154,68 @@ def test_backend_errors(backend):
     with pytest.raises(ivx.IvxError):
         backend.status()
     assert np.isnan(s.cpu().numpy()[1]) and np.isfinite(s.cpu().numpy()[0])
+
+
+def _pairs(labels):
+    i, j = np.triu_indices(len(labels), k=1)
+    return np.stack([i, j], axis=1).astype(np.int32), labels[i] == labels[j]
+
+
+def test_chain_on_synthetic_speakers_matches_the_oracle_chain(backend):
+    """Speaker-labelled utterances drawn from the shape-1 model; i-vectors
+    extracted with that model in the standard formulation (T_true, bias mu,
+    Sigma = UBM covariances, p = 0) by each side; then centring, whitening
+    and length norm with training-speaker statistics, LDA 32 -> 16 and PLDA
+    trained on 40 speakers, all pairs of the other 40 speakers scored.  The
+    oracle runs the whole chain on its own i-vectors.  Bounds follow the
+    extraction tolerance (i-vector cosine >= 0.9999): scores within
+    1e-3 (1 + |s|), EER within 3 target trials."""
+    import oracle
+    import synth
+    from _gpu_helpers import dev, make_ctx
+    from paper_1906_08556_amd import ivx
+    wl, lab = synth.speakers(1, n_spk=80, per_spk=6, lengths="uniform:100:300", rho=0.5)
+    R = wl.shape.R
+    ctx = make_ctx(wl)
+    ctx.set_tv(dev(wl.T_true), dev(wl.cov), dev(np.zeros(R)))
+    ctx.set_bias(dev(wl.mu))
+    phi = torch.empty((wl.U, R), dtype=torch.float32, device="cuda")
+    ctx.extract_ivectors(dev(wl.X), dev(wl.utt_off), phi)
+    ctx.sync_status()
+    # oracle i-vectors from its own posteriors and centred statistics
+    gamma, _ = oracle.posteriors(oracle.frame_loglik(wl.X, wl.w, wl.mu, wl.cov))
+    n, f, _ = oracle.bw_stats(wl.X, wl.utt_off, gamma, second_order=False)
+    fc = f - n[:, :, None] * wl.mu[None]
+    phio = oracle.estep(n, fc, wl.T_true, wl.cov, np.zeros(R), want_cov=False)["phi"]
+    g = phi.cpu().numpy()
+    cos = np.sum(g * phio, 1) / (np.linalg.norm(g, axis=1) * np.linalg.norm(phio, axis=1))
+    assert cos.min() >= 0.9999
+
+    train = lab < 40
+    test = ~train
+    # GPU chain
+    Xtr, Xte = phi[torch.from_numpy(train).cuda()], phi[torch.from_numpy(test).cuda()]
+    mean, W = backend.whitening(Xtr.contiguous())
+    Ytr = backend.lnorm(Xtr.contiguous(), mean, W)
+    Yte = backend.lnorm(Xte.contiguous(), mean, W)
+    V, _ = backend.lda(Ytr, _dev(lab[train]), 40, 16)
+    Ptr, Pte = backend.project(Ytr, V), backend.project(Yte, V)
+    model = backend.plda_fit(Ptr, _dev(lab[train]), 40)
+    tr, tgt = _pairs(lab[test])
+    s = backend.plda_score(model, Pte, Pte, _dev(tr)).cpu().numpy()
+    backend.status()
+    # oracle chain
+    mo, Wo = be.whitening(phio[train])
+    Yo_tr = be.center_lnorm(phio[train], mo, Wo)
+    Yo_te = be.center_lnorm(phio[test], mo, Wo)
+    Vo, _ = be.lda(Yo_tr, lab[train], 16)
+    muo, Bo, Wpo = be.plda_fit(Yo_tr @ Vo, lab[train])
+    Pte_o = Yo_te @ Vo
+    so = be.plda_llr(Pte_o[tr[:, 0]], Pte_o[tr[:, 1]], muo, Bo, Wpo)
+    err = np.max(np.abs(s - so) / (1 + np.abs(so)))
+    e_gpu, e_o = ivx.eer(s, tgt), be.eer(so, tgt)
+    print(f"chain: max |ds| / (1 + |s|) {err:.2e}; EER gpu {e_gpu:.4f} oracle {e_o:.4f} "
+          f"({tgt.sum()} target / {(~tgt).sum()} non-target trials)")
+    assert err <= 1e-3
+    assert abs(e_gpu - e_o) <= 3.0 / tgt.sum()
+    assert e_gpu < 0.25
