@@ -19,6 +19,7 @@ struct GemmArgs {
   int64_t sS = 0;                  // per-split stride of the FP32 store epilogue
   int ksplit = 1;
   int kchunk = 0;                  // K per split (multiple of 16); ignored when ksplit == 1
+  int m_fast = 0;                  // set by gemm_f32: M tiles of one column block consecutive
 };
 
 // C = op(A) op(B).  ta / tb select the transposed addressing of A / B, epi one

@@ -9,6 +9,9 @@
 //    op(B)(k, n) = B[k*ldb + n] (TB = false) or B[n*ldb + k] (TB = true).
 //  * blockIdx.z = batch * ksplit + split; split s covers K range
 //    [s*kchunk, min(K, (s+1)*kchunk)).
+//  * Tile order: the larger operand is streamed once -- with m_fast the M
+//    tiles of one column block of B are consecutive, otherwise the N tiles of
+//    one row block of A.
 //  * Epilogues: store FP32 (per split to its own slice), add into FP64
 //    (atomic when ksplit > 1), or store FP32 into the tile-packed symmetric
 //    layout (lower 16 x 16 tiles only).
@@ -33,7 +36,8 @@ __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs g) {
   const int wm = wave >> 1, wn = wave & 1;  // wave tile: 128 rows x 64 columns
   const int h = lane >> 5, l32 = lane & 31;
   const int batch = blockIdx.z / g.ksplit, split = blockIdx.z % g.ksplit;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int m0 = (g.m_fast ? blockIdx.x : blockIdx.y) * BM;
+  const int n0 = (g.m_fast ? blockIdx.y : blockIdx.x) * BN;
   if (EPI == GEMM_STORE_TP) {
     // skip workgroups whose tiles all lie strictly above the diagonal
     const int mlast = min(m0 + BM, g.M) - 1;
@@ -157,8 +161,9 @@ __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs g) {
 
 template <bool TA, bool TB, int EPI>
 void launch(const GemmArgs& g, int batches, hipStream_t s) {
-  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM),
-            (unsigned)(batches * g.ksplit));
+  const unsigned nt = (unsigned)((g.N + BN - 1) / BN), mt = (unsigned)((g.M + BM - 1) / BM);
+  const unsigned z = (unsigned)(batches * g.ksplit);
+  const dim3 grid = g.m_fast ? dim3(mt, nt, z) : dim3(nt, mt, z);
   k_gemm<TA, TB, EPI><<<grid, 256, 0, s>>>(g);
 }
 
@@ -172,6 +177,9 @@ bool gemm_f32(const GemmArgs& g0, bool ta, bool tb, int epi, int batches, hipStr
     g.kchunk = g.K;
   }
   if (g.M <= 0 || g.N <= 0 || batches <= 0) return true;
+  // stream the larger operand (per K) once; y-dimension limits apply
+  const int64_t mt = (g.M + BM - 1) / BM, nt = (g.N + BN - 1) / BN;
+  g.m_fast = ((int64_t)g.N > (int64_t)g.M && nt <= 65535) || mt > 65535 ? 1 : 0;
 #define IVX_GEMM_CASE(TA_, TB_, EPI_)                 \
   if (ta == TA_ && tb == TB_ && epi == EPI_) {        \
     launch<TA_, TB_, EPI_>(g, batches, s);            \
@@ -204,14 +212,15 @@ constexpr int SR = 24;  // LDS row stride (bf16) of a staged 16-k row (48 B)
 __global__ void __launch_bounds__(256, 2)
 k_gemm_bf16x3_nt(const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo, int64_t lda,
                  const __bf16* __restrict__ Bhi, const __bf16* __restrict__ Blo, int64_t ldb,
-                 float* __restrict__ C, int64_t ldc, int M, int N, int K) {
+                 float* __restrict__ C, int64_t ldc, int M, int N, int K, int m_fast) {
   // [buf][operand: A hi, A lo, B hi, B lo][128 rows][SR]
   __shared__ __bf16 St[2][4][128 * SR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int h = lane >> 5, l32 = lane & 31;
-  const int64_t m0 = (int64_t)blockIdx.y * 128;
-  const int64_t n0 = (int64_t)blockIdx.x * 128;
+  // m_fast: the M tiles of one column block of B run consecutively
+  const int64_t m0 = (int64_t)(m_fast ? blockIdx.x : blockIdx.y) * 128;
+  const int64_t n0 = (int64_t)(m_fast ? blockIdx.y : blockIdx.x) * 128;
   // loader: thread covers row tid / 2 and k half (tid & 1) * 8 of each operand
   const int lr = tid >> 1, lk = (tid & 1) * 8;
   uint4 rg[4];
@@ -332,8 +341,10 @@ void gemm_bf16x3_nt(const __bf16* Ahi, const __bf16* Alo, int64_t lda, const __b
                     const __bf16* Blo, int64_t ldb, float* C, int64_t ldc, int M, int N, int K,
                     hipStream_t s) {
   if (M <= 0 || N <= 0) return;
-  dim3 grid((unsigned)((N + 127) / 128), (unsigned)((M + 127) / 128));
-  k_gemm_bf16x3_nt<<<grid, 256, 0, s>>>(Ahi, Alo, lda, Bhi, Blo, ldb, C, ldc, M, N, K);
+  const unsigned mt = (unsigned)((M + 127) / 128), nt = (unsigned)((N + 127) / 128);
+  const int m_fast = (N > M && nt <= 65535u) || mt > 65535u ? 1 : 0;  // stream B once
+  const dim3 grid = m_fast ? dim3(mt, nt) : dim3(nt, mt);
+  k_gemm_bf16x3_nt<<<grid, 256, 0, s>>>(Ahi, Alo, lda, Bhi, Blo, ldb, C, ldc, M, N, K, m_fast);
 }
 
 }  // namespace ivx
