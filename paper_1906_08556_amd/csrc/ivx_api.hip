@@ -118,9 +118,9 @@ void ivx_destroy(ivx_ctx* ctx) {
   selector_free(ctx);
   presel_free(ctx);
   void* ptrs[] = {ctx->w, ctx->mu, ctx->cov, ctx->shift, ctx->Wexp, ctx->W16, ctx->linv,
-                  ctx->linv32r, ctx->cst,
+                  ctx->linv32r, ctx->ldense, ctx->cst,
                   ctx->pairs, ctx->T, ctx->Sigma, ctx->p, ctx->bias, ctx->bias32, ctx->cand, ctx->cM, ctx->cflag, ctx->post_idx,
-                  ctx->post_val, ctx->frame_ll, ctx->hist, ctx->coff, ctx->ent, ctx->partial,
+                  ctx->post_val, ctx->frame_ll, ctx->lscore, ctx->hist, ctx->coff, ctx->ent, ctx->partial,
                   ctx->Y32, ctx->V32, ctx->Utp, ctx->Psig, ctx->sig_logdet, ctx->Lbuf, ctx->Wbuf, ctx->Psi64,
                   ctx->bpart, ctx->bvec, ctx->llu, ctx->n_ws, ctx->f_ws, ctx->Tnew, ctx->obj_part,
                   ctx->Gmat, ctx->Mmat, ctx->Winv, ctx->Ut16hi, ctx->Ut16lo, ctx->n16hi,
@@ -172,6 +172,7 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   A(dalloc(&c->W16, (size_t)c->Cpad * c->Kpad * 2));
   A(dalloc(&c->linv, C * c->Dp));
   A(dalloc(&c->linv32r, C * c->Dp));
+  A(dalloc(&c->ldense, C * 4096));
   A(dalloc(&c->cst, C));
   A(dalloc(&c->pairs, (size_t)c->Kpad));
   A(dalloc(&c->T, C * D * R));
@@ -185,6 +186,7 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   A(dalloc(&c->post_idx, F * KP));
   A(dalloc(&c->post_val, F * KP));
   A(dalloc(&c->frame_ll, F));
+  A(dalloc(&c->lscore, F * KP));
   A(dalloc(&c->hist, (size_t)c->nhist * C));
   A(dalloc(&c->coff, C + 1));
   A(dalloc(&c->ent, F * KP));

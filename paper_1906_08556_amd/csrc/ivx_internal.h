@@ -160,6 +160,7 @@ struct ivx_ctx {
   __bf16* W16 = nullptr;      // [Kpad/16][Cpad][32] the same as BF16 (16 hi, 16 lo per chunk)
   double* linv = nullptr;     // [C][Dp] L_c^{-1}, lower triangle column by column
   float* linv32r = nullptr;   // [C][Dp] L_c^{-1} in FP32, lower triangle row by row
+  double* ldense = nullptr;   // [C][64][64] L_c^{-1} dense, column-major, zero-padded
   double* cst = nullptr;      // [C] log w_c - D/2 log 2pi - sum_i log L_c[i,i]
   uint16_t* pairs = nullptr;  // [Kpad] expanded-feature index pairs (a | b << 8)
 
@@ -179,6 +180,7 @@ struct ivx_ctx {
   int* post_idx = nullptr;    // [maxF][KP]
   float* post_val = nullptr;  // [maxF][KP]
   double* frame_ll = nullptr; // [maxF]
+  double* lscore = nullptr;   // [maxF][KP] exact FP64 scores of the kept candidates
   int* hist = nullptr;        // [nhist][C]
   int* coff = nullptr;        // [C+1]
   int2* ent = nullptr;        // [maxF*KP] component-sorted (frame, gamma bits)

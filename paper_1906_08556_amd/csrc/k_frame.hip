@@ -9,7 +9,9 @@
 // of components within the candidate margin of it are kept across component tiles:
 // the [F x C] log-likelihood matrix never leaves registers.
 //
-// Stage 2 (k_rescore): every surviving candidate is rescored exactly in FP64,
+// Stage 2 (k_exact_sorted, k_rescore): every surviving candidate is rescored
+// exactly in FP64 (candidates bucketed by component first, so that each
+// L_c^-1 is read once per run of its candidates),
 // l = const_c - 1/2 || L_c^{-1} (x - mu_c) ||^2, and the posteriors follow
 // from a log-sum-exp over the candidates.  Frames whose candidate list
 // overflowed are rescored over all C components and keep the KP best.
@@ -354,11 +356,113 @@ k_frame_tile_bf16(const float* __restrict__ X, int64_t F, int D, const float* __
   for (int fb = 0; fb < FB; ++fb) frame_epilogue<NCB>(acc[fb], st[fb], h, c0, C, margin, cM, cflag);
 }
 
+// ---- exact FP64 scores of the kept candidates, sorted by component --------
+// A candidate slot e = g * KP + s is kept when the frame's list did not
+// overflow and its FP32 score lies within the margin of the frame's maximum
+// (the test k_rescore applies).  Kept slots are bucketed by component
+// (per-block histograms, the shared scan, a scatter); k_exact_sorted then
+// walks the sorted slots so that a wave loads each L_c^-1 row once per run
+// of slots of one component instead of once per slot.
+constexpr int RHB = 8192;  // frames per histogram block
+
+__device__ inline int resc_kept(int64_t e, int C, const int2* __restrict__ cand,
+                                const float* __restrict__ cM, float margin,
+                                const int* __restrict__ cflag) {
+  const int64_t g = e / KP;
+  if (cflag[g] != 0) return -1;
+  const int2 v = cand[e];
+  return (v.x >= 0 && v.x < C && __int_as_float(v.y) >= cM[g] - margin) ? v.x : -1;
+}
+
+__global__ void __launch_bounds__(256)
+k_resc_hist(int64_t F, int C, const int2* __restrict__ cand, const float* __restrict__ cM,
+            float margin, const int* __restrict__ cflag, const int* __restrict__ Fdev,
+            int* __restrict__ hist) {
+  extern __shared__ int hl[];
+  if (Fdev && (int64_t)Fdev[0] < F) F = Fdev[0];
+  for (int c = threadIdx.x; c < C; c += 256) hl[c] = 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * RHB * KP;
+  const int64_t e1 = min(F * KP, e0 + (int64_t)RHB * KP);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int c = resc_kept(e, C, cand, cM, margin, cflag);
+    if (c >= 0) atomicAdd(&hl[c], 1);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < C; c += 256) hist[(size_t)blockIdx.x * C + c] = hl[c];
+}
+
+__global__ void __launch_bounds__(256)
+k_resc_scatter(int64_t F, int C, const int2* __restrict__ cand, const float* __restrict__ cM,
+               float margin, const int* __restrict__ cflag, const int* __restrict__ Fdev,
+               const int* __restrict__ base, int2* __restrict__ ent) {
+  extern __shared__ int cur[];
+  if (Fdev && (int64_t)Fdev[0] < F) F = Fdev[0];
+  for (int c = threadIdx.x; c < C; c += 256) cur[c] = base[(size_t)blockIdx.x * C + c];
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * RHB * KP;
+  const int64_t e1 = min(F * KP, e0 + (int64_t)RHB * KP);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int c = resc_kept(e, C, cand, cM, margin, cflag);
+    if (c >= 0) ent[atomicAdd(&cur[c], 1)] = make_int2((int)e, c);
+  }
+}
+
+constexpr int EXC = 64;  // sorted slots per wave chunk
+
+// lscore[slot] = cst_c - 1/2 ||L_c^-1 (x_g - mu_c)||^2 (FP64) for the sorted
+// slots ent[0, coff[C]), with L_c^-1 read from its dense column-major copy
+// ldense [C][64][64] (zero outside the lower triangle of the D x D block).
+// Lane i holds row i of L_c^-1 and mu_c[i] for the
+// current component; (x - mu)_j reaches all lanes as a broadcast LDS read.
+// Waves take chunks of EXC slots in a grid-stride loop.
+__global__ void __launch_bounds__(256)
+k_exact_sorted(const int2* __restrict__ ent, const int* __restrict__ coff, int C,
+               const float* __restrict__ X, int D, const double* __restrict__ mu,
+               const double* __restrict__ ldense, const double* __restrict__ cst,
+               double* __restrict__ lscore) {
+  __shared__ double dsh[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t total = coff[C];
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  int cur = -1;
+  double Lr[64];
+  double mul = 0.0, cc = 0.0;
+#pragma unroll
+  for (int j = 0; j < 64; ++j) Lr[j] = 0.0;
+  for (int64_t e0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * EXC; e0 < total;
+       e0 += nw * EXC) {
+    const int64_t e1 = min(total, e0 + EXC);
+    for (int64_t e = e0; e < e1; ++e) {
+      const int2 v = ent[e];  // wave-uniform
+      if (v.y != cur) {
+        cur = v.y;
+        const double* Lc = ldense + (size_t)cur * 4096 + lane;  // column j at Lc[64 j]
+#pragma unroll
+        for (int j = 0; j < 64; ++j) Lr[j] = (j < D) ? Lc[64 * j] : 0.0;
+        mul = (lane < D) ? mu[(size_t)cur * D + lane] : 0.0;
+        cc = cst[cur];
+      }
+      const int64_t g = v.x / KP;
+      __builtin_amdgcn_wave_barrier();  // previous slot's reads of dsh are done
+      dsh[wv][lane] = (lane < D) ? (double)X[g * D + lane] - mul : 0.0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      double y = 0.0;
+#pragma unroll
+      for (int j = 0; j < 64; ++j) y += Lr[j] * dsh[wv][j];
+      const double q = wave_sum(y * y);
+      if (lane == 0) lscore[v.x] = cc - 0.5 * q;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256)
 k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __restrict__ mu,
           const double* __restrict__ linv, const double* __restrict__ cst,
           const int2* __restrict__ cand, const float* __restrict__ cM, float margin,
-          const int* __restrict__ cflag,
+          const int* __restrict__ cflag, const double* __restrict__ lscore,
           int* __restrict__ post_idx, float* __restrict__ post_val, double* __restrict__ frame_ll,
           int* __restrict__ err, const int* __restrict__ Fdev, const int* __restrict__ fmap) {
   __shared__ double dsh[4][64];
@@ -383,7 +487,7 @@ k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __
     for (int s = 0; s < KP; ++s) {
       const int c = __shfl(ci, s);
       if (c < 0 || c >= C) continue;
-      const double l = exact_ll(c, xd, lane, D, Dp, mu, linv, cst, dsh[wave]);
+      const double l = lscore[g * KP + s];  // k_exact_sorted
       if (lane == 0) {
         lsh[wave][m] = l;
         ish[wave][m] = c;
@@ -532,11 +636,21 @@ void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int prec, int* post
                     float* post_val, double* frame_ll, hipStream_t s, const int* Fdev,
                     const int* fmap) {
   if (F <= 0) return;
+  const float margin = prec == IVX_BF16 ? ctx->margin_bf16 : ctx->margin;
+  // exact scores of the kept candidates, by component
+  const unsigned nb = (unsigned)((F + RHB - 1) / RHB);
+  const size_t ldsc = sizeof(int) * ctx->C;
+  k_resc_hist<<<nb, 256, ldsc, s>>>(F, ctx->C, ctx->cand, ctx->cM, margin, ctx->cflag, Fdev,
+                                    ctx->hist);
+  launch_hist_scan((int)nb, ctx->C, ctx->hist, ctx->coff, s);
+  k_resc_scatter<<<nb, 256, ldsc, s>>>(F, ctx->C, ctx->cand, ctx->cM, margin, ctx->cflag, Fdev,
+                                       ctx->hist, ctx->ent);
+  k_exact_sorted<<<4096, 256, 0, s>>>(ctx->ent, ctx->coff, ctx->C, X, ctx->D, ctx->mu,
+                                      ctx->ldense, ctx->cst, ctx->lscore);
   const unsigned nblk = (unsigned)((F + 3) / 4);
   k_rescore<<<nblk, 256, 0, s>>>(X, F, ctx->D, ctx->C, ctx->mu, ctx->linv, ctx->cst, ctx->cand,
-                                 ctx->cM, prec == IVX_BF16 ? ctx->margin_bf16 : ctx->margin,
-                                 ctx->cflag, post_idx, post_val, frame_ll, ctx->dev_err, Fdev,
-                                 fmap);
+                                 ctx->cM, margin, ctx->cflag, ctx->lscore, post_idx, post_val,
+                                 frame_ll, ctx->dev_err, Fdev, fmap);
 }
 
 void launch_dense_gamma(ivx_ctx* ctx, int64_t F, const int* post_idx, const float* post_val,

@@ -202,6 +202,20 @@ __global__ void k_bias32(const double* __restrict__ bias, int64_t n, float* __re
     bias32[i] = (float)bias[i];
 }
 
+// ldense[c][j][i] = L_c^-1[i][j] for j <= i < D, else 0 (dense column-major
+// copy of the column-packed FP64 factor, for the sorted exact rescoring)
+__global__ void k_linv_dense(const double* __restrict__ linv, int C, int D,
+                             double* __restrict__ ldense) {
+  const int Dp = D * (D + 1) / 2;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)C * 4096;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e >> 12), j = (int)((e >> 6) & 63), i = (int)(e & 63);
+    double v = 0.0;
+    if (j < D && i < D && j <= i) v = linv[(size_t)c * Dp + j * D - j * (j - 1) / 2 + (i - j)];
+    ldense[e] = v;
+  }
+}
+
 __global__ void k_update_means(const double* __restrict__ T, const double* __restrict__ p, int C,
                                int D, int R, double* __restrict__ mu) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -216,6 +230,7 @@ void launch_ubm_prepare(ivx_ctx* ctx, hipStream_t s) {
   k_ubm_prepare<<<ctx->Cpad, 64, lds, s>>>(ctx->w, ctx->mu, ctx->cov, ctx->shift, ctx->C, ctx->D,
                                            ctx->K, ctx->Kpad, ctx->pairs, ctx->Wexp, ctx->W16,
                                            ctx->linv, ctx->linv32r, ctx->cst, ctx->dev_err);
+  k_linv_dense<<<2048, 256, 0, s>>>(ctx->linv, ctx->C, ctx->D, ctx->ldense);
 }
 
 void launch_init_tv(ivx_ctx* ctx, const double* T_rand, double p0, hipStream_t s) {
