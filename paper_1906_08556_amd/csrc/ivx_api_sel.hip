@@ -16,7 +16,8 @@ void selector_free(ivx_ctx* ctx) {
   Selector* S = ctx->sel;
   void* ptrs[] = {S->param, S->grad, S->adam_m, S->adam_v, S->mean, S->stdv, S->istd, S->W1b,
                   S->W2b, S->W3b, S->b3p, S->h1b, S->h2b, S->prop, S->mass, S->fb, S->fb_list,
-                  S->counters, S->score, S->hist, S->coff, S->ent, S->xfb, S->xs, S->a1, S->h1,
+                  S->counters, S->score, S->thr, S->lscore, S->hist, S->coff, S->ent, S->xfb,
+                  S->xs, S->a1, S->h1,
                   S->a2, S->h2, S->z, S->dz, S->dh1, S->dh2, S->loss_part, S->colpart};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -27,7 +28,8 @@ void selector_free(ivx_ctx* ctx) {
 void presel_free(ivx_ctx* ctx) {
   if (!ctx || !ctx->presel) return;
   Presel* P = ctx->presel;
-  void* ptrs[] = {P->Wd, P->pairs, P->prop, P->score, P->hist, P->coff, P->ent};
+  void* ptrs[] = {P->Wd, P->pairs, P->prop, P->score, P->thr, P->lscore, P->hist, P->coff,
+                  P->ent};
   for (void* p : ptrs)
     if (p) hipFree(p);
   delete P;
@@ -161,6 +163,8 @@ ivx_status ivx_selector_set(ivx_ctx* ctx, const ivx_selector_dims* sd, const flo
   A(salloc(&S->fb_list, maxF));
   A(salloc(&S->counters, 4));
   A(salloc(&S->score, maxF * k));
+  A(salloc(&S->thr, maxF));
+  A(salloc(&S->lscore, maxF * k));
   A(salloc(&S->hist, nbh * C));
   A(salloc(&S->coff, C + 1));
   A(salloc(&S->ent, maxF * k));
@@ -225,6 +229,8 @@ ivx_status ivx_pruned_set(ivx_ctx* ctx, int32_t k, float prune, void* stream) {
   A(salloc(&P->pairs, P->Kd8));
   A(salloc(&P->prop, maxF * k));
   A(salloc(&P->score, maxF * k));
+  A(salloc(&P->thr, maxF));
+  A(salloc(&P->lscore, maxF * k));
   A(salloc(&P->hist, (maxF / 8192 + 1) * C));
   A(salloc(&P->coff, C + 1));
   A(salloc(&P->ent, maxF * k));

@@ -86,6 +86,8 @@ struct Selector {
   int* fb_list = nullptr; // [maxF]
   int* counters = nullptr;  // [4]: fallback frames, kept (frame, proposal) pairs
   float* score = nullptr;   // [maxF][k] FP32 filter scores
+  float* thr = nullptr;     // [maxF] the frame's best filter score minus the margin
+  double* lscore = nullptr; // [maxF][k] exact FP64 scores of the kept proposals
   int* hist = nullptr;      // [maxF / 8192 + 1][C]
   int* coff = nullptr;      // [C + 1]
   int2* ent = nullptr;      // [maxF * k] (frame * k + slot, component), by component
@@ -115,6 +117,8 @@ struct Presel {
   uint16_t* pairs = nullptr;  // [Kd8] feature index pairs (1, x_d, x_d^2)
   int* prop = nullptr;      // [maxF][k]
   float* score = nullptr;   // [maxF][k]
+  float* thr = nullptr;     // [maxF] the frame's best filter score minus the margin
+  double* lscore = nullptr; // [maxF][k] exact FP64 scores of the kept proposals
   int* hist = nullptr;      // [maxF / 8192 + 1][C]
   int* coff = nullptr;      // [C + 1]
   int2* ent = nullptr;      // [maxF * k]
@@ -279,6 +283,10 @@ void launch_stats_nf(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64
                      float* n, float* f, hipStream_t s);
 void launch_stats_S(ivx_ctx* ctx, const float* X, int64_t F, double* S_acc, hipStream_t s);
 void launch_sum_f64(ivx_ctx* ctx, const double* x, int64_t n, double* acc, hipStream_t s);
+// lscore[slot] = exact FP64 log w_c N(x_g; mu_c, Sigma_c) for the slots of
+// ent[0, coff[C]) sorted by component (slot = g * kpf + index, c = .y)
+void launch_exact_sorted(ivx_ctx* ctx, const int2* ent, const int* coff, int kpf, const float* X,
+                         double* lscore, hipStream_t s);
 void launch_hist_scan(int nb, int C, int* hist, int* coff, hipStream_t s);
 
 // ---- ivx_api_tv.hip

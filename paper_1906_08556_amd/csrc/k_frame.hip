@@ -411,13 +411,14 @@ k_resc_scatter(int64_t F, int C, const int2* __restrict__ cand, const float* __r
 constexpr int EXC = 64;  // sorted slots per wave chunk
 
 // lscore[slot] = cst_c - 1/2 ||L_c^-1 (x_g - mu_c)||^2 (FP64) for the sorted
-// slots ent[0, coff[C]), with L_c^-1 read from its dense column-major copy
+// slots ent[0, coff[C]) (slot = frame * kpf + index), with L_c^-1 read from
+// its dense column-major copy
 // ldense [C][64][64] (zero outside the lower triangle of the D x D block).
 // Lane i holds row i of L_c^-1 and mu_c[i] for the
 // current component; (x - mu)_j reaches all lanes as a broadcast LDS read.
 // Waves take chunks of EXC slots in a grid-stride loop.
 __global__ void __launch_bounds__(256)
-k_exact_sorted(const int2* __restrict__ ent, const int* __restrict__ coff, int C,
+k_exact_sorted(const int2* __restrict__ ent, const int* __restrict__ coff, int C, int kpf,
                const float* __restrict__ X, int D, const double* __restrict__ mu,
                const double* __restrict__ ldense, const double* __restrict__ cst,
                double* __restrict__ lscore) {
@@ -443,7 +444,7 @@ k_exact_sorted(const int2* __restrict__ ent, const int* __restrict__ coff, int C
         mul = (lane < D) ? mu[(size_t)cur * D + lane] : 0.0;
         cc = cst[cur];
       }
-      const int64_t g = v.x / KP;
+      const int64_t g = v.x / kpf;
       __builtin_amdgcn_wave_barrier();  // previous slot's reads of dsh are done
       dsh[wv][lane] = (lane < D) ? (double)X[g * D + lane] - mul : 0.0;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -645,12 +646,17 @@ void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int prec, int* post
   launch_hist_scan((int)nb, ctx->C, ctx->hist, ctx->coff, s);
   k_resc_scatter<<<nb, 256, ldsc, s>>>(F, ctx->C, ctx->cand, ctx->cM, margin, ctx->cflag, Fdev,
                                        ctx->hist, ctx->ent);
-  k_exact_sorted<<<4096, 256, 0, s>>>(ctx->ent, ctx->coff, ctx->C, X, ctx->D, ctx->mu,
-                                      ctx->ldense, ctx->cst, ctx->lscore);
+  launch_exact_sorted(ctx, ctx->ent, ctx->coff, KP, X, ctx->lscore, s);
   const unsigned nblk = (unsigned)((F + 3) / 4);
   k_rescore<<<nblk, 256, 0, s>>>(X, F, ctx->D, ctx->C, ctx->mu, ctx->linv, ctx->cst, ctx->cand,
                                  ctx->cM, margin, ctx->cflag, ctx->lscore, post_idx, post_val,
                                  frame_ll, ctx->dev_err, Fdev, fmap);
+}
+
+void launch_exact_sorted(ivx_ctx* ctx, const int2* ent, const int* coff, int kpf, const float* X,
+                         double* lscore, hipStream_t s) {
+  k_exact_sorted<<<4096, 256, 0, s>>>(ent, coff, ctx->C, kpf, X, ctx->D, ctx->mu, ctx->ldense,
+                                      ctx->cst, lscore);
 }
 
 void launch_dense_gamma(ivx_ctx* ctx, int64_t F, const int* post_idx, const float* post_val,

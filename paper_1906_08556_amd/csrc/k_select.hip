@@ -15,8 +15,10 @@
 //   k_sel_hist / scan / k_sel_scatter   (frame, proposal) pairs by component
 //   k_sel_score      FP32 shifted-form score of every pair: one component per
 //                    wave pass, its L^-1 read through the scalar cache
-//   k_sel_finalize   FP64 exact scores of the proposals within the margin of
-//                    the frame's best, posteriors renormalised over them
+//   k_sel_thr / k_kept_hist / scan / k_kept_scatter / k_exact_sorted
+//                    FP64 exact scores of the proposals within the margin of
+//                    the frame's best, again bucketed by component
+//   k_sel_finalize   posteriors renormalised over the kept proposals
 //   fallback frames  gathered and sent through the all-component kernels
 //
 // Training runs in FP32 on the FP32 GEMM (k_gemm.hip) with the helpers below.
@@ -607,6 +609,63 @@ k_sel_scatter(int64_t F, int k, int C, const int* __restrict__ prop, const int* 
   }
 }
 
+// thr[g] = (largest filter score of the frame's k proposals) - margin: the
+// proposals at or above it are scored exactly (the test of k_sel_finalize)
+__global__ void __launch_bounds__(256)
+k_sel_thr(int64_t F, int k, const float* __restrict__ score, float margin,
+          float* __restrict__ thr) {
+  const int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (g >= F) return;
+  float M = -INFINITY;
+  for (int s = 0; s < k; ++s) M = fmaxf(M, score[g * k + s]);
+  thr[g] = M - margin;
+}
+
+__device__ inline int sel_kept(int64_t e, int k, int C, const int* __restrict__ prop,
+                               const int* __restrict__ fb, const float* __restrict__ score,
+                               const float* __restrict__ thr) {
+  const int64_t g = e / k;
+  if (fb && fb[g]) return -1;
+  const int c = prop[e];
+  return (c >= 0 && c < C && score[e] >= thr[g]) ? c : -1;
+}
+
+// bucket the kept (frame, proposal) slots by component (as k_sel_hist /
+// k_sel_scatter, restricted to the slots within the margin)
+__global__ void __launch_bounds__(256)
+k_kept_hist(int64_t F, int k, int C, const int* __restrict__ prop, const int* __restrict__ fb,
+            const float* __restrict__ score, const float* __restrict__ thr,
+            int* __restrict__ hist) {
+  extern __shared__ int hl[];
+  const int b = blockIdx.x;
+  for (int c = threadIdx.x; c < C; c += 256) hl[c] = 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)b * HBS * k;
+  const int64_t e1 = min(F * k, e0 + (int64_t)HBS * k);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int c = sel_kept(e, k, C, prop, fb, score, thr);
+    if (c >= 0) atomicAdd(&hl[c], 1);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < C; c += 256) hist[(size_t)b * C + c] = hl[c];
+}
+
+__global__ void __launch_bounds__(256)
+k_kept_scatter(int64_t F, int k, int C, const int* __restrict__ prop, const int* __restrict__ fb,
+               const float* __restrict__ score, const float* __restrict__ thr,
+               const int* __restrict__ base, int2* __restrict__ ent) {
+  extern __shared__ int cur[];
+  const int b = blockIdx.x;
+  for (int c = threadIdx.x; c < C; c += 256) cur[c] = base[(size_t)b * C + c];
+  __syncthreads();
+  const int64_t e0 = (int64_t)b * HBS * k;
+  const int64_t e1 = min(F * k, e0 + (int64_t)HBS * k);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int c = sel_kept(e, k, C, prop, fb, score, thr);
+    if (c >= 0) ent[atomicAdd(&cur[c], 1)] = make_int2((int)e, c);
+  }
+}
+
 // FP32 shifted-form score cst_c - 1/2 ||L_c^-1 (x - mu_c)||^2 of every
 // (frame, proposal) pair, pairs sorted by component.  The wave handles one
 // component at a time (a wave-uniform index), so mu_c and L_c^-1 (FP32, rows
@@ -667,19 +726,15 @@ k_sel_score(const float* __restrict__ X, int D, int k, const int* __restrict__ c
 __global__ void __launch_bounds__(256)
 k_sel_finalize(const float* __restrict__ X, int64_t F, int D, int C, int k,
                const int* __restrict__ prop, const int* __restrict__ fb,
-               const float* __restrict__ score, const double* __restrict__ mu,
-               const double* __restrict__ linv, const double* __restrict__ cst, float margin,
+               const float* __restrict__ score, const double* __restrict__ lscore, float margin,
                float prune, int* __restrict__ post_idx, float* __restrict__ post_val,
                double* __restrict__ frame_ll, int* __restrict__ err) {
-  __shared__ double dsh[4][64];
   __shared__ double lsh[4][32];
   __shared__ int ish[4][32];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t g = (int64_t)blockIdx.x * 4 + wave;
   if (g >= F) return;  // wave-uniform
   if (fb && fb[g]) return;
-  const int Dp = D * (D + 1) / 2;
-  const double xd = (lane < D) ? (double)X[g * D + lane] : 0.0;
   int c = -1;
   float sc = -INFINITY;
   if (lane < k) {
@@ -696,7 +751,7 @@ k_sel_finalize(const float* __restrict__ X, int64_t F, int D, int C, int k,
   for (int s = 0; s < k; ++s) {
     const int cs = __shfl(cin, s);
     if (cs < 0) continue;
-    const double l = exact_ll(cs, xd, lane, D, Dp, mu, linv, cst, dsh[wave]);
+    const double l = lscore[g * k + s];  // exact FP64 (k_exact_sorted)
     if (lane == 0) {  // sorted insertion, largest first
       int pos = m;
       while (pos > 0 && lsh[wave][pos - 1] < l) {
@@ -1061,6 +1116,21 @@ void launch_selector_mlp(ivx_ctx* ctx, const float* X, int64_t F, uint16_t* h1_o
   }
 }
 
+// Exact FP64 scores of the proposals within the margin of each frame's best
+// filter score, bucketed by component and scored by k_exact_sorted (the
+// sort buffers of the filter pass are reused).
+static void exact_kept(ivx_ctx* ctx, const float* X, int64_t F, int k, const int* prop, const int* fb,
+                const float* score, float margin, float* thr, int* hist, int* coff, int2* ent,
+                double* lscore, hipStream_t s) {
+  k_sel_thr<<<(unsigned)((F + 255) / 256), 256, 0, s>>>(F, k, score, margin, thr);
+  const int nb = (int)((F + HBS - 1) / HBS);
+  const size_t ldsc = sizeof(int) * ctx->C;
+  k_kept_hist<<<nb, 256, ldsc, s>>>(F, k, ctx->C, prop, fb, score, thr, hist);
+  launch_hist_scan(nb, ctx->C, hist, coff, s);
+  k_kept_scatter<<<nb, 256, ldsc, s>>>(F, k, ctx->C, prop, fb, score, thr, hist, ent);
+  launch_exact_sorted(ctx, ent, coff, k, X, lscore, s);
+}
+
 void launch_select_learned(ivx_ctx* ctx, const float* X, int64_t F, int prec, int* post_idx,
                            float* post_val, double* frame_ll, hipStream_t s) {
   if (F <= 0) return;
@@ -1076,9 +1146,11 @@ void launch_select_learned(ivx_ctx* ctx, const float* X, int64_t F, int prec, in
     const int64_t cap = F * S.k;
     k_sel_score<<<(unsigned)((cap + 255) / 256), 256, 0, s>>>(
         X, ctx->D, S.k, S.coff, ctx->C, S.ent, cap, ctx->mu, ctx->linv32r, ctx->cst, S.score);
+    exact_kept(ctx, X, F, S.k, S.prop, S.fb, S.score, S.margin, S.thr, S.hist, S.coff, S.ent,
+               S.lscore, s);
     k_sel_finalize<<<(unsigned)((F + 3) / 4), 256, 0, s>>>(
-        X, F, ctx->D, ctx->C, S.k, S.prop, S.fb, S.score, ctx->mu, ctx->linv, ctx->cst, S.margin,
-        0.0f, post_idx, post_val, frame_ll, ctx->dev_err);
+        X, F, ctx->D, ctx->C, S.k, S.prop, S.fb, S.score, S.lscore, S.margin, 0.0f, post_idx,
+        post_val, frame_ll, ctx->dev_err);
   }
   // fallback frames: all components, results written at their own rows
   k_gather_rows<<<2048, 256, 0, s>>>(X, ctx->D, S.fb_list, S.counters, F, S.xfb);
@@ -1120,9 +1192,11 @@ void launch_select_pruned(ivx_ctx* ctx, const float* X, int64_t F, int* post_idx
   const int64_t cap = F * P.k;
   k_sel_score<<<(unsigned)((cap + 255) / 256), 256, 0, s>>>(
       X, ctx->D, P.k, P.coff, ctx->C, P.ent, cap, ctx->mu, ctx->linv32r, ctx->cst, P.score);
+  exact_kept(ctx, X, F, P.k, P.prop, nullptr, P.score, P.margin, P.thr, P.hist, P.coff, P.ent,
+             P.lscore, s);
   k_sel_finalize<<<(unsigned)((F + 3) / 4), 256, 0, s>>>(
-      X, F, ctx->D, ctx->C, P.k, P.prop, nullptr, P.score, ctx->mu, ctx->linv, ctx->cst, P.margin,
-      P.prune, post_idx, post_val, frame_ll, ctx->dev_err);
+      X, F, ctx->D, ctx->C, P.k, P.prop, nullptr, P.score, P.lscore, P.margin, P.prune, post_idx,
+      post_val, frame_ll, ctx->dev_err);
 }
 
 // Gradients of the soft-target cross-entropy over a batch of B frames into
