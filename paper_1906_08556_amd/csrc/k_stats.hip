@@ -6,11 +6,11 @@
 //  S_c = sum_t gamma_tc x_t x_t^T (FP64 totals): the (frame, component)
 //    posterior entries are bucketed by component with a counting sort
 //    (per-block histograms, a scan, a scatter); one workgroup per component
-//    then accumulates the packed upper triangle in FP64 registers.
+//    then forms (gamma X)^T X on FP64 MFMA over its entries.
 //  Standard formulation (Sec. 2): with a bias m set, every term is centred
 //    before it is accumulated, f~_c(u) = sum_t gamma_tc (x_t - m_c) and
-//    S~_c = sum_t gamma_tc (x_t - m_c)(x_t - m_c)^T, so no large uncentred
-//    sums are formed and cancelled afterwards.
+//    S~_c = sum_t gamma_tc (x_t - m_c)(x_t - m_c)^T (the frames staged as
+//    FP64 x - m_c), so no large uncentred sums are formed and cancelled.
 #include "ivx_internal.h"
 
 namespace ivx {
@@ -141,62 +141,61 @@ k_scatter(int64_t F, int C, const int* __restrict__ post_idx, const float* __res
   }
 }
 
-// S_c += sum over the component's entries of gamma x x^T, packed upper
-// triangle (i <= j, row by row), FP64.  ST = float stages the frames as they
-// are; ST = double stages x - m_c (bias mb, FP64) for the centred form.
-constexpr int SB = 32;  // entries staged per step
-template <typename ST>
+// S_c += sum over the component's entries of gamma x x^T (centred on mb[c]
+// when mb is given) as an FP64 MFMA product (gamma X)^T X over the entries,
+// 64 entries staged at a time in LDS.  Output 64 x 64 (D <= 63, zero
+// padded): wave w computes rows 16w..16w+15 as four 16 x 16 blocks of
+// v_mfma_f64_16x16x4f64; the upper triangle (i <= j < D) is added to S_acc.
+constexpr int SE = 64;      // entries per LDS stage
+constexpr int SLD = 64 + 4; // padded row (doubles)
+typedef double sdoublex4 __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(256)
-k_S_accum(const float* __restrict__ X, int D, const int* __restrict__ coff,
-          const int2* __restrict__ ent, const double* __restrict__ mb, double* __restrict__ S_acc) {
-  extern __shared__ __align__(8) unsigned char s_raw[];
-  ST* xsm = reinterpret_cast<ST*>(s_raw);  // [SB][D]
-  __shared__ float gsm[SB];
+k_S_mfma(const float* __restrict__ X, int D, const int* __restrict__ coff,
+         const int2* __restrict__ ent, const double* __restrict__ mb, double* __restrict__ S_acc) {
+  __shared__ double xs[SE][SLD];  // entry e, feature d: x (or x - m_c)
+  __shared__ double gs[SE];       // gamma of entry e
   const int c = blockIdx.x;
-  const int Dp = D * (D + 1) / 2;
-  const int tid = threadIdx.x;
-  constexpr int MAXM = 8;  // Dp <= 2016 for D <= 63
-  int ii[MAXM], jj[MAXM];
-  double acc[MAXM];
-#pragma unroll
-  for (int m = 0; m < MAXM; ++m) {
-    acc[m] = 0.0;
-    const int k = tid + m * 256;
-    int i = 0, rem = k;
-    while (i < D && rem >= D - i) {
-      rem -= D - i;
-      ++i;
-    }
-    ii[m] = (k < Dp) ? i : 0;
-    jj[m] = (k < Dp) ? i + rem : 0;
-  }
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, q16 = lane >> 4;
   const int e0 = coff[c], e1 = coff[c + 1];
-  for (int eb = e0; eb < e1; eb += SB) {
-    const int ne = min(SB, e1 - eb);
-    __syncthreads();
-    for (int i = tid; i < ne * D; i += 256) {
-      const int e = i / D, d = i - e * D;
-      const float x = X[(int64_t)ent[eb + e].x * D + d];
-      if constexpr (sizeof(ST) == sizeof(double))
-        xsm[i] = (double)x - mb[(size_t)c * D + d];
-      else
-        xsm[i] = x;
-    }
-    if (tid < ne) gsm[tid] = __int_as_float(ent[eb + tid].y);
-    __syncthreads();
-    for (int e = 0; e < ne; ++e) {
-      const double g = (double)gsm[e];
-      const ST* xe = xsm + e * D;
+  const double* mc = mb ? mb + (size_t)c * D : nullptr;
+  sdoublex4 acc[4];
 #pragma unroll
-      for (int m = 0; m < MAXM; ++m)
-        acc[m] += g * ((double)xe[ii[m]] * (double)xe[jj[m]]);
+  for (int j = 0; j < 4; ++j) acc[j] = sdoublex4{0.0, 0.0, 0.0, 0.0};
+  for (int eb = e0; eb < e1; eb += SE) {
+    const int ne = min(SE, e1 - eb);
+    __syncthreads();
+    for (int i = tid; i < SE * 64; i += 256) {
+      const int e = i >> 6, d = i & 63;
+      double v = 0.0;
+      if (e < ne && d < D) {
+        v = (double)X[(int64_t)ent[eb + e].x * D + d];
+        if (mc) v -= mc[d];
+      }
+      xs[e][d] = v;
+    }
+    if (tid < SE) gs[tid] = tid < ne ? (double)__int_as_float(ent[eb + tid].y) : 0.0;
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < SE; k += 4) {
+      const int e = k + q16;
+      const double a = gs[e] * xs[e][16 * w + l16];  // A[m][k] = gamma_e x_e[m]
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xs[e][16 * j + l16], acc[j], 0, 0, 0);
     }
   }
+  // acc[j][r] = S[16 w + 4 r + q16][16 j + l16]
+  const int Dp = D * (D + 1) / 2;
 #pragma unroll
-  for (int m = 0; m < MAXM; ++m) {
-    const int k = tid + m * 256;
-    if (k < Dp) S_acc[(size_t)c * Dp + k] += acc[m];
-  }
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * w + 4 * r + q16, jj = 16 * j + l16;
+      if (i < D && jj < D && i <= jj)
+        S_acc[(size_t)c * Dp + i * D - i * (i - 1) / 2 + (jj - i)] += acc[j][r];
+    }
 }
 
 __global__ void __launch_bounds__(256) k_sum_partial(const double* __restrict__ x, int64_t n,
@@ -255,12 +254,8 @@ void launch_stats_S(ivx_ctx* ctx, const float* X, int64_t F, double* S_acc, hipS
   k_hist<<<nb, 256, ldsc, s>>>(F, ctx->C, ctx->post_idx, ctx->hist);
   k_hist_scan<<<1, 1024, 0, s>>>(nb, ctx->C, ctx->hist, ctx->coff);
   k_scatter<<<nb, 256, ldsc, s>>>(F, ctx->C, ctx->post_idx, ctx->post_val, ctx->hist, ctx->ent);
-  if (ctx->standard)
-    k_S_accum<double><<<ctx->C, 256, sizeof(double) * SB * ctx->D, s>>>(X, ctx->D, ctx->coff,
-                                                                       ctx->ent, ctx->bias, S_acc);
-  else
-    k_S_accum<float><<<ctx->C, 256, sizeof(float) * SB * ctx->D, s>>>(X, ctx->D, ctx->coff,
-                                                                     ctx->ent, nullptr, S_acc);
+  k_S_mfma<<<ctx->C, 256, 0, s>>>(X, ctx->D, ctx->coff, ctx->ent,
+                                  ctx->standard ? ctx->bias : nullptr, S_acc);
 }
 
 void launch_hist_scan(int nb, int C, int* hist, int* coff, hipStream_t s) {
