@@ -349,15 +349,26 @@ k_estep_chol(int R, int nb, int64_t TP, float* __restrict__ Lb, float* __restric
   for (int i = 1; i < nb; ++i) {
     for (int k = wave; k < i; k += 4) {
       floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-      for (int j = k; j < i; ++j) {
-        const float* Gij = L + tile_off(i, j);
-        const float* Wjk = W + tile_off(j, k);
+      // four j steps per round: all their loads first, then the MFMAs
+      for (int j0 = k; j0 < i; j0 += 4) {
+        float av[4][4], bv[4][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float a = Gij[l16 * 16 + 4 * q + q16];
-          const float bb = Wjk[(4 * q + q16) * 16 + l16];
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb, acc, 0, 0, 0);
+        for (int jj = 0; jj < 4; ++jj) {
+          const int j = j0 + jj;
+          const bool ok = j < i;
+          const float* Gij = L + tile_off(i, ok ? j : k);
+          const float* Wjk = W + tile_off(ok ? j : k, k);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            av[jj][q] = ok ? Gij[l16 * 16 + 4 * q + q16] : 0.0f;
+            bv[jj][q] = ok ? Wjk[(4 * q + q16) * 16 + l16] : 0.0f;
+          }
         }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jj][q], bv[jj][q], acc, 0, 0, 0);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) wsc[wave][(4 * q16 + r) * 16 + l16] = acc[r];
@@ -383,15 +394,26 @@ k_estep_chol(int R, int nb, int64_t TP, float* __restrict__ Lb, float* __restric
     int i, j;
     decode_tri(t, i, j);
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k = i; k < nb; ++k) {
-      const float* Wki = W + tile_off(k, i);
-      const float* Wkj = W + tile_off(k, j);
+    // four k steps per round: all their loads first, then the MFMAs
+    for (int k0 = i; k0 < nb; k0 += 4) {
+      float av[4][4], bv[4][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float a = Wki[(4 * q + q16) * 16 + l16];
-        const float bb = Wkj[(4 * q + q16) * 16 + l16];
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb, acc, 0, 0, 0);
+      for (int kk = 0; kk < 4; ++kk) {
+        const int k = k0 + kk;
+        const bool ok = k < nb;
+        const float* Wki = W + tile_off(ok ? k : i, i);
+        const float* Wkj = W + tile_off(ok ? k : i, j);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          av[kk][q] = ok ? Wki[(4 * q + q16) * 16 + l16] : 0.0f;
+          bv[kk][q] = ok ? Wkj[(4 * q + q16) * 16 + l16] : 0.0f;
+        }
       }
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk][q], bv[kk][q], acc, 0, 0, 0);
     }
     float* Pt = L + tile_off(i, j);
 #pragma unroll
