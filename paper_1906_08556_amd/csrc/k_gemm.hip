@@ -30,8 +30,8 @@ constexpr int LDB_S = BN + 32;  // LDS row stride (floats) of the [k][n] tile
 
 template <bool TA, bool TB, int EPI>
 __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs g) {
-  __shared__ float As[2][BK][LDA_S];
-  __shared__ float Bs[2][BK][LDB_S];
+  __shared__ __attribute__((aligned(16))) float As[2][BK][LDA_S];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BK][LDB_S];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;  // wave tile: 128 rows x 64 columns
   const int h = lane >> 5, l32 = lane & 31;
@@ -48,49 +48,96 @@ __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs g) {
   const int kb = split * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
 
-  // global tile loader: 16 elements of A and 8 of B per thread
-  float ra[16], rb[8];
-  auto load = [&](int k0) {
-    if (!TA) {  // row m = tid, 16 consecutive k
-      const int m = m0 + tid;
-#pragma unroll
-      for (int e = 0; e < 16; ++e)
-        ra[e] = (m < g.M && k0 + e < ke) ? A[(int64_t)m * g.lda + k0 + e] : 0.0f;
-    } else {    // row k = tid / 16, 16 consecutive m
-      const int k = k0 + (tid >> 4), mm = m0 + (tid & 15) * 16;
-#pragma unroll
-      for (int e = 0; e < 16; ++e)
-        ra[e] = (k < ke && mm + e < g.M) ? A[(int64_t)k * g.lda + mm + e] : 0.0f;
+  // global tile loader: lanes run along the contiguous dimension of each
+  // operand (coalesced), four consecutive elements per load (float4 where
+  // the rows are 16-byte aligned), 4 loads of A and 2 of B per thread:
+  //  !TA  A[m][k]: m = 64 j + tid / 4,  k = 4 (tid % 4)
+  //   TA  A[k][m]: k = 4 j + tid / 64,  m = 4 (tid % 64)
+  //  !TB  B[k][n]: k = 8 j + tid / 32,  n = 4 (tid % 32)
+  //   TB  B[n][k]: n = 64 j + tid / 4,  k = 4 (tid % 4)
+  const bool vecA = g.lda % 4 == 0 && g.sA % 4 == 0 && reinterpret_cast<uintptr_t>(g.A) % 16 == 0;
+  const bool vecB = g.ldb % 4 == 0 && g.sB % 4 == 0 && reinterpret_cast<uintptr_t>(g.B) % 16 == 0;
+  float4 ra[4], rb[2];
+  // nval: how many of the four consecutive elements at p lie in bounds
+  auto ld4 = [](const float* p, int nval, bool vec) -> float4 {
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (nval >= 4 && vec) {
+      v = *reinterpret_cast<const float4*>(p);
+    } else {
+      if (nval > 0) v.x = p[0];
+      if (nval > 1) v.y = p[1];
+      if (nval > 2) v.z = p[2];
+      if (nval > 3) v.w = p[3];
     }
-    if (!TB) {  // row k = tid / 16, 8 consecutive n
-      const int k = k0 + (tid >> 4), nn = n0 + (tid & 15) * 8;
+    return v;
+  };
+  // tiles inside both operands with aligned rows: unguarded float4 loads
+  const bool inner = vecA && vecB && m0 + BM <= g.M && n0 + BN <= g.N;
+  auto load = [&](int k0) {
+    if (inner && k0 + BK <= ke) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
-        rb[e] = (k < ke && nn + e < g.N) ? B[(int64_t)k * g.ldb + nn + e] : 0.0f;
-    } else {    // row n = tid / 2, 8 consecutive k
-      const int n = n0 + (tid >> 1), kk = k0 + (tid & 1) * 8;
+      for (int j = 0; j < 4; ++j) {
+        const float* p = !TA ? A + (int64_t)(m0 + 64 * j + (tid >> 2)) * g.lda + k0 + 4 * (tid & 3)
+                             : A + (int64_t)(k0 + 4 * j + (tid >> 6)) * g.lda + m0 + 4 * (tid & 63);
+        ra[j] = *reinterpret_cast<const float4*>(p);
+      }
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
-        rb[e] = (n < g.N && kk + e < ke) ? B[(int64_t)n * g.ldb + kk + e] : 0.0f;
+      for (int j = 0; j < 2; ++j) {
+        const float* p = !TB ? B + (int64_t)(k0 + 8 * j + (tid >> 5)) * g.ldb + n0 + 4 * (tid & 31)
+                             : B + (int64_t)(n0 + 64 * j + (tid >> 2)) * g.ldb + k0 + 4 * (tid & 3);
+        rb[j] = *reinterpret_cast<const float4*>(p);
+      }
+      return;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (!TA) {
+        const int m = m0 + 64 * j + (tid >> 2), k = k0 + 4 * (tid & 3);
+        const int nv = m < g.M ? min(4, ke - k) : 0;
+        ra[j] = ld4(A + (int64_t)m * g.lda + k, nv, vecA);
+      } else {
+        const int k = k0 + 4 * j + (tid >> 6), m = m0 + 4 * (tid & 63);
+        const int nv = k < ke ? min(4, g.M - m) : 0;
+        ra[j] = ld4(A + (int64_t)k * g.lda + m, nv, vecA);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (!TB) {
+        const int k = k0 + 8 * j + (tid >> 5), n = n0 + 4 * (tid & 31);
+        const int nv = k < ke ? min(4, g.N - n) : 0;
+        rb[j] = ld4(B + (int64_t)k * g.ldb + n, nv, vecB);
+      } else {
+        const int n = n0 + 64 * j + (tid >> 2), k = k0 + 4 * (tid & 3);
+        const int nv = n < g.N ? min(4, ke - k) : 0;
+        rb[j] = ld4(B + (int64_t)n * g.ldb + k, nv, vecB);
+      }
     }
   };
   auto store = [&](int buf) {
-    if (!TA) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) As[buf][e][tid] = ra[e];
-    } else {
-      const int k = tid >> 4, mm = (tid & 15) * 16;
-#pragma unroll
-      for (int e = 0; e < 16; ++e) As[buf][k][mm + e] = ra[e];
+    for (int j = 0; j < 4; ++j) {
+      if (!TA) {
+        const int m = 64 * j + (tid >> 2), k = 4 * (tid & 3);
+        As[buf][k][m] = ra[j].x;
+        As[buf][k + 1][m] = ra[j].y;
+        As[buf][k + 2][m] = ra[j].z;
+        As[buf][k + 3][m] = ra[j].w;
+      } else {
+        *reinterpret_cast<float4*>(&As[buf][4 * j + (tid >> 6)][4 * (tid & 63)]) = ra[j];
+      }
     }
-    if (!TB) {
-      const int k = tid >> 4, nn = (tid & 15) * 8;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) Bs[buf][k][nn + e] = rb[e];
-    } else {
-      const int n = tid >> 1, kk = (tid & 1) * 8;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) Bs[buf][kk + e][n] = rb[e];
+    for (int j = 0; j < 2; ++j) {
+      if (!TB) {
+        *reinterpret_cast<float4*>(&Bs[buf][8 * j + (tid >> 5)][4 * (tid & 31)]) = rb[j];
+      } else {
+        const int n = 64 * j + (tid >> 2), k = 4 * (tid & 3);
+        Bs[buf][k][n] = rb[j].x;
+        Bs[buf][k + 1][n] = rb[j].y;
+        Bs[buf][k + 2][n] = rb[j].z;
+        Bs[buf][k + 3][n] = rb[j].w;
+      }
     }
   };
 
