@@ -130,7 +130,7 @@ __device__ inline void load4(const float* p, double& a, double& b, double& c, do
 
 // NJ: 16-column blocks per wave (4: 128 x 128 tile, 2: 128 x 64 tile)
 template <int NJ, typename TBe>
-__global__ void __launch_bounds__(256) k_gemm64_tn_128(const float* __restrict__ A, int64_t lda,
+__global__ void __launch_bounds__(256, 4) k_gemm64_tn_128(const float* __restrict__ A, int64_t lda,
                                                        const TBe* __restrict__ B, int64_t ldb,
                                                        double* __restrict__ C, int64_t ldc,
                                                        int N, int K, int m_fast) {
