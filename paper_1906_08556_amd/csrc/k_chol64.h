@@ -30,6 +30,9 @@ __device__ inline doublex4 mma16_xyt(FX x, FY y, doublex4 acc, double s) {
   return acc;
 }
 
+// tiles per wave and round in the update loops
+constexpr int UT = 2;
+
 __device__ inline void tri_decode(int t, int& ii, int& jj) {
   int i = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
   while ((i + 1) * (i + 2) / 2 <= t) ++i;
@@ -88,6 +91,8 @@ __device__ inline int chol_tp64(double* __restrict__ A, int nb, double* __restri
 #pragma unroll
           for (int l = 0; l < i; ++l) s -= dg[i * 16 + l] * w[l];
           w[i] = (i >= j) ? s / dg[i * 16 + i] : 0.0;
+          // one row at a time: keeps the row's LDS reads from piling up in registers
+          __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int i = 0; i < 16; ++i) Winv[k * 256 + i * 16 + j] = w[i];
@@ -113,21 +118,35 @@ __device__ inline int chol_tp64(double* __restrict__ A, int nb, double* __restri
       }
     }
     __syncthreads();
-    // trailing update: A_(k+1+ii),(k+1+jj) -= P_ii P_jj^T, jj <= ii
+    // trailing update: A_(k+1+ii),(k+1+jj) -= P_ii P_jj^T, jj <= ii; each
+    // wave takes UT tiles per round and loads all of them before the MFMAs
+    // (tiles past the end repeat the round's first tile and are not stored)
     const int nt = m * (m + 1) / 2;
-    for (int t = wave; t < nt; t += 4) {
-      int ii, jj;
-      tri_decode(t, ii, jj);
-      double* Ct = A + tp_off(k + 1 + ii, k + 1 + jj);
-      doublex4 acc;
+    for (int t0 = wave; t0 < nt; t0 += 4 * UT) {
+      doublex4 acc[UT];
+      double* Ct[UT];
+      int ii[UT], jj[UT];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = Ct[(4 * r + q16) * 16 + l16];
-      const double* Pi = pan + ii * 256;
-      const double* Pj = pan + jj * 256;
-      acc = mma16_xyt([&](int i, int l) { return Pi[i * 16 + l]; },
-                      [&](int j, int l) { return Pj[j * 16 + l]; }, acc, -1.0);
+      for (int u = 0; u < UT; ++u) {
+        const int t = t0 + 4 * u < nt ? t0 + 4 * u : t0;
+        tri_decode(t, ii[u], jj[u]);
+        Ct[u] = A + tp_off(k + 1 + ii[u], k + 1 + jj[u]);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Ct[(4 * r + q16) * 16 + l16] = acc[r];
+        for (int r = 0; r < 4; ++r) acc[u][r] = Ct[u][(4 * r + q16) * 16 + l16];
+      }
+#pragma unroll
+      for (int u = 0; u < UT; ++u) {
+        const double* Pi = pan + ii[u] * 256;
+        const double* Pj = pan + jj[u] * 256;
+        acc[u] = mma16_xyt([&](int i, int l) { return Pi[i * 16 + l]; },
+                           [&](int j, int l) { return Pj[j * 16 + l]; }, acc[u], -1.0);
+      }
+#pragma unroll
+      for (int u = 0; u < UT; ++u) {
+        if (t0 + 4 * u >= nt) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Ct[u][(4 * r + q16) * 16 + l16] = acc[u][r];
+      }
     }
     __syncthreads();
   }
@@ -165,20 +184,40 @@ __device__ inline void solve_tp64(const double* __restrict__ G, const double* __
         if (row < nrow && d < ncol) B[(int64_t)d * ldb + row] = zb[(4 * r + q16) * 64 + d];
       }
     }
-    // B_i -= G_ik Z_k for i > k
+    // B_i -= G_ik Z_k for i > k (UT tiles per wave and round, loads first)
     const int m = nb - k - 1;
-    for (int w = wave; w < 4 * m; w += 4) {
-      const int it = k + 1 + (w >> 2), d0 = (w & 3) * 16;
-      const double* Gt = G + tp_off(it, k);
-      doublex4 acc;
+    for (int w0 = wave; w0 < 4 * m; w0 += 4 * UT) {
+      doublex4 acc[UT];
+      double gv[UT][4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = bat(it * 16 + 4 * r + q16, d0 + l16);
-      acc = mma16_xyt([&](int i, int l) { return Gt[i * 16 + l]; },
-                      [&](int j, int l) { return zb[l * 64 + d0 + j]; }, acc, -1.0);
+      for (int u = 0; u < UT; ++u) {
+        const int w = w0 + 4 * u < 4 * m ? w0 + 4 * u : w0;
+        const int it = k + 1 + (w >> 2), d0 = (w & 3) * 16;
+        const double* Gt = G + tp_off(it, k);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = it * 16 + 4 * r + q16, d = d0 + l16;
-        if (row < nrow && d < ncol) B[(int64_t)d * ldb + row] = acc[r];
+        for (int r = 0; r < 4; ++r) acc[u][r] = bat(it * 16 + 4 * r + q16, d0 + l16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gv[u][q] = Gt[l16 * 16 + 4 * q + q16];
+      }
+#pragma unroll
+      for (int u = 0; u < UT; ++u) {
+        const int w = w0 + 4 * u < 4 * m ? w0 + 4 * u : w0;
+        const int d0 = (w & 3) * 16;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-gv[u][q], zb[(4 * q + q16) * 64 + d0 + l16],
+                                                        acc[u], 0, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < UT; ++u) {
+        const int w = w0 + 4 * u;
+        if (w >= 4 * m) break;
+        const int it = k + 1 + (w >> 2), d0 = (w & 3) * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = it * 16 + 4 * r + q16, d = d0 + l16;
+          if (row < nrow && d < ncol) B[(int64_t)d * ldb + row] = acc[u][r];
+        }
       }
     }
     __syncthreads();
@@ -202,19 +241,39 @@ __device__ inline void solve_tp64(const double* __restrict__ G, const double* __
         if (row < nrow && d < ncol) B[(int64_t)d * ldb + row] = zb[(4 * r + q16) * 64 + d];
       }
     }
-    // Z_i -= G_ki^T X_k for i < k
-    for (int w = wave; w < 4 * k; w += 4) {
-      const int it = w >> 2, d0 = (w & 3) * 16;
-      const double* Gt = G + tp_off(k, it);
-      doublex4 acc;
+    // Z_i -= G_ki^T X_k for i < k (UT tiles per wave and round, loads first)
+    for (int w0 = wave; w0 < 4 * k; w0 += 4 * UT) {
+      doublex4 acc[UT];
+      double gv[UT][4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = bat(it * 16 + 4 * r + q16, d0 + l16);
-      acc = mma16_xyt([&](int i, int l) { return Gt[l * 16 + i]; },
-                      [&](int j, int l) { return zb[l * 64 + d0 + j]; }, acc, -1.0);
+      for (int u = 0; u < UT; ++u) {
+        const int w = w0 + 4 * u < 4 * k ? w0 + 4 * u : w0;
+        const int it = w >> 2, d0 = (w & 3) * 16;
+        const double* Gt = G + tp_off(k, it);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = it * 16 + 4 * r + q16, d = d0 + l16;
-        if (row < nrow && d < ncol) B[(int64_t)d * ldb + row] = acc[r];
+        for (int r = 0; r < 4; ++r) acc[u][r] = bat(it * 16 + 4 * r + q16, d0 + l16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gv[u][q] = Gt[(4 * q + q16) * 16 + l16];
+      }
+#pragma unroll
+      for (int u = 0; u < UT; ++u) {
+        const int w = w0 + 4 * u < 4 * k ? w0 + 4 * u : w0;
+        const int d0 = (w & 3) * 16;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-gv[u][q], zb[(4 * q + q16) * 64 + d0 + l16],
+                                                        acc[u], 0, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < UT; ++u) {
+        const int w = w0 + 4 * u;
+        if (w >= 4 * k) break;
+        const int it = w >> 2, d0 = (w & 3) * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = it * 16 + 4 * r + q16, d = d0 + l16;
+          if (row < nrow && d < ncol) B[(int64_t)d * ldb + row] = acc[u][r];
+        }
       }
     }
     __syncthreads();

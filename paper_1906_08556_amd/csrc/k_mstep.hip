@@ -80,7 +80,7 @@ k_objective_finish(const double* __restrict__ part, int C, const double* __restr
 // (solve_tp64, in place in T_c), then Sigma_c = sym((S_c - T_c Cc_c^T) / N_c)
 // with T_c Cc_c^T on MFMA, kept only if it is positive definite.  T_c and
 // Sigma_c are untouched when A_c is not positive definite.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
               const double* __restrict__ Cc, const double* __restrict__ N,
               const double* __restrict__ S, int update_sigma, double* __restrict__ T,

@@ -210,24 +210,37 @@ k_estep_chol(int R, int nb, int64_t TP, float* __restrict__ Lb, float* __restric
     }
     __syncthreads();
     // trailing tiles (k+1+ii, k+1+jj), jj <= ii: C -= P_ii P_jj^T
+    // four tiles per wave and round, all loaded before their MFMAs (tiles
+    // past the end repeat the round's first tile and are not stored)
     const int ntile = m * (m + 1) / 2;
-    for (int t = wave; t < ntile; t += 4) {
-      int ii, jj;
-      decode_tri(t, ii, jj);
-      float* Ct = L + tile_off(k + 1 + ii, k + 1 + jj);
-      floatx4 acc;
+    for (int t0 = wave; t0 < ntile; t0 += 16) {
+      floatx4 acc[4];
+      float* Ct[4];
+      int ii[4], jj[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = Ct[(4 * q16 + r) * 16 + l16];
-      const float* Pi = pan + ii * 256;
-      const float* Pj = pan + jj * 256;
+      for (int v = 0; v < 4; ++v) {
+        decode_tri(t0 + 4 * v < ntile ? t0 + 4 * v : t0, ii[v], jj[v]);
+        Ct[v] = L + tile_off(k + 1 + ii[v], k + 1 + jj[v]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float a = -Pi[l16 * 16 + 4 * q + q16];
-        const float bb = Pj[l16 * 16 + 4 * q + q16];
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb, acc, 0, 0, 0);
+        for (int r = 0; r < 4; ++r) acc[v][r] = Ct[v][(4 * q16 + r) * 16 + l16];
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Ct[(4 * q16 + r) * 16 + l16] = acc[r];
+      for (int v = 0; v < 4; ++v) {
+        const float* Pi = pan + ii[v] * 256;
+        const float* Pj = pan + jj[v] * 256;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float a = -Pi[l16 * 16 + 4 * q + q16];
+          const float bb = Pj[l16 * 16 + 4 * q + q16];
+          acc[v] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb, acc[v], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (t0 + 4 * v >= ntile) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Ct[v][(4 * q16 + r) * 16 + l16] = acc[v][r];
+      }
     }
     __syncthreads();
   }
