@@ -142,10 +142,12 @@ k_estep_chol(int R, int nb, int64_t TP, float* __restrict__ Lb, float* __restric
              float* __restrict__ phi, double* __restrict__ llu, int* __restrict__ info,
              int want_cov, int* __restrict__ err) {
   __shared__ float dg[256];
-  __shared__ float pan[(MAXNB - 1) * 256];
+  __shared__ __attribute__((aligned(16))) float pan[(MAXNB - 1) * 256];
   __shared__ float vec[MAXNB * 16];
   __shared__ float wsc[4][256];
-  __shared__ double red[256];
+  // reduction scratch, used only after the factorisation: shares the panel's
+  // memory (keeps the workgroup under 40 KB of LDS, four per CU)
+  double* red = reinterpret_cast<double*>(pan);
   __shared__ int s_bad;
   const int64_t u = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -201,6 +203,9 @@ k_estep_chol(int R, int nb, int64_t TP, float* __restrict__ Lb, float* __restric
 #pragma unroll
         for (int l = 0; l < j; ++l) s -= x[l] * dg[j * 16 + l];
         x[j] = s / dg[j * 16 + j];
+        // one column at a time: keeps the LDS reads of later columns from
+        // being hoisted into registers
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int cc = 0; cc < 16; ++cc) {
