@@ -122,7 +122,7 @@ void ivx_destroy(ivx_ctx* ctx) {
                   ctx->pairs, ctx->T, ctx->Sigma, ctx->p, ctx->bias, ctx->bias32, ctx->cand, ctx->cM, ctx->cflag, ctx->post_idx,
                   ctx->post_val, ctx->frame_ll, ctx->lscore, ctx->hist, ctx->coff, ctx->ent, ctx->partial,
                   ctx->Y32, ctx->V32, ctx->Utp, ctx->Psig, ctx->sig_logdet, ctx->Lbuf, ctx->Wbuf, ctx->Psi64,
-                  ctx->bpart, ctx->bvec, ctx->llu, ctx->n_ws, ctx->f_ws, ctx->Tnew, ctx->obj_part,
+                  ctx->bpart, ctx->colpart, ctx->bvec, ctx->llu, ctx->n_ws, ctx->f_ws, ctx->Tnew, ctx->obj_part,
                   ctx->Gmat, ctx->Mmat, ctx->Winv, ctx->Ut16hi, ctx->Ut16lo, ctx->n16hi,
                   ctx->n16lo, ctx->mvec, ctx->mstat, ctx->dev_err};
   for (void* p : ptrs)
@@ -201,6 +201,7 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   A(dalloc(&c->Wbuf, U * TP));
   A(dalloc(&c->Psi64, U * TP));
   A(dalloc(&c->bpart, (size_t)c->nsplit_max * U * R));
+  A(dalloc(&c->colpart, (size_t)CSPLIT * (C + R + TP)));
   A(dalloc(&c->bvec, U * R));
   A(dalloc(&c->llu, U));
   A(dalloc(&c->n_ws, U * C));

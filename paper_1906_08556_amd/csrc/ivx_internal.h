@@ -11,6 +11,7 @@ namespace ivx {
 
 // Posterior list capacity per frame (entries of post_idx / post_val).
 constexpr int KP = 16;
+constexpr int CSPLIT = 16;  // row chunks of the accumulator column sums
 // Candidate margin in nats: components whose log-likelihood is more than
 // margin(C) = ln C + 16.64 + 2 below the frame's best are dropped.  Their
 // total posterior mass is then below C e^-margin = 2^-24 e^-2, under the FP32
@@ -205,6 +206,7 @@ struct ivx_ctx {
   float* Wbuf = nullptr;      // [maxU][TP] G^{-1}
   double* Psi64 = nullptr;    // [maxU][TP] Psi(u) = Phi(u) + phi phi^T (accumulate call)
   float* bpart = nullptr;     // [nsplit_max][maxU][R]
+  double* colpart = nullptr;  // [CSPLIT][C + R + TP] column-sum partials
   float* bvec = nullptr;      // [maxU][R]
   double* llu = nullptr;      // [maxU]
   float* n_ws = nullptr;      // [maxU][C]   (extract_ivectors)

@@ -90,17 +90,26 @@ k_tv_prep(const double* __restrict__ T, const double* __restrict__ Sigma, int D,
   if (t == 0) logdet[c] = ld;
   __syncthreads();
   for (int e = t; e < D * D; e += 256) Psig[(size_t)c * D * D + e] = A[e];
+  // Y = L^{-1} T_c, V = P T_c: thread t holds column r of T_c in registers
+  // (D <= 63) and forms all D rows of that column from the LDS copies of
+  // L^{-1} and P (same summation order over k as a plain loop)
   const double* Tc = T + (size_t)c * D * R;
-  for (int e = t; e < D * R; e += 256) {
-    const int d = e / R, r = e - d * R;
-    double y = 0.0, v = 0.0;
-    for (int k = 0; k < D; ++k) {
-      const double tk = Tc[(size_t)k * R + r];
-      if (k <= d) y += Li[d * D + k] * tk;
-      v += A[d * D + k] * tk;
+  for (int r = t; r < R; r += 256) {
+    double tk[64];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) tk[k] = (k < D) ? Tc[(size_t)k * R + r] : 0.0;
+    for (int d = 0; d < D; ++d) {
+      double y = 0.0, v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 64; ++k) {
+        if (k < D) {
+          if (k <= d) y += Li[d * D + k] * tk[k];
+          v += A[d * D + k] * tk[k];
+        }
+      }
+      Y32[((size_t)c * D + d) * R + r] = (float)y;
+      V32[((size_t)c * D + d) * R + r] = (float)v;
     }
-    Y32[(size_t)c * D * R + e] = (float)y;
-    V32[(size_t)c * D * R + e] = (float)v;
   }
 }
 
@@ -481,28 +490,46 @@ __global__ void k_packed_to_psi(const float* __restrict__ Phi, const float* __re
   Psi[idx] = v;
 }
 
-// N[c] += sum_u n[u][c]; h[r] += sum_u phi[u][r]; H[e] += sum_u Psi[u][e]; count += U
-__global__ void k_colsums(const float* __restrict__ n, const float* __restrict__ phi,
-                          const double* __restrict__ Psi, int64_t U, int C, int R, int64_t TP,
-                          double* __restrict__ N, double* __restrict__ h, double* __restrict__ H,
-                          double* __restrict__ count) {
+// Column sums over the utterances, in two passes with a fixed order (results
+// do not depend on scheduling): pass 1, blockIdx.y = row chunk s of CSPLIT,
+// part[s][col] = sum over the chunk's u of the column, columns [n | phi | Psi]
+__global__ void k_colsums_part(const float* __restrict__ n, const float* __restrict__ phi,
+                               const double* __restrict__ Psi, int64_t U, int C, int R,
+                               int64_t TP, double* __restrict__ part) {
+  const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t total = C + R + TP;
+  if (col >= total) return;
+  const int64_t ucnt = (U + CSPLIT - 1) / CSPLIT;
+  const int64_t u0 = blockIdx.y * ucnt, u1 = min(U, u0 + ucnt);
+  double s = 0.0;
+  if (col < C) {
+    for (int64_t u = u0; u < u1; ++u) s += n[u * C + col];
+  } else if (col < C + R) {
+    const int64_t r = col - C;
+    for (int64_t u = u0; u < u1; ++u) s += phi[u * R + r];
+  } else {
+    const int64_t e = col - C - R;
+    for (int64_t u = u0; u < u1; ++u) s += Psi[u * TP + e];
+  }
+  part[blockIdx.y * total + col] = s;
+}
+
+// pass 2: N[c] += sum_s part[s][c]; h[r] += ...; H[e] += ...; count += U
+__global__ void k_colsums_fin(const double* __restrict__ part, int64_t U, int C, int R, int64_t TP,
+                              double* __restrict__ N, double* __restrict__ h,
+                              double* __restrict__ H, double* __restrict__ count) {
   const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t total = C + R + TP;
   if (col == 0) count[0] += (double)U;
   if (col >= total) return;
   double s = 0.0;
-  if (col < C) {
-    for (int64_t u = 0; u < U; ++u) s += n[u * C + col];
+  for (int k = 0; k < CSPLIT; ++k) s += part[k * total + col];
+  if (col < C)
     N[col] += s;
-  } else if (col < C + R) {
-    const int64_t r = col - C;
-    for (int64_t u = 0; u < U; ++u) s += phi[u * R + r];
-    h[r] += s;
-  } else {
-    const int64_t e = col - C - R;
-    for (int64_t u = 0; u < U; ++u) s += Psi[u * TP + e];
-    H[e] += s;
-  }
+  else if (col < C + R)
+    h[col - C] += s;
+  else
+    H[col - C - R] += s;
 }
 
 }  // namespace
@@ -551,8 +578,11 @@ void launch_packed_to_psi(ivx_ctx* ctx, const float* Phi, const float* phi, int6
 void launch_colsums(ivx_ctx* ctx, const float* n, const float* phi, const double* Psi, int64_t U,
                     const ivx_accum* acc, hipStream_t s) {
   const int64_t total = ctx->C + ctx->R + ctx->TP;
-  k_colsums<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(n, phi, Psi, U, ctx->C, ctx->R, ctx->TP,
-                                                            acc->N, acc->h, acc->H, acc->count);
+  const unsigned nbx = (unsigned)((total + 255) / 256);
+  k_colsums_part<<<dim3(nbx, CSPLIT), 256, 0, s>>>(n, phi, Psi, U, ctx->C, ctx->R, ctx->TP,
+                                                   ctx->colpart);
+  k_colsums_fin<<<nbx, 256, 0, s>>>(ctx->colpart, U, ctx->C, ctx->R, ctx->TP, acc->N, acc->h,
+                                    acc->H, acc->count);
 }
 
 }  // namespace ivx
