@@ -448,38 +448,51 @@ k_estep_chol(int R, int nb, int64_t TP, float* __restrict__ Lb, float* __restric
   }
 }
 
-// Phi (tile-packed) -> packed upper triangle, row by row
-__global__ void k_tp_to_packed(const float* __restrict__ Ptp, int64_t TP, int R, int64_t U,
-                               float* __restrict__ out) {
-  const int64_t np = (int64_t)R * (R + 1) / 2;
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= U * np) return;
-  const int64_t u = idx / np;
-  int64_t k = idx - u * np;
-  // row i: entries (i, i..R-1); start(i) = i*R - i*(i-1)/2
-  int i = (int)((2.0 * R + 1.0 - sqrt((2.0 * R + 1.0) * (2.0 * R + 1.0) - 8.0 * (double)k)) * 0.5);
-  if (i < 0) i = 0;
-  while (i > 0 && (int64_t)i * R - (int64_t)i * (i - 1) / 2 > k) --i;
-  while ((int64_t)(i + 1) * R - (int64_t)(i + 1) * i / 2 <= k) ++i;
-  const int j = i + (int)(k - ((int64_t)i * R - (int64_t)i * (i - 1) / 2));
-  // element (i, j), i <= j, lives in the lower tile (j, i) at (j & 15, i & 15)
-  out[idx] = Ptp[u * TP + tile_off(j >> 4, i >> 4) + (j & 15) * 16 + (i & 15)];
+// tile t of the tile-packed layout -> its block row / column (t = bi (bi + 1) / 2 + bj)
+__device__ inline void tile_decode(int t, int& bi, int& bj) {
+  int i = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  bi = i;
+  bj = t - i * (i + 1) / 2;
+}
+
+// Phi (tile-packed) -> packed upper triangle, row by row.  One workgroup per
+// (utterance, tile): the tile is read whole, transposed through LDS, and
+// element (i, j), i <= j (lower tile (j, i) at (j & 15, i & 15)) is written
+// with lanes along j, i.e. consecutive packed positions of row i.
+__global__ void __launch_bounds__(256) k_tp_to_packed(const float* __restrict__ Ptp, int64_t TP,
+                                                      int R, float* __restrict__ out) {
+  __shared__ float ts[16][17];
+  const int64_t u = blockIdx.x;
+  const int t = blockIdx.y, tid = threadIdx.x;
+  int bi, bj;
+  tile_decode(t, bi, bj);
+  ts[tid >> 4][tid & 15] = Ptp[u * TP + (int64_t)t * 256 + tid];
+  __syncthreads();
+  const int cl = tid >> 4, rl = tid & 15;
+  const int i = bj * 16 + cl, j = bi * 16 + rl;
+  if (j < R && i <= j) {
+    const int64_t np = (int64_t)R * (R + 1) / 2;
+    out[u * np + (int64_t)i * R - (int64_t)i * (i - 1) / 2 + (j - i)] = ts[rl][cl];
+  }
 }
 
 // Psi(u) = Phi(u) + phi phi^T in tile-packed FP64 (padding zero); the FP32
-// inputs are widened first, so the product phi phi^T is exact
-__global__ void k_packed_to_psi(const float* __restrict__ Phi, const float* __restrict__ phi,
-                                int64_t TP, int R, int64_t U, double* __restrict__ Psi) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= U * TP) return;
-  const int64_t u = idx / TP;
-  const int64_t e = idx - u * TP;
-  const int64_t t = e >> 8;
-  int bi = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while ((int64_t)(bi + 1) * (bi + 2) / 2 <= t) ++bi;
-  while ((int64_t)bi * (bi + 1) / 2 > t) --bi;
-  const int bj = (int)(t - (int64_t)bi * (bi + 1) / 2);
-  const int r = bi * 16 + (int)((e >> 4) & 15), c = bj * 16 + (int)(e & 15);
+// inputs are widened first, so the product phi phi^T is exact.  One
+// workgroup per (utterance, tile): packed entries are read with lanes along
+// the tile's rows (consecutive positions of one packed row below the
+// diagonal), transposed through LDS and the tile written whole.
+__global__ void __launch_bounds__(256) k_packed_to_psi(const float* __restrict__ Phi,
+                                                       const float* __restrict__ phi, int64_t TP,
+                                                       int R, double* __restrict__ Psi) {
+  __shared__ double ts[16][17];
+  const int64_t u = blockIdx.x;
+  const int t = blockIdx.y, tid = threadIdx.x;
+  int bi, bj;
+  tile_decode(t, bi, bj);
+  const int cl = tid >> 4, rl = tid & 15;
+  const int r = bi * 16 + rl, c = bj * 16 + cl;
   double v = 0.0;
   if (r < R && c < R) {
     const int i = c < r ? c : r, j = c < r ? r : c;  // i <= j
@@ -487,7 +500,9 @@ __global__ void k_packed_to_psi(const float* __restrict__ Phi, const float* __re
     v = (double)Phi[u * ((int64_t)R * (R + 1) / 2) + k] +
         (double)phi[u * R + r] * (double)phi[u * R + c];
   }
-  Psi[idx] = v;
+  ts[rl][cl] = v;
+  __syncthreads();
+  Psi[u * TP + (int64_t)t * 256 + tid] = ts[tid >> 4][tid & 15];
 }
 
 // Column sums over the utterances, in two passes with a fixed order (results
@@ -563,16 +578,16 @@ void launch_estep_chol(ivx_ctx* ctx, int64_t U, float* Lb, float* Wb, const floa
 }
 
 void launch_tp_to_packed(ivx_ctx* ctx, const float* Ptp, int64_t U, float* out, hipStream_t s) {
-  const int64_t n = U * (int64_t)ctx->R * (ctx->R + 1) / 2;
-  if (n <= 0) return;
-  k_tp_to_packed<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(Ptp, ctx->TP, ctx->R, U, out);
+  if (U <= 0) return;
+  const unsigned ntile = (unsigned)(ctx->TP / 256);
+  k_tp_to_packed<<<dim3((unsigned)U, ntile), 256, 0, s>>>(Ptp, ctx->TP, ctx->R, out);
 }
 
 void launch_packed_to_psi(ivx_ctx* ctx, const float* Phi, const float* phi, int64_t U, double* Psi,
                           hipStream_t s) {
-  const int64_t n = U * ctx->TP;
-  if (n <= 0) return;
-  k_packed_to_psi<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(Phi, phi, ctx->TP, ctx->R, U, Psi);
+  if (U <= 0) return;
+  const unsigned ntile = (unsigned)(ctx->TP / 256);
+  k_packed_to_psi<<<dim3((unsigned)U, ntile), 256, 0, s>>>(Phi, phi, ctx->TP, ctx->R, Psi);
 }
 
 void launch_colsums(ivx_ctx* ctx, const float* n, const float* phi, const double* Psi, int64_t U,
