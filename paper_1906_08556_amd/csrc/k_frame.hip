@@ -475,20 +475,29 @@ k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __
   if (g >= F) return;  // wave-uniform; no workgroup barriers below
   const int64_t go = fmap ? (int64_t)fmap[g] : g;  // output row
   const int Dp = D * (D + 1) / 2;
+  // every input of the frame is requested at once: features, flag, running
+  // maximum, candidate slots and their exact scores (k_exact_sorted; slots
+  // that were not kept hold stale values and are never read back)
   const double xd = (lane < D) ? (double)X[g * D + lane] : 0.0;
+  const int fl = cflag[g];
+  const float mg = cM[g];
+  int2 e = make_int2(-1, 0);
+  double ls = 0.0;
+  if (lane < KP) {
+    e = cand[g * KP + lane];
+    ls = lscore[g * KP + lane];
+  }
   int m = 0;
   double full_lse = NAN;  // set when all components were scored
-  if (cflag[g] == 0) {
-    const float thr = cM[g] - margin;
-    int ci = -1;
-    if (lane < KP) {
-      const int2 e = cand[g * KP + lane];
-      if (e.x >= 0 && __int_as_float(e.y) >= thr) ci = e.x;
-    }
+  if (fl == 0) {
+    const float thr = mg - margin;
+    const int ci = (e.x >= 0 && __int_as_float(e.y) >= thr) ? e.x : -1;
+    const int ls_lo = __double2loint(ls), ls_hi = __double2hiint(ls);
     for (int s = 0; s < KP; ++s) {
-      const int c = __shfl(ci, s);
+      const int c = __builtin_amdgcn_readlane(ci, s);
       if (c < 0 || c >= C) continue;
-      const double l = lscore[g * KP + s];  // k_exact_sorted
+      const double l = __hiloint2double(__builtin_amdgcn_readlane(ls_hi, s),
+                                        __builtin_amdgcn_readlane(ls_lo, s));
       if (lane == 0) {
         lsh[wave][m] = l;
         ish[wave][m] = c;
