@@ -168,6 +168,26 @@ def test_accumulate_matches_oracle(cfg1):
     assert acc.count.item() == wl.U
 
 
+def test_accumulate_is_deterministic(cfg1):
+    """Two passes over the same batch give bit-identical accumulators: the
+    FP64 GEMMs own their output tiles and the column sums of N, h and H add
+    fixed row chunks in a fixed order (no atomics on this path)."""
+    wl, n, f, S, tv = cfg1
+    ctx = _ctx_tv(wl, tv)
+    n32, f32 = n.astype(np.float32), f.astype(np.float32)
+    e = oracle.estep(n32.astype(np.float64), f32.astype(np.float64), *tv)
+    phi32 = e["phi"].astype(np.float32)
+    Phi32 = packed_upper(e["Phi"]).astype(np.float32)
+    runs = []
+    for _ in range(2):
+        acc = ctx.new_accum()
+        ctx.tv_mstep_accumulate(dev(n32), dev(f32), dev(phi32), dev(Phi32), acc)
+        ctx.sync_status()
+        runs.append([t.cpu().numpy().copy() for t in (acc.A, acc.Cc, acc.N, acc.h, acc.H)])
+    for a, b in zip(*runs):
+        np.testing.assert_array_equal(a, b)
+
+
 def _accum_from_oracle(ctx, ref):
     acc = ctx.new_accum()
     acc.A.copy_(dev(pack_tp(ref["A"])))
