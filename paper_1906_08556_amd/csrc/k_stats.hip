@@ -163,20 +163,39 @@ k_S_mfma(const float* __restrict__ X, int D, const int* __restrict__ coff,
   sdoublex4 acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = sdoublex4{0.0, 0.0, 0.0, 0.0};
-  for (int eb = e0; eb < e1; eb += SE) {
-    const int ne = min(SE, e1 - eb);
-    __syncthreads();
-    for (int i = tid; i < SE * 64; i += 256) {
-      const int e = i >> 6, d = i & 63;
-      double v = 0.0;
-      if (e < ne && d < D) {
-        v = (double)X[(int64_t)ent[eb + e].x * D + d];
-        if (mc) v -= mc[d];
-      }
-      xs[e][d] = v;
+  // stage loader: thread tid stages feature d = tid % 64 of entries
+  // e = tid / 64 + 4 it; the next stage is requested before the current
+  // stage's MFMAs and written to LDS after them
+  constexpr int NIT = SE * 64 / 256;
+  const int dl = tid & 63, el = tid >> 6;
+  float xr[NIT];
+  float gr = 0.0f;
+  int nr = 0;
+  auto gload = [&](int eb) {
+    nr = min(SE, e1 - eb);
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int e = el + 4 * it;
+      xr[it] = (e < nr && dl < D) ? X[(int64_t)ent[eb + e].x * D + dl] : 0.0f;
     }
-    if (tid < SE) gs[tid] = tid < ne ? (double)__int_as_float(ent[eb + tid].y) : 0.0;
+    gr = (tid < nr) ? __int_as_float(ent[eb + tid].y) : 0.0f;
+  };
+  if (e0 < e1) gload(e0);
+  for (int eb = e0; eb < e1; eb += SE) {
     __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int e = el + 4 * it;
+      double v = 0.0;
+      if (e < nr && dl < D) {
+        v = (double)xr[it];
+        if (mc) v -= mc[dl];
+      }
+      xs[e][dl] = v;
+    }
+    if (tid < SE) gs[tid] = (double)gr;
+    __syncthreads();
+    if (eb + SE < e1) gload(eb + SE);
 #pragma unroll 4
     for (int k = 0; k < SE; k += 4) {
       const int e = k + q16;
