@@ -15,7 +15,7 @@
 //                     alone, p stays 0.
 //  k_bias_update      standard formulation, optional (Sec. 5):
 //                     m_c <- m_c + T_c h/U with the T of the M-step.
-//  k_apply_M          T_c <- T_c M for all c (FP64 GEMM, LDS tiles).
+//  k_apply_M          T_c <- T_c M for all c (FP64 MFMA GEMM, LDS tiles).
 #include <cmath>
 
 #include "ivx_internal.h"
@@ -325,13 +325,23 @@ k_bias_update(const double* __restrict__ T, const double* __restrict__ hb, int64
 __global__ void __launch_bounds__(256)
 k_apply_M(const double* __restrict__ T, const double* __restrict__ M, int64_t rows, int R,
           double* __restrict__ Tn) {
-  __shared__ double As[16][64 + 1];
-  __shared__ double Bs[16][64 + 1];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  // 64 x 64 output tile; wave w computes the 32 x 32 quarter (w / 2, w % 2)
+  // as 2 x 2 blocks of v_mfma_f64_16x16x4f64, K staged 16 at a time.  LDS
+  // rows are padded to 80 doubles so that the four K rows a wave reads at
+  // once fall into alternate halves of the banks.
+  constexpr int AL = 64 + 16;
+  __shared__ double As[16][AL];  // [k][row]
+  __shared__ double Bs[16][AL];  // [k][col]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, q16 = lane >> 4;
+  const int wm = w >> 1, wn = w & 1;
   const int64_t r0 = (int64_t)blockIdx.y * 64;
   const int c0 = blockIdx.x * 64;
-  double acc[4][4] = {};
+  doublex4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < R; k0 += 16) {
     for (int e = tid; e < 64 * 16; e += 256) {
       const int rr = e >> 4, kk = e & 15;
@@ -342,29 +352,34 @@ k_apply_M(const double* __restrict__ T, const double* __restrict__ M, int64_t ro
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double av[4], bv[4];
+    for (int ks = 0; ks < 16; ks += 4) {
+      const int k = ks + q16;
+      double av[2], bv[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[kk][ty * 4 + i];
+      for (int i = 0; i < 2; ++i) av[i] = As[k][wm * 32 + i * 16 + l16];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx * 4 + j];
+      for (int j = 0; j < 2; ++j) bv[j] = Bs[k][wn * 32 + j * 16 + l16];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
+  // acc[i][j][r] = Tn[r0 + 32 wm + 16 i + 4 r + q16][c0 + 32 wn + 16 j + l16]
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t row = r0 + ty * 4 + i;
-    if (row >= rows) continue;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int col = c0 + tx * 4 + j;
-      if (col < R) Tn[row * R + col] = acc[i][j];
+    for (int j = 0; j < 2; ++j) {
+      const int col = c0 + wn * 32 + j * 16 + l16;
+      if (col >= R) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + wm * 32 + i * 16 + 4 * r + q16;
+        if (row < rows) Tn[row * R + col] = acc[i][j][r];
+      }
     }
-  }
 }
 
 }  // namespace
