@@ -30,7 +30,7 @@ __device__ inline doublex4 mma16_xyt(FX x, FY y, doublex4 acc, double s) {
   return acc;
 }
 
-// tiles per wave and round in the update loops
+// tiles per wave and pass in the update loops
 constexpr int UT = 2;
 
 __device__ inline void tri_decode(int t, int& ii, int& jj) {
@@ -119,8 +119,8 @@ __device__ inline int chol_tp64(double* __restrict__ A, int nb, double* __restri
     }
     __syncthreads();
     // trailing update: A_(k+1+ii),(k+1+jj) -= P_ii P_jj^T, jj <= ii; each
-    // wave takes UT tiles per round and loads all of them before the MFMAs
-    // (tiles past the end repeat the round's first tile and are not stored)
+    // wave takes UT tiles per pass and loads all of them before the MFMAs
+    // (tiles past the end repeat the pass's first tile and are not stored)
     const int nt = m * (m + 1) / 2;
     for (int t0 = wave; t0 < nt; t0 += 4 * UT) {
       doublex4 acc[UT];
@@ -184,7 +184,7 @@ __device__ inline void solve_tp64(const double* __restrict__ G, const double* __
         if (row < nrow && d < ncol) B[(int64_t)d * ldb + row] = zb[(4 * r + q16) * 64 + d];
       }
     }
-    // B_i -= G_ik Z_k for i > k (UT tiles per wave and round, loads first)
+    // B_i -= G_ik Z_k for i > k (UT tiles per wave and pass, loads first)
     const int m = nb - k - 1;
     for (int w0 = wave; w0 < 4 * m; w0 += 4 * UT) {
       doublex4 acc[UT];
@@ -241,7 +241,7 @@ __device__ inline void solve_tp64(const double* __restrict__ G, const double* __
         if (row < nrow && d < ncol) B[(int64_t)d * ldb + row] = zb[(4 * r + q16) * 64 + d];
       }
     }
-    // Z_i -= G_ki^T X_k for i < k (UT tiles per wave and round, loads first)
+    // Z_i -= G_ki^T X_k for i < k (UT tiles per wave and pass, loads first)
     for (int w0 = wave; w0 < 4 * k; w0 += 4 * UT) {
       doublex4 acc[UT];
       double gv[UT][4];

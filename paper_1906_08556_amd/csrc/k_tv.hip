@@ -224,8 +224,8 @@ k_estep_chol(int R, int nb, int64_t TP, float* __restrict__ Lb, float* __restric
     }
     __syncthreads();
     // trailing tiles (k+1+ii, k+1+jj), jj <= ii: C -= P_ii P_jj^T
-    // four tiles per wave and round, all loaded before their MFMAs (tiles
-    // past the end repeat the round's first tile and are not stored)
+    // four tiles per wave and pass, all loaded before their MFMAs (tiles
+    // past the end repeat the pass's first tile and are not stored)
     const int ntile = m * (m + 1) / 2;
     for (int t0 = wave; t0 < ntile; t0 += 16) {
       floatx4 acc[4];
@@ -376,7 +376,7 @@ k_estep_chol(int R, int nb, int64_t TP, float* __restrict__ Lb, float* __restric
   for (int i = 1; i < nb; ++i) {
     for (int k = wave; k < i; k += 4) {
       floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-      // four j steps per round: all their loads first, then the MFMAs
+      // four j steps per pass: all their loads first, then the MFMAs
       for (int j0 = k; j0 < i; j0 += 4) {
         float av[4][4], bv[4][4];
 #pragma unroll
@@ -421,7 +421,7 @@ k_estep_chol(int R, int nb, int64_t TP, float* __restrict__ Lb, float* __restric
     int i, j;
     decode_tri(t, i, j);
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    // four k steps per round: all their loads first, then the MFMAs
+    // four k steps per pass: all their loads first, then the MFMAs
     for (int k0 = i; k0 < nb; k0 += 4) {
       float av[4][4], bv[4][4];
 #pragma unroll
