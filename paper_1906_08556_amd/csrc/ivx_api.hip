@@ -22,13 +22,17 @@ int prof_begin(ivx_ctx* ctx, int k, hipStream_t s) {
   if (!ctx || !ctx->prof_on || ctx->prof_used >= ctx->prof_cap) return -1;
   const int slot = ctx->prof_used++;
   ctx->prof_kind[slot] = k;
-  hipEventRecord(ctx->prof_ev[2 * slot], s);
+  if (hipEventRecord(ctx->prof_ev[2 * slot], s) != hipSuccess) {
+    --ctx->prof_used;  // slot not started: the group goes untimed
+    return -1;
+  }
   return slot;
 }
 
 void prof_end(ivx_ctx* ctx, int slot, hipStream_t s) {
   if (slot < 0) return;
-  hipEventRecord(ctx->prof_ev[2 * slot + 1], s);
+  // a failed record leaves this slot out of the totals (no elapsed time)
+  (void)hipEventRecord(ctx->prof_ev[2 * slot + 1], s);
 }
 
 static void prof_free(ivx_ctx* ctx) {

@@ -20,7 +20,7 @@ void selector_free(ivx_ctx* ctx) {
                   S->xs, S->a1, S->h1,
                   S->a2, S->h2, S->z, S->dz, S->dh1, S->dh2, S->loss_part, S->colpart};
   for (void* p : ptrs)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);  // teardown
   delete S;
   ctx->sel = nullptr;
 }
@@ -31,7 +31,7 @@ void presel_free(ivx_ctx* ctx) {
   void* ptrs[] = {P->Wd, P->pairs, P->prop, P->score, P->thr, P->lscore, P->hist, P->coff,
                   P->ent};
   for (void* p : ptrs)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);  // teardown
   delete P;
   ctx->presel = nullptr;
 }
@@ -280,8 +280,7 @@ ivx_status ivx_selector_forward(ivx_ctx* ctx, const float* X, int64_t F, uint16_
   if (F == 0) return IVX_OK;
   hipStream_t s = as_stream(stream);
   Selector& S = *ctx->sel;
-  launch_selector_mlp(ctx, X, F, h1, h2, z, s);
-  bool ok = true;
+  bool ok = launch_selector_mlp(ctx, X, F, h1, h2, z, s);
   if (prop)
     ok = ok && hipMemcpyAsync(prop, S.prop, sizeof(int) * F * S.k, hipMemcpyDeviceToDevice, s) ==
                    hipSuccess;

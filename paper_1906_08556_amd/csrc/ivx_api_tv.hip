@@ -257,11 +257,13 @@ ivx_status tv_mindiv(ivx_ctx* ctx, const ivx_accum* acc, int method, void* strea
     set_error("tv_mindiv: hipSetDevice failed");
     return IVX_EDEVICE;
   }
+  ivx_status st;
   {
     ProfScope ps(ctx, PK_MINDIV, as_stream(stream));
-    launch_mindiv(ctx, acc, ctx->standard, false, as_stream(stream));
+    st = launch_mindiv(ctx, acc, ctx->standard, false, as_stream(stream));
   }
   ctx->tv_dirty = true;
+  if (st != IVX_OK) return st;
   return after_launch("tv_mindiv");
 }
 
@@ -277,11 +279,13 @@ ivx_status tv_mindiv_standard(ivx_ctx* ctx, const ivx_accum* acc, int method, in
     set_error("tv_mindiv_standard: hipSetDevice failed");
     return IVX_EDEVICE;
   }
+  ivx_status st;
   {
     ProfScope ps(ctx, PK_MINDIV, as_stream(stream));
-    launch_mindiv(ctx, acc, true, update_mean != 0, as_stream(stream));
+    st = launch_mindiv(ctx, acc, true, update_mean != 0, as_stream(stream));
   }
   ctx->tv_dirty = true;
+  if (st != IVX_OK) return st;
   return after_launch("tv_mindiv_standard");
 }
 

@@ -69,7 +69,7 @@ void be_free(ivx_backend* b) {
                   b->Wh, b->T1, b->T2, b->coef, b->muA, b->Z1, b->Z2, b->idx, b->flags,
                   b->rot, b->part};
   for (void* p : ptrs)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);  // teardown
   delete b;
 }
 
@@ -175,7 +175,7 @@ ivx_status ivx_backend_create(int32_t max_dim, int64_t max_n, int32_t max_classe
 
 void ivx_backend_destroy(ivx_backend* b) {
   if (!b) return;
-  hipSetDevice(b->device);
+  (void)hipSetDevice(b->device);  // teardown: best effort
   hipDeviceSynchronize();
   be_free(b);
 }

@@ -36,8 +36,8 @@ extern "C" {
 
 void ivx_graph_destroy(ivx_graph* g) {
   if (!g) return;
-  if (g->exec) hipGraphExecDestroy(g->exec);
-  if (g->graph) hipGraphDestroy(g->graph);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
   if (g->cap) hipStreamDestroy(g->cap);
   delete g;
 }

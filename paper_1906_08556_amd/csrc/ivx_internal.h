@@ -307,7 +307,7 @@ void launch_selector_pack(ivx_ctx* ctx, hipStream_t s);
 void launch_feature_stats(ivx_ctx* ctx, const float* X, int64_t F, float* mean, float* stdv,
                           hipStream_t s);
 void launch_selector_inv_std(ivx_ctx* ctx, hipStream_t s);
-void launch_selector_mlp(ivx_ctx* ctx, const float* X, int64_t F, uint16_t* h1_out,
+bool launch_selector_mlp(ivx_ctx* ctx, const float* X, int64_t F, uint16_t* h1_out,
                          uint16_t* h2_out, float* z_out, hipStream_t s);
 void launch_select_learned(ivx_ctx* ctx, const float* X, int64_t F, int prec, int* post_idx,
                            float* post_val, double* frame_ll, hipStream_t s);

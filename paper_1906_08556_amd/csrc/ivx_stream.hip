@@ -59,9 +59,9 @@ namespace {
 
 void stream_free(ivx_stream* st) {
   for (float* p : st->hX)
-    if (p) hipHostFree(p);
+    if (p) (void)hipHostFree(p);
   for (int64_t* p : st->hoff)
-    if (p) hipHostFree(p);
+    if (p) (void)hipHostFree(p);
   for (int i = 0; i < 2; ++i) {
     if (st->dX[i]) hipFree(st->dX[i]);
     if (st->doff[i]) hipFree(st->doff[i]);

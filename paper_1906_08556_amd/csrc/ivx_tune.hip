@@ -34,8 +34,8 @@ struct Timer {
     ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
   }
   ~Timer() {
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
   }
   // best of `reps` timed runs after one untimed run; ms, or INFINITY on error
   template <typename Fn>

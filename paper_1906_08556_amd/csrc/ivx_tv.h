@@ -23,8 +23,9 @@ void launch_objective(ivx_ctx* ctx, const double* N, const double* S, const doub
                       double* objective, hipStream_t s);
 void launch_mstep_solve(ivx_ctx* ctx, const ivx_accum* acc, const double* S, int update_sigma,
                         int* status, hipStream_t s);
-// standard: M = L_G only (Sec. 3.1); update_mean (standard only): bias += T h/U first
-void launch_mindiv(ivx_ctx* ctx, const ivx_accum* acc, bool standard, bool update_mean,
-                   hipStream_t s);
+// standard: M = L_G only (Sec. 3.1); update_mean (standard only): bias += T h/U first.
+// IVX_EDEVICE (message set) when the copy of the updated T cannot be queued.
+ivx_status launch_mindiv(ivx_ctx* ctx, const ivx_accum* acc, bool standard, bool update_mean,
+                         hipStream_t s);
 
 }  // namespace ivx

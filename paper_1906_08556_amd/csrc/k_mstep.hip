@@ -413,8 +413,8 @@ void launch_mstep_solve(ivx_ctx* ctx, const ivx_accum* acc, const double* S, int
       ctx->Sigma, ctx->Winv, status, ctx->dev_err);
 }
 
-void launch_mindiv(ivx_ctx* ctx, const ivx_accum* acc, bool standard, bool update_mean,
-                   hipStream_t s) {
+ivx_status launch_mindiv(ivx_ctx* ctx, const ivx_accum* acc, bool standard, bool update_mean,
+                         hipStream_t s) {
   const int nb = (ctx->R + 15) / 16;
   k_mindiv_setup<<<1, 256, sizeof(double) * 256 * nb, s>>>(
       ctx->R, nb, acc->h, acc->H, acc->count, standard ? 1 : 0, ctx->Gmat, ctx->Winv, ctx->Mmat,
@@ -429,7 +429,12 @@ void launch_mindiv(ivx_ctx* ctx, const ivx_accum* acc, bool standard, bool updat
   k_apply_M<<<grid, 256, 0, s>>>(ctx->T, ctx->Mmat, rows, ctx->R, ctx->Tnew);
   // copy back on the stream (no host-side pointer swap, so a captured graph
   // replays correctly)
-  hipMemcpyAsync(ctx->T, ctx->Tnew, sizeof(double) * rows * ctx->R, hipMemcpyDeviceToDevice, s);
+  if (hipMemcpyAsync(ctx->T, ctx->Tnew, sizeof(double) * rows * ctx->R, hipMemcpyDeviceToDevice,
+                     s) != hipSuccess) {
+    set_error("tv_mindiv: queueing the copy of the updated T failed");
+    return IVX_EDEVICE;
+  }
+  return IVX_OK;
 }
 
 }  // namespace ivx

@@ -1077,8 +1077,9 @@ void launch_selector_inv_std(ivx_ctx* ctx, hipStream_t s) {
 }
 
 // MLP forward over frames [0, F) with proposals, masses and the fallback
-// list; optional copies of h1, h2 (BF16 bits) and z for inspection.
-void launch_selector_mlp(ivx_ctx* ctx, const float* X, int64_t F, uint16_t* h1_out,
+// list; optional copies of h1, h2 (BF16 bits) and z for inspection.  Returns
+// false when one of those copies could not be queued.
+bool launch_selector_mlp(ivx_ctx* ctx, const float* X, int64_t F, uint16_t* h1_out,
                          uint16_t* h2_out, float* z_out, hipStream_t s) {
   Selector& S = *ctx->sel;
   k_fill_i32<<<1, 64, 0, s>>>(S.counters, 4, 0);
@@ -1107,13 +1108,14 @@ void launch_selector_mlp(ivx_ctx* ctx, const float* X, int64_t F, uint16_t* h1_o
         IVX_L3(32);
 #undef IVX_L3
     }
-    if (h1_out)
-      hipMemcpyAsync(h1_out + r0 * S.H1, S.h1b, sizeof(uint16_t) * rows * S.H1,
-                     hipMemcpyDeviceToDevice, s);
-    if (h2_out)
-      hipMemcpyAsync(h2_out + r0 * S.H2, S.h2b, sizeof(uint16_t) * rows * S.H2,
-                     hipMemcpyDeviceToDevice, s);
+    if (h1_out && hipMemcpyAsync(h1_out + r0 * S.H1, S.h1b, sizeof(uint16_t) * rows * S.H1,
+                                 hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return false;
+    if (h2_out && hipMemcpyAsync(h2_out + r0 * S.H2, S.h2b, sizeof(uint16_t) * rows * S.H2,
+                                 hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return false;
   }
+  return true;
 }
 
 // Exact FP64 scores of the proposals within the margin of each frame's best
@@ -1135,7 +1137,7 @@ void launch_select_learned(ivx_ctx* ctx, const float* X, int64_t F, int prec, in
                            float* post_val, double* frame_ll, hipStream_t s) {
   if (F <= 0) return;
   Selector& S = *ctx->sel;
-  launch_selector_mlp(ctx, X, F, nullptr, nullptr, nullptr, s);
+  (void)launch_selector_mlp(ctx, X, F, nullptr, nullptr, nullptr, s);  // no copies asked for
   {
     ProfScope ps(ctx, PK_SEL_SCORE, s);
     const int nb = (int)((F + HBS - 1) / HBS);
