@@ -37,7 +37,7 @@ void prof_end(ivx_ctx* ctx, int slot, hipStream_t s) {
 
 static void prof_free(ivx_ctx* ctx) {
   if (ctx->prof_ev) {
-    for (int i = 0; i < 2 * ctx->prof_cap; ++i) hipEventDestroy(ctx->prof_ev[i]);
+    for (int i = 0; i < 2 * ctx->prof_cap; ++i) (void)hipEventDestroy(ctx->prof_ev[i]);
     delete[] ctx->prof_ev;
     delete[] ctx->prof_kind;
   }
@@ -114,9 +114,9 @@ int64_t ivx_tp_size(int32_t R) { return R > 0 ? tp_size(R) : 0; }
 
 void ivx_destroy(ivx_ctx* ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   if (ctx->prof_ev) {
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     prof_free(ctx);
   }
   selector_free(ctx);
@@ -130,7 +130,7 @@ void ivx_destroy(ivx_ctx* ctx) {
                   ctx->Gmat, ctx->Mmat, ctx->Winv, ctx->Ut16hi, ctx->Ut16lo, ctx->n16hi,
                   ctx->n16lo, ctx->mvec, ctx->mstat, ctx->dev_err};
   for (void* p : ptrs)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   delete ctx;
 }
 
@@ -227,7 +227,7 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   A(dalloc(&c->dev_err, 4));
   if (!ok) {
     ivx_destroy(c);
-    hipGetLastError();
+    (void)hipGetLastError();
     set_error("ivx_create: device allocation failed");
     return IVX_ENOMEM;
   }

@@ -184,7 +184,7 @@ ivx_status ivx_selector_set(ivx_ctx* ctx, const ivx_selector_dims* sd, const flo
   }
   if (!ok) {
     selector_free(ctx);
-    hipGetLastError();
+    (void)hipGetLastError();
     set_error("ivx_selector_set: device allocation failed");
     return IVX_ENOMEM;
   }
@@ -236,7 +236,7 @@ ivx_status ivx_pruned_set(ivx_ctx* ctx, int32_t k, float prune, void* stream) {
   A(salloc(&P->ent, maxF * k));
   if (!ok) {
     presel_free(ctx);
-    hipGetLastError();
+    (void)hipGetLastError();
     set_error("ivx_pruned_set: device allocation failed");
     return IVX_ENOMEM;
   }

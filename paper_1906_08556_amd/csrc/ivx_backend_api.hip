@@ -176,7 +176,7 @@ ivx_status ivx_backend_create(int32_t max_dim, int64_t max_n, int32_t max_classe
 void ivx_backend_destroy(ivx_backend* b) {
   if (!b) return;
   (void)hipSetDevice(b->device);  // teardown: best effort
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   be_free(b);
 }
 

@@ -38,7 +38,7 @@ void ivx_graph_destroy(ivx_graph* g) {
   if (!g) return;
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
-  if (g->cap) hipStreamDestroy(g->cap);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
   delete g;
 }
 
@@ -97,7 +97,7 @@ ivx_status ivx_graph_create_em(ivx_ctx* ctx, const float* X, const int64_t* utt_
   ctx->prof_on = prof;
   ctx->tv_dirty = true;
   if (st != IVX_OK || ec != hipSuccess || !graph) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     ivx_graph_destroy(g);
     if (st == IVX_OK) {
       set_error("ivx_graph_create_em: stream capture failed: %s", hipGetErrorString(ec));

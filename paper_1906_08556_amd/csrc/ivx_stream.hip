@@ -63,16 +63,16 @@ void stream_free(ivx_stream* st) {
   for (int64_t* p : st->hoff)
     if (p) (void)hipHostFree(p);
   for (int i = 0; i < 2; ++i) {
-    if (st->dX[i]) hipFree(st->dX[i]);
-    if (st->doff[i]) hipFree(st->doff[i]);
-    if (st->computed[i]) hipEventDestroy(st->computed[i]);
+    if (st->dX[i]) (void)hipFree(st->dX[i]);
+    if (st->doff[i]) (void)hipFree(st->doff[i]);
+    if (st->computed[i]) (void)hipEventDestroy(st->computed[i]);
   }
   for (hipEvent_t e : st->copied)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   void* ptrs[] = {st->n, st->f, st->phi, st->Phi};
   for (void* p : ptrs)
-    if (p) hipFree(p);
-  if (st->copy) hipStreamDestroy(st->copy);
+    if (p) (void)hipFree(p);
+  if (st->copy) (void)hipStreamDestroy(st->copy);
   delete st;
 }
 
@@ -256,10 +256,10 @@ ivx_status ivx_stream_create(ivx_ctx* ctx, const ivx_stream_config* cfg, ivx_str
 
 void ivx_stream_destroy(ivx_stream* st) {
   if (!st) return;
-  hipSetDevice(st->ctx->device);
-  if (st->copy) hipStreamSynchronize(st->copy);
+  (void)hipSetDevice(st->ctx->device);
+  if (st->copy) (void)hipStreamSynchronize(st->copy);
   for (int i = 0; i < 2; ++i)  // the last batches may still be computing
-    if (st->used[i]) hipEventSynchronize(st->computed[i]);
+    if (st->used[i]) (void)hipEventSynchronize(st->computed[i]);
   stream_free(st);
 }
 
