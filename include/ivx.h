@@ -79,7 +79,10 @@ typedef enum { IVX_SEL_ALL = 0, IVX_SEL_LEARNED = 1, IVX_SEL_PRUNED = 2 } ivx_se
  *   C  UBM components (>= 1), D feature dimension (1..63), R latent
  *   dimension including the offset dimension (2..480).
  *   max_batch_utts    largest U accepted by the utterance-batch calls.
- *   max_batch_frames  largest F accepted by the frame-batch calls. */
+ *   max_batch_frames  largest F accepted by the frame-batch calls, at most
+ *                     2^31 / 32 - 1 = 67,108,863 (per-frame candidate and
+ *                     proposal slots are numbered in 32-bit ints); ivx_create
+ *                     returns IVX_EINVAL above it. */
 typedef struct {
   int32_t C, D, R;
   int32_t max_batch_utts;

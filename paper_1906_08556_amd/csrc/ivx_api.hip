@@ -141,8 +141,13 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   IVX_CHECK(dims->D >= 1 && dims->D <= 63, "ivx_create: D=%d out of range [1, 63]", dims->D);
   IVX_CHECK(dims->R >= 2 && dims->R <= 480, "ivx_create: R=%d out of range [2, 480]", dims->R);
   IVX_CHECK(dims->max_batch_utts >= 1, "ivx_create: max_batch_utts must be >= 1");
-  IVX_CHECK(dims->max_batch_frames >= 1 && dims->max_batch_frames <= (int64_t(1) << 28),
-            "ivx_create: max_batch_frames out of range [1, 2^28]");
+  // candidate, posterior and proposal slots are addressed as frame * slots
+  // in 32-bit ints (slots <= max(KP, kMaxProposals)), so every slot id of a
+  // batch must stay below 2^31
+  const int64_t max_frames = int64_t(INT32_MAX) / (KP > kMaxProposals ? KP : kMaxProposals);
+  IVX_CHECK(dims->max_batch_frames >= 1 && dims->max_batch_frames <= max_frames,
+            "ivx_create: max_batch_frames=%lld out of range [1, %lld]",
+            (long long)dims->max_batch_frames, (long long)max_frames);
   int ndev = 0;
   IVX_HIP(hipGetDeviceCount(&ndev));
   IVX_CHECK(device >= 0 && device < ndev, "ivx_create: device %d not present (%d visible)", device,

@@ -54,6 +54,11 @@ def test_host_validation_without_gpu():
     assert b"C=0" in lib.ivx_last_error()
     bad = ivx.Dims(16, 64, 400, 10, 1000)
     assert lib.ivx_create(ctypes.byref(bad), 0, ctypes.byref(h)) == -1
+    # slot ids (frame * 32 proposal slots) must fit in int32: 2^26 frames is
+    # the first batch size refused, 2^26 - 1 the last accepted by the check
+    big = ivx.Dims(16, 20, 32, 10, 1 << 26)
+    assert lib.ivx_create(ctypes.byref(big), 0, ctypes.byref(h)) == -1
+    assert b"max_batch_frames=67108864 out of range [1, 67108863]" in lib.ivx_last_error()
     # null context is rejected before any HIP call
     assert lib.ubm_posteriors(None, None, 0, 0, 0, None, None, None, 8, None, None) == -1
     assert lib.bw_stats(None, None, None, 1, 0, 0, 0, None, None, None, None, None) == -1
