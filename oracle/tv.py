@@ -100,7 +100,7 @@ def tv_precompute(T, Sigma):
     return V, Uc
 
 
-def estep(n, f, T, Sigma, p, want_cov=True):
+def estep(n, f, T, Sigma, p, want_cov=True, pre=None):
     """Posterior precision / covariance / mean of the latent vector per utterance.
 
     L(u)   = I + sum_c n_c(u) T_c^T Sigma_c^{-1} T_c      (inverse of eq. (3))
@@ -110,10 +110,12 @@ def estep(n, f, T, Sigma, p, want_cov=True):
     ll(u)  = -1/2 log|L(u)| + 1/2 b(u)^T phi(u) - 1/2 p^T p
     ll(u) is the utterance's share of the marginal log-likelihood of the
     alignment-weighted statistics (the latent vector integrated out).
+    ``pre`` may pass (V, U) from tv_precompute(T, Sigma) when they are
+    already at hand.
     """
     C, D, R = T.shape
     U = n.shape[0]
-    V, Uc = tv_precompute(T, Sigma)
+    V, Uc = pre if pre is not None else tv_precompute(T, Sigma)
     Lu = np.eye(R)[None] + (n @ Uc.reshape(C, R * R)).reshape(U, R, R)
     b = p[None, :] + f.reshape(U, C * D) @ V.reshape(C * D, R)
     phi = np.empty((U, R))
@@ -321,12 +323,15 @@ def preselect(ll_diag, k):
     return order[:, :k]
 
 
-def pruned_posteriors(X, w, mu, cov, idx, prune=0.025):
+def pruned_posteriors(X, w, mu, cov, idx, prune=0.025, ll=None):
     """Full-covariance posteriors restricted to the preselected components
     idx [F, k] and renormalised over them; entries below `prune` are then
     dropped and the rest renormalised.  Returns the dense [F, C] posteriors
-    and the per-frame log-likelihood over the preselected set."""
-    ll = frame_loglik(X, w, mu, cov)
+    and the per-frame log-likelihood over the preselected set.  ``ll`` may
+    pass the frames' full-covariance log-likelihoods (frame_loglik) when
+    they are already at hand."""
+    if ll is None:
+        ll = frame_loglik(X, w, mu, cov)
     sub = np.take_along_axis(ll, idx, axis=1)
     g_sub, lse = posteriors(sub)
     g_sub = np.where(g_sub < prune, 0.0, g_sub)

@@ -123,3 +123,102 @@ def test_graph_on_bf16_path_matches_eager_bf16():
     print("bf16 graph vs eager max |dn|", dn)
     assert dn <= 1e-5
     g.close()
+
+
+@pytest.fixture(scope="module")
+def loguniform_workload():
+    """The batching workload scaled down: 40 utterances with log-uniform
+    200-3000-frame lengths (about 41k frames) at the full model shape
+    (D 60, C 2048, R 400), and the oracle's iteration from its initial state
+    with realignment."""
+    import oracle
+    wl = synth.make(4, U=40)
+    assert wl.shape.lengths == "loguniform:200:3000"
+    tv = oracle.init_tv(wl.mu, wl.cov, wl.T_init)
+    r = oracle.em_iteration(wl.X, wl.utt_off, (wl.w, wl.mu, wl.cov), tv, realign=True)
+    return wl, tv, r
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16"])
+def test_graph_replay_matches_the_oracle_on_loguniform_lengths(loguniform_workload, prec):
+    """One replay of the captured iteration (posteriors, statistics, E-step,
+    accumulation, M-step with the Sigma update, minimum divergence,
+    realignment) from the oracle's state against the oracle's iteration:
+    the bounds of the eager full-shape iteration (objective <= 1e-6
+    relative, T_c <= 1e-3 per component, Sigma, p and the realigned means
+    <= 1e-4), in both precision forms.  The skip decision N_c < 0.5 may
+    differ only for components within rounding of 0.5.
+
+    A new Sigma_c that is not positive definite is rejected (the old one
+    kept).  With about 17 frames per component here, many residual
+    covariances (S_c - T_c Cc_c^T) / N_c are rank-deficient up to the
+    contributions of frames with negligible posteriors, which the GPU drops
+    below the candidate margin (mass < 2^-24 e^-2) and the oracle keeps:
+    for those the decision is not fixed by the method.  A component whose
+    Sigma differs is therefore accepted only when the two sides took
+    different decisions and the side that accepted holds a numerically
+    singular Sigma (smallest / largest eigenvalue <= 1e-4); every other
+    component must match to 1e-4."""
+    wl, tv, r = loguniform_workload
+    U, C, D, R = wl.U, wl.shape.C, wl.shape.D, wl.shape.R
+    X, off = dev(wl.X), dev(wl.utt_off)
+    cg = make_ctx(wl)
+    cg.set_tv(dev(tv[0]), dev(tv[1]), dev(tv[2]))
+    acc = cg.new_accum()
+    for t in (acc.A, acc.Cc, acc.N, acc.h, acc.H, acc.count):
+        t.fill_(1e30)   # the graph must clear what it accumulates
+    b = _graph_buffers(wl)
+    g = cg.graph_create_em(X, off, b["n"], b["f"], b["S"], b["phi"], b["Phi"], acc,
+                           b["ll_frames"], b["ll_utts"], b["objective"], update_sigma=True,
+                           realign=True, prec=prec)
+    torch.cuda.synchronize()
+    _ = torch.ones(1024, device="cuda").sum().item()   # unrelated eager work before the replay
+    g.launch()
+    cg.sync_status()
+    torch.cuda.synchronize()
+    Tg, Sg, pg, mug = [t.cpu().numpy() for t in cg.get_tv()]
+    obj = b["objective"].item()
+    llf = b["ll_frames"].item()
+    g.close()
+    Ng = acc.N.cpu().numpy()
+    N = r["acc"]["N"]
+    skip_o = np.zeros(C, bool)
+    skip_o[r["mstep_info"]["skipped"]] = True
+    skip_g = Ng < 0.5
+    differ = skip_g != skip_o
+    assert np.all(np.abs(N[differ] - 0.5) <= 1e-5)
+    same = ~differ
+    t_err = np.linalg.norm((Tg - r["T"]).reshape(C, -1), axis=1) / \
+        np.linalg.norm(r["T"].reshape(C, -1), axis=1)
+    obj_rel = abs(obj - r["objective"]) / abs(r["objective"])
+    llf_rel = abs(llf - r["lse"].sum()) / abs(r["lse"].sum())
+    cos = np.sum(b["phi"].cpu().numpy() * r["estep"]["phi"], 1) / (
+        np.linalg.norm(b["phi"].cpu().numpy(), axis=1) * np.linalg.norm(r["estep"]["phi"], axis=1))
+    print(f"graph replay ({'BF16' if prec else 'FP32'}), {U} utterances, {wl.F} frames, lengths "
+          f"{np.diff(wl.utt_off).min()}-{np.diff(wl.utt_off).max()}: objective rel {obj_rel:.2e}  "
+          f"frame ll rel {llf_rel:.2e}  min i-vector cos {cos.min():.9f}  T_c rel median "
+          f"{np.median(t_err[same]):.2e} max {t_err[same].max():.2e}  Sigma relfro "
+          f"{relfro(Sg, r['Sigma']):.2e}  p0 {pg[0]:.6f} vs {r['p'][0]:.6f}  mu relfro "
+          f"{relfro(mug[same], r['mu'][same]):.2e}")
+    assert llf_rel <= 1e-9
+    assert cos.min() >= 0.9999
+    assert obj_rel <= 1e-6
+    assert t_err[same].max() <= 1e-3
+    So = r["Sigma"]
+    s_err = np.linalg.norm((Sg - So).reshape(C, -1), axis=1) / np.linalg.norm(So.reshape(C, -1), axis=1)
+    rej_o = np.zeros(C, bool)
+    rej_o[r["mstep_info"]["notpd"]] = True
+    rej_g = np.all((Sg == tv[1]).reshape(C, -1), axis=1)
+    bad = np.nonzero(s_err > 1e-4)[0]
+    for c in bad:
+        assert rej_g[c] != rej_o[c], (c, s_err[c], N[c])
+        lam = np.linalg.eigvalsh(So[c] if rej_g[c] else Sg[c])
+        assert lam.min() <= 1e-4 * lam.max(), (c, lam.min(), lam.max(), N[c])
+    good = np.setdiff1d(np.arange(C), bad)
+    print(f"Sigma: {len(bad)} components decided differently (numerically singular, N_c "
+          f"{np.round(N[bad], 2).tolist()[:10]}); the other {len(good)} relfro "
+          f"{relfro(Sg[good], So[good]):.2e}")
+    assert relfro(Sg[good], So[good]) <= 1e-4
+    assert abs(pg[0] - r["p"][0]) <= 1e-4 * r["p"][0]
+    assert relfro(mug[same], r["mu"][same]) <= 1e-4
