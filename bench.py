@@ -28,6 +28,9 @@ sys.path.insert(0, ROOT)
 METRIC = "TV EM utts/s + frame posteriors/s at C=2048,D=60,R=400 vs FP32 plain"
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+# BF16 MFMA products per FP32 product in the BF16 frame filter (operands split
+# into high and low BF16 parts: hi*hi + hi*lo + lo*hi)
+BF16_PRODUCTS = 3
 
 
 def parse():
@@ -39,13 +42,25 @@ def parse():
     ap.add_argument("--n-utts", type=int, default=None, help="first U utterances only")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-utts", type=int, default=6)
+    ap.add_argument("--cpu-frame-utts", type=int, default=40,
+                    help="oracle baseline: utterances for posteriors + n/f/S (all threads)")
+    ap.add_argument("--cpu-estep-utts", type=int, default=400,
+                    help="oracle baseline: utterances for E-step + accumulation (all threads)")
+    ap.add_argument("--cpu-components", type=int, default=256,
+                    help="oracle baseline: components of the per-component fixed work")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 form")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB device-to-device once "
                          "(reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--graph", action="store_true",
-                    help="also time the EM iteration replayed from a captured HIP graph")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the EM iteration replayed from a captured HIP graph")
+    ap.add_argument("--form-steps", type=int, default=5,
+                    help="timed steps of each secondary form (BF16, graph, standard, streamed, "
+                         "pruned, learned); at most --steps")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the batching workload (20,000 log-uniform utterances)")
+    ap.add_argument("--batching-steps", type=int, default=3,
+                    help="timed steps (eager and graph replay) of the batching workload")
     ap.add_argument("--learned-steps", type=int, default=3000,
                     help="training steps of the learned selector (0: skip the learned form)")
     ap.add_argument("--learned-batch", type=int, default=4096)
@@ -98,60 +113,103 @@ def measured_traffic(kernel, workload, frames):
         return None
 
 
-def cpu_baseline(wl, n_sample):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload.
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    Per-utterance work (posteriors over all C, n/f/S, E-step, accumulation)
-    is timed on the first ``n_sample`` utterances; the per-iteration fixed
-    work (V_c / U_c precompute, M-step solve, minimum divergence) is timed
-    once and spread over the workload's U utterances.  Returns utts/s of a
-    whole EM iteration at the workload's U.
-    """
+
+def _oracle_rates(wl, n_frame, n_estep, n_comp, pre=None):
+    """Times the FP64 oracle, as it stands, on bounded samples of the workload
+    with the BLAS threads currently allowed:
+      * posteriors over all C + n/f/S on the first ``n_frame`` utterances;
+      * E-step + accumulation on ``n_estep`` utterances whose statistics are
+        those of the frame sample repeated (the cost does not depend on the
+        values);
+      * the per-component fixed work (V/U precompute, M-step solve, T update
+        of minimum divergence) on the first ``n_comp`` components, scaled to C.
+    ``pre`` passes the full V/U precompute for the E-step when it is at hand
+    (else it is computed here, untimed beyond the component sample).
+    Returns the rates, the extrapolated utts/s of a whole iteration at the
+    workload's U, and the full precompute for reuse."""
     import numpy as np
     import oracle
-    from threadpoolctl import threadpool_info
-
-    a, b = 0, n_sample
-    off = wl.utt_off[: b + 1]
+    C = wl.shape.C
+    off = wl.utt_off[: n_frame + 1]
     F = int(off[-1])
     X = wl.X[:F]
-    tv = oracle.init_tv(wl.mu, wl.cov, wl.T_init)
+    T, Sigma, p = oracle.init_tv(wl.mu, wl.cov, wl.T_init)
     t0 = time.perf_counter()
     gamma, lse = oracle.posteriors(oracle.frame_loglik(X, wl.w, wl.mu, wl.cov))
     n, f, S = oracle.bw_stats(X, off, gamma)
     t_frame = time.perf_counter() - t0
+    cs = slice(0, n_comp)
     t0 = time.perf_counter()
-    V, Uc = oracle.tv_precompute(*tv[:2])
-    t_pre = time.perf_counter() - t0
-    del V, Uc
+    oracle.tv_precompute(T[cs], Sigma[cs])
+    t_pre = (time.perf_counter() - t0) * C / n_comp
+    if pre is None:
+        pre = oracle.tv_precompute(T, Sigma)
+    reps = -(-n_estep // n_frame)
+    ne = np.tile(n, (reps, 1))[:n_estep]
+    fe = np.tile(f, (reps, 1, 1))[:n_estep]
     t0 = time.perf_counter()
-    e = oracle.estep(n, f, *tv)
-    acc = oracle.accumulate(n, f, e["phi"], e["Phi"])
-    t_utt = time.perf_counter() - t0 - t_pre  # estep() repeats the precompute
+    e = oracle.estep(ne, fe, T, Sigma, p, pre=pre)
+    acc = oracle.accumulate(ne, fe, e["phi"], e["Phi"])
+    t_utt = time.perf_counter() - t0
+    sub = dict(N=acc["N"][cs], A=acc["A"][cs], Cc=acc["Cc"][cs])
     t0 = time.perf_counter()
-    T1, S1, _ = oracle.mstep(acc, S, tv[0], tv[1])
-    h, H = acc["hsum"] / acc["count"], acc["Hsum"] / acc["count"]
-    oracle.mindiv(h, H, T1)
-    t_fixed_m = time.perf_counter() - t0
+    T1, _, _ = oracle.mstep(sub, S[cs], T[cs], Sigma[cs])
+    oracle.mindiv(acc["hsum"] / acc["count"], acc["Hsum"] / acc["count"], T1)
+    t_fixed = t_pre + (time.perf_counter() - t0) * C / n_comp
     U = wl.U
-    per_utt = (t_frame + max(t_utt, 0.0)) / n_sample
-    fixed = t_pre + t_fixed_m
-    total = per_utt * U + fixed
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    total = U * (t_frame / n_frame + t_utt / n_estep) + t_fixed
+    return dict(value=U / total, frames_per_s=F / t_frame, estep_utts_per_s=n_estep / t_utt,
+                fixed_s=t_fixed, frames=F), pre
+
+
+def cpu_baseline(wl, n_frame, n_estep, n_comp, n_frame_1t, n_estep_1t):
+    """The FP64 oracle on the host cores, all BLAS threads and one thread.
+
+    ``value`` is utts/s of a whole EM iteration at the workload's U,
+    extrapolated from bounded samples (see _oracle_rates); ``one_thread``
+    holds the same figures with a single BLAS thread on smaller samples."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    ncpu = os.cpu_count() or 1
+    with threadpool_limits(1):
+        one, pre = _oracle_rates(wl, n_frame_1t, n_estep_1t, n_comp)
+    with threadpool_limits(ncpu):
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        allt, _ = _oracle_rates(wl, n_frame, n_estep, n_comp, pre=pre)
+    r = lambda x: round(float(x), 3)  # noqa: E731
     return {
-        "value": U / total,
+        "value": r(allt["value"]),
         "unit": "utts/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"first {n_sample} utterances ({F} frames) for posteriors, n/f/S, E-step and "
-                   f"accumulation; one V/U precompute, M-step solve and min-div; scaled to U={U} "
-                   f"(frame part {t_frame:.1f}s, E-step part {max(t_utt, 0):.1f}s, fixed "
-                   f"{fixed:.1f}s)"),
-        "frames_per_s": F / t_frame,
+        "sample": (f"FP64 oracle, {threads} BLAS threads: posteriors over all C and n/f/S on the "
+                   f"first {n_frame} utterances ({allt['frames']} frames), E-step + accumulation "
+                   f"on {n_estep} utterances (the sample's statistics repeated), precompute + "
+                   f"M-step solve + min-div T update on {n_comp} of {wl.shape.C} components "
+                   f"scaled to C; whole iteration extrapolated to U={wl.U}"),
+        "cpu_model": _cpu_model(),
+        "cpu_count": ncpu,
+        "frames_per_s": r(allt["frames_per_s"]),
+        "estep_utts_per_s": r(allt["estep_utts_per_s"]),
+        "fixed_s_per_iteration": r(allt["fixed_s"]),
+        "one_thread": {"value": r(one["value"]), "frames_per_s": r(one["frames_per_s"]),
+                       "estep_utts_per_s": r(one["estep_utts_per_s"]),
+                       "fixed_s_per_iteration": r(one["fixed_s"]),
+                       "sample": f"first {n_frame_1t} utterances ({one['frames']} frames), "
+                                 f"E-step on {n_estep_1t}, {n_comp} components"},
     }
 
 
-def learned_form(args, ctx, wl, X, step, timed, reset_model, phi, K, dev):
+def learned_form(args, ctx, wl, X, step, timed, reset_model, phi, K, W, dev):
     """Trains the learned selector on the GPU (exact all-component posteriors
     of the first tenth of the utterances as targets), then reports its
     accuracy on the other utterances and the throughput of the EM iteration
@@ -196,7 +254,7 @@ def learned_form(args, ctx, wl, X, step, timed, reset_model, phi, K, dev):
         miss[r0:r1] = 1.0 - (pv[Ftr + r0:Ftr + r1].double() * hit).sum(1)
     kept = ~fb
     # throughput of the whole EM iteration with the learned selection
-    el, ph, prof = timed(0, K, args.warmup, sel=ivx.IVX_SEL_LEARNED)
+    el, ph, prof = timed(0, K, W, sel=ivx.IVX_SEL_LEARNED)
     nfb, pairs = ctx.selector_counts()
     mlp_ms = prof["sel_mlp"][0] / K
     mlp_tflops = 2.0 * (D * H + H * H + H * C) * F / (mlp_ms / 1e3) / 1e12 if mlp_ms > 0 else None
@@ -211,7 +269,7 @@ def learned_form(args, ctx, wl, X, step, timed, reset_model, phi, K, dev):
     cos = (a * b).sum(1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1))
     m = miss[kept].cpu().numpy() if bool(kept.any()) else np.zeros(1)
     return {
-        "utts_per_s": round(U * K / el, 3), "ms_per_step": round(el * 1e3 / K, 3),
+        "utts_per_s": round(U * K / el, 3), "ms_per_step": round(el * 1e3 / K, 3), "steps": K,
         "frame_posteriors_per_s": round(F * K / (ph["frame"] / 1e3), 1),
         "train": {"steps": n_steps, "batch": B, "seconds": round(t_train, 2),
                   "final_loss": round(loss.item(), 4), "train_utterances": Utr},
@@ -226,6 +284,127 @@ def learned_form(args, ctx, wl, X, step, timed, reset_model, phi, K, dev):
                             "frac": None if mlp_tflops is None else round(mlp_tflops / 2500.0, 4)},
         "vs_plain_first_iteration": {"ivector_min_cosine": float(cos.min())},
     }
+
+
+class _Generator:
+    """Generates a seeded workload on a daemon host thread (numpy releases the
+    interpreter lock inside its array kernels); join() returns it."""
+
+    def __init__(self, shape_id, seed):
+        import threading
+        self.result, self.error, self.seconds = None, None, 0.0
+        self._t = threading.Thread(target=self._run, args=(shape_id, seed), daemon=True)
+        self._t.start()
+
+    def _run(self, shape_id, seed):
+        import synth
+        t0 = time.time()
+        try:
+            self.result = synth.make(shape_id, seed=seed)
+        except BaseException as e:  # noqa: BLE001  (re-raised in join)
+            self.error = e
+        self.seconds = time.time() - t0
+
+    def join(self):
+        self._t.join()
+        if self.error is not None:
+            raise self.error
+        return self.result
+
+
+def graph_replay(ctx, reset_model, X, off, n, f, S, phi, Phi, acc, ll_frames, ll_utts, obj, K, W,
+                 U):
+    """Times the whole EM iteration (posteriors, statistics, E-step,
+    accumulation, M-step, minimum divergence, realignment) replayed from one
+    captured HIP graph: W untimed replays, then K timed."""
+    import torch
+    reset_model()
+    t0 = time.perf_counter()
+    g = ctx.graph_create_em(X, off, n, f, S, phi, Phi, acc, ll_frames, ll_utts, obj)
+    t_cap = time.perf_counter() - t0
+    for _ in range(W):
+        g.launch()
+    ctx.sync_status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        g.launch()
+    torch.cuda.synchronize()
+    elg = time.perf_counter() - t0
+    ctx.sync_status()
+    g.close()
+    return {"utts_per_s": round(U * K / elg, 3), "ms_per_step": round(elg * 1e3 / K, 3),
+            "steps": K, "capture_and_instantiate_ms": round(t_cap * 1e3, 1)}
+
+
+def batching_block(args, wl, tuning, dev):
+    """The batching workload: 20,000 utterances with log-uniform 200-3000
+    frame lengths (~20.5M frames) at D 60, C 2048, R 400, FP32, realignment
+    every iteration; whole EM iterations issued eagerly and replayed from a
+    captured HIP graph, with the launch shapes tuned on the headline workload."""
+    import torch
+    from paper_1906_08556_amd import ivx
+    sh = wl.shape
+    C, D, R, U, F = sh.C, sh.D, sh.R, wl.U, wl.F
+    K, W = max(1, args.batching_steps), 1
+    ctx = ivx.Context(C, D, R, U, F)
+    if tuning:
+        ctx.tuning_set(**tuning)
+    X = torch.from_numpy(wl.X).to(dev)
+    off = torch.from_numpy(wl.utt_off).to(dev)
+    w_d, mu_d, cov_d = (torch.from_numpy(a).to(dev) for a in (wl.w, wl.mu, wl.cov))
+    T0 = torch.from_numpy(wl.T_init).to(dev)
+    f64 = torch.float64
+    n = torch.empty((U, C), dtype=torch.float32, device=dev)
+    f = torch.empty((U, C, D), dtype=torch.float32, device=dev)
+    S = torch.zeros((C, D * (D + 1) // 2), dtype=f64, device=dev)
+    phi = torch.empty((U, R), dtype=torch.float32, device=dev)
+    Phi = torch.empty((U, R * (R + 1) // 2), dtype=torch.float32, device=dev)
+    llf, llu, obj = (torch.zeros(1, dtype=f64, device=dev) for _ in range(3))
+    acc = ctx.new_accum()
+
+    def reset_model():
+        ctx.set_ubm(w_d, mu_d, cov_d)
+        ctx.init_tv(T0, 100.0)
+
+    def step():
+        S.zero_()
+        llf.zero_()
+        llu.zero_()
+        acc.zero_()
+        ctx.bw_stats(X, off, n, f, S_acc=S, ll_acc=llf)
+        ctx.tv_estep(n, f, phi, Phi=Phi, ll_acc=llu)
+        ctx.tv_mstep_accumulate(n, f, phi, Phi, acc)
+        ctx.tv_mstep_solve(acc, S, update_sigma=True, ll_sum=llu, objective=obj)
+        ctx.tv_mindiv(acc)
+        ctx.ubm_update_means()
+
+    reset_model()
+    for _ in range(W):
+        step()
+    ctx.sync_status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.sync_status()
+    obj_eager = obj.item()
+    graph = graph_replay(ctx, reset_model, X, off, n, f, S, phi, Phi, acc, llf, llu, obj, K, W, U)
+    lens = wl.utt_off[1:] - wl.utt_off[:-1]
+    out = {"workload": f"shape4:{sh.name}", "utterances": U, "frames": F,
+           "lengths": {"min": int(lens.min()), "mean": round(float(lens.mean()), 1),
+                       "max": int(lens.max()), "distribution": sh.lengths},
+           "eager": {"utts_per_s": round(U * K / el, 3), "ms_per_step": round(el * 1e3 / K, 3),
+                     "frame_posteriors_per_s_whole_step": round(F * K / el, 1), "steps": K},
+           "graph_replay": graph,
+           "graph_vs_eager": round(graph["utts_per_s"] / (U * K / el), 4),
+           "objective_after_eager_steps": obj_eager,
+           "step": "posteriors+n/f/S+E-step+accumulate+M-step(T,Sigma)+min-div+realign"}
+    del acc
+    ctx.close()
+    return out
 
 
 def backend_block(ctx, wl0, dev):
@@ -315,6 +494,12 @@ def main():
     sh = wl.shape
     log(f"[bench] workload shape {args.shape}: U={wl.U} F={wl.F} D={sh.D} C={sh.C} R={sh.R} "
         f"(generated in {time.time() - t0:.1f}s)")
+    # the batching workload (20,000 log-uniform utterances) is generated on a
+    # host thread while the GPU runs the forms below (kernel launches are
+    # asynchronous, so the thread does not enter the timed regions' GPU time)
+    gen4 = None
+    if not args.no_batching and args.shape != 4:
+        gen4 = _Generator(4, args.seed)
     C, D, R, U, F = sh.C, sh.D, sh.R, wl.U, wl.F
     dev = torch.device("cuda", 0)
     ctx = ivx.Context(C, D, R, U, F)
@@ -390,6 +575,7 @@ def main():
         tuning = ctx.autotune(X, off)
         log(f"[bench] autotuned launch shapes {tuning} in {time.time() - t0:.1f}s")
     K = args.steps
+    Ks, Ws = max(1, min(K, args.form_steps)), min(args.warmup, 2)
     elapsed, phase, prof = timed(0, K, args.warmup)
     if args.copy_calib_mib > 0:
         nbytes = args.copy_calib_mib << 20
@@ -427,15 +613,16 @@ def main():
 
     bf16 = None
     if not args.no_bf16:
-        el16, ph16, prof16 = timed(1, K, args.warmup)
+        el16, ph16, prof16 = timed(1, Ks, Ws)
         fs16_ms, fs16_calls = prof16["frame_select"]
         fs16_avg_s = fs16_ms / max(fs16_calls, 1) / 1e3
         bf16_peak = 2500.0
         tile16 = 256 if tune_now["frame_ncb_bf16"] == 8 else 128
-        # three BF16 products (hi*hi, hi*lo, lo*hi) per FP32 one
-        ach16 = 3.0 * 2.0 * Kexp * tile16 * F / fs16_avg_s / 1e12
+        # the method's FLOPs (2 K per frame and component) counted once; the
+        # MFMA instructions execute more (split operands), reported apart
+        ach16 = 2.0 * Kexp * tile16 * F / fs16_avg_s / 1e12
         log("[bench] BF16 kernel groups (ms per step): " + ", ".join(
-            f"{k}={v[0] / K:.2f}" for k, v in prof16.items() if v[1]))
+            f"{k}={v[0] / Ks:.2f}" for k, v in prof16.items() if v[1]))
         # one iteration of each form from the same initial model: BF16 vs FP32
         outs = {}
         for prec in (0, 1):
@@ -445,11 +632,15 @@ def main():
             outs[prec] = (phi.double().cpu().numpy(), obj.item())
         a, b = outs[1][0], outs[0][0]
         cos = (a * b).sum(1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1))
-        bf16 = {"utts_per_s": round(U * K / el16, 3), "ms_per_step": round(el16 * 1e3 / K, 3),
-                "frame_posteriors_per_s": round(F * K / (ph16["frame"] / 1e3), 1),
-                "tv_em_utts_per_s": round(U * K / (ph16["em"] / 1e3), 3),
+        bf16 = {"utts_per_s": round(U * Ks / el16, 3), "ms_per_step": round(el16 * 1e3 / Ks, 3),
+                "steps": Ks,
+                "frame_posteriors_per_s": round(F * Ks / (ph16["frame"] / 1e3), 1),
+                "tv_em_utts_per_s": round(U * Ks / (ph16["em"] / 1e3), 3),
                 "frame_kernel": {"kernel": "k_frame_tile_bf16", "achieved_bf16_tflops": round(ach16, 2),
                                  "peak": bf16_peak, "frac": round(ach16 / bf16_peak, 4),
+                                 "flops_counted": "method (2 K per frame and component, once)",
+                                 "mfma_products_per_method_product": BF16_PRODUCTS,
+                                 "hardware_mfma_tflops": round(BF16_PRODUCTS * ach16, 2),
                                  "avg_launch_ms": round(fs16_avg_s * 1e3, 3),
                                  "components_per_launch": tile16},
                 "vs_fp32_form_first_iteration": {
@@ -458,32 +649,22 @@ def main():
         log(f"[bench] BF16 form: {bf16}")
 
     graph = None
-    if args.graph:
-        reset_model()
-        g = ctx.graph_create_em(X, off, n, f, S, phi, Phi, acc, ll_frames, ll_utt, obj)
-        for _ in range(args.warmup):
-            g.launch()
-        ctx.sync_status()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(K):
-            g.launch()
-        torch.cuda.synchronize()
-        elg = time.perf_counter() - t0
-        ctx.sync_status()
-        g.close()
-        graph = {"utts_per_s": round(U * K / elg, 3), "ms_per_step": round(elg * 1e3 / K, 3)}
+    if not args.no_graph:
+        graph = graph_replay(ctx, reset_model, X, off, n, f, S, phi, Phi, acc, ll_frames, ll_utt,
+                             obj, Ks, Ws, U)
+        graph["eager_utts_per_s_same_run"] = round(value, 3)
         log(f"[bench] graph replay: {graph}")
 
     standard = None
     if not args.no_standard:
         # Sec. 2.1 model with centred statistics, Sigma update and the
         # P1-only minimum divergence; no realignment
-        els, phs, profs = timed(0, K, args.warmup, form="standard")
-        standard = {"utts_per_s": round(U * K / els, 3), "ms_per_step": round(els * 1e3 / K, 3),
-                    "tv_em_utts_per_s": round(U * K / (phs["em"] / 1e3), 3),
-                    "stats_S_ms_per_step": round(profs["stats_S"][0] / K, 3),
-                    "stats_nf_ms_per_step": round(profs["stats_nf"][0] / K, 3),
+        els, phs, profs = timed(0, Ks, Ws, form="standard")
+        standard = {"utts_per_s": round(U * Ks / els, 3), "ms_per_step": round(els * 1e3 / Ks, 3),
+                    "steps": Ks,
+                    "tv_em_utts_per_s": round(U * Ks / (phs["em"] / 1e3), 3),
+                    "stats_S_ms_per_step": round(profs["stats_S"][0] / Ks, 3),
+                    "stats_nf_ms_per_step": round(profs["stats_nf"][0] / Ks, 3),
                     "objective_after_last_step": obj.item(),
                     "step": "posteriors+centred n/f/S+E-step(p=0)+accumulate+M-step(T,Sigma)"
                             "+min-div(P1)"}
@@ -527,17 +708,18 @@ def main():
         T_res, T_str = ctx.get_tv()[0], ctx2.get_tv()[0]
         t_rel = ((T_str - T_res).norm() / T_res.norm()).item()
         reset2()
-        for _ in range(args.warmup):
+        for _ in range(Ws):
             sstep()
         ctx2.sync_status()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(K):
+        for _ in range(Ks):
             sstep()
         torch.cuda.synchronize()
         els = time.perf_counter() - t0
         ctx2.sync_status()
-        streamed = {"utts_per_s": round(U * K / els, 3), "ms_per_step": round(els * 1e3 / K, 3),
+        streamed = {"utts_per_s": round(U * Ks / els, 3), "ms_per_step": round(els * 1e3 / Ks, 3),
+                    "steps": Ks,
                     "batches_per_step": nb, "batch_limits": {"utterances": bu, "frames": bfr},
                     "loaders": args.stream_loaders, "host_bytes_per_step": int(wl.X.nbytes),
                     "vs_resident_first_iteration": {
@@ -556,7 +738,7 @@ def main():
     pruned = None
     if not args.no_pruned:
         ctx.pruned_set(20, 0.025)
-        elp, php, profp = timed(0, K, args.warmup, sel=ivx.IVX_SEL_PRUNED)
+        elp, php, profp = timed(0, Ks, Ws, sel=ivx.IVX_SEL_PRUNED)
         outs = []
         for sel in (ivx.IVX_SEL_ALL, ivx.IVX_SEL_PRUNED):
             reset_model()
@@ -565,25 +747,36 @@ def main():
             outs.append(phi.double().cpu().numpy())
         a, b = outs
         cos = (a * b).sum(1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1))
-        pruned = {"utts_per_s": round(U * K / elp, 3), "ms_per_step": round(elp * 1e3 / K, 3),
-                  "frame_posteriors_per_s": round(F * K / (php["frame"] / 1e3), 1),
-                  "diag_select_ms_per_step": round(profp["sel_mlp"][0] / K, 3),
-                  "scoring_ms_per_step": round(profp["sel_score"][0] / K, 3),
+        pruned = {"utts_per_s": round(U * Ks / elp, 3), "ms_per_step": round(elp * 1e3 / Ks, 3),
+                  "steps": Ks,
+                  "frame_posteriors_per_s": round(F * Ks / (php["frame"] / 1e3), 1),
+                  "diag_select_ms_per_step": round(profp["sel_mlp"][0] / Ks, 3),
+                  "scoring_ms_per_step": round(profp["sel_score"][0] / Ks, 3),
                   "vs_plain_first_iteration": {"ivector_min_cosine": float(cos.min())}}
         log(f"[bench] pruned alignment: {pruned}")
 
     learned = None
     if args.learned_steps > 0:
-        learned = learned_form(args, ctx, wl, X, step, timed, reset_model, phi, K, dev)
+        learned = learned_form(args, ctx, wl, X, step, timed, reset_model, phi, Ks, Ws, dev)
         log(f"[bench] learned selection: {learned}")
+
+    batching = None
+    if gen4 is not None:
+        wl4 = gen4.join()
+        log(f"[bench] batching workload: U={wl4.U} F={wl4.F} (generated in {gen4.seconds:.1f}s "
+            "beside the GPU work)")
+        batching = batching_block(args, wl4, tune_now, dev)
+        del wl4
+        log(f"[bench] batching workload: {batching}")
 
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample ...")
-        cpu = cpu_baseline(wl, min(args.cpu_sample_utts, U))
-        log(f"[bench] cpu baseline: {cpu['value']:.3f} utts/s, {cpu['frames_per_s']:.0f} frames/s "
-            f"({cpu['cores']} threads)")
-        cpu.pop("frames_per_s")
+        t0 = time.time()
+        nf = min(args.cpu_frame_utts, U)
+        cpu = cpu_baseline(wl, nf, args.cpu_estep_utts, min(args.cpu_components, C),
+                           max(1, nf // 8), max(1, args.cpu_estep_utts // 20))
+        log(f"[bench] cpu baseline ({time.time() - t0:.0f}s): {cpu}")
 
     out = {
         "metric": METRIC,
@@ -609,6 +802,7 @@ def main():
         "tuning": tuning,
         "bf16_form": bf16,
         "graph_replay": graph,
+        "batching_loguniform": batching,
         "standard_formulation": standard,
         "backend_synthetic_speakers": backend,
         "streamed_from_host": streamed,
