@@ -188,6 +188,30 @@ ivx_status ubm_posteriors(ivx_ctx* ctx, const float* X, int64_t F, ivx_precision
                           ivx_selection sel, float* gamma, int32_t* post_idx, float* post_val,
                           int32_t K, double* frame_ll, void* stream);
 
+/* ubm_posteriors with IVX_SEL_ALL for callers that cannot allocate device
+ * memory or hold a batch-sized workspace (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the frame-stage workspace
+ * (candidate lists, maxima, overflow flags, exact scores, the component-
+ * sorted slot list) lives in one fixed device array of the library, 64 MiB
+ * per device (ivx_static_bytes), resolved by ivx_create on each device it
+ * creates a context on.  The call allocates nothing; F is bounded by that
+ * array, not by the context's max_batch_frames: it needs about
+ * 392 + C/2048 bytes per frame (about 170,000 frames at C = 2048) and
+ * returns IVX_EINVAL, before any launch, for a larger F.
+ *   post_idx [F][K] int32 / post_val [F][K] FP32 (K = 16) are required;
+ *   frame_ll [F] FP64 or NULL; prec as in ubm_posteriors.
+ * Results equal ubm_posteriors(..., IVX_SEL_ALL, ...) on the same inputs.
+ * Every call on a device shares that device's array and overwrites all of
+ * it that it reads: calls that overlap on one device (two streams or host
+ * threads, whatever the context) race and must be serialised by the
+ * caller. */
+ivx_status ubm_posteriors_static(ivx_ctx* ctx, const float* X, int64_t F, ivx_precision prec,
+                                 int32_t* post_idx, float* post_val, int32_t K, double* frame_ll,
+                                 void* stream);
+
+/* Size in bytes of ubm_posteriors_static's per-device array. */
+int64_t ivx_static_bytes(void);
+
 /* Baum-Welch statistics of U utterances (Sec. 2), uncentred in the augmented
  * formulation; in the standard formulation every term is centred on the bias
  * first: f~_c(u) = sum_t gamma_tc (x_t - m_c), S~_c = sum_t gamma_tc

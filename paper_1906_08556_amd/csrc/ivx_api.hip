@@ -153,6 +153,7 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   IVX_CHECK(device >= 0 && device < ndev, "ivx_create: device %d not present (%d visible)", device,
             ndev);
   IVX_HIP(hipSetDevice(device));
+  IVX_HIP(static_scratch_init(device));
 
   ivx_ctx* c = new ivx_ctx();
   c->device = device;

@@ -295,6 +295,11 @@ void launch_hist_scan(int nb, int C, int* hist, int* coff, hipStream_t s);
 ivx_status launch_linear_term(ivx_ctx* ctx, const float* f, int64_t U, int ns, hipStream_t s);
 ivx_status ensure_tv_ready(ivx_ctx* ctx, hipStream_t s);
 
+// ---- ivx_static.hip
+// Resolves the device address of the static workspace of
+// ubm_posteriors_static on `device` (which must be current); idempotent.
+hipError_t static_scratch_init(int device);
+
 // ---- ivx_api_sel.hip
 void selector_free(ivx_ctx* ctx);
 void presel_free(ivx_ctx* ctx);

@@ -80,6 +80,8 @@ PROTOTYPES = {
     "ivx_set_tv": (_I32, [_P, _P, _P, _P, _P]),
     "ivx_get_tv": (_I32, [_P, _P, _P, _P, _P, _P]),
     "ubm_posteriors": (_I32, [_P, _P, _I64, _I32, _I32, _P, _P, _P, _I32, _P, _P]),
+    "ubm_posteriors_static": (_I32, [_P, _P, _I64, _I32, _P, _P, _I32, _P, _P]),
+    "ivx_static_bytes": (_I64, []),
     "bw_stats": (_I32, [_P, _P, _P, _I64, _I64, _I32, _I32, _P, _P, _P, _P, _P]),
     "tv_estep": (_I32, [_P, _P, _P, _I64, _I32, _P, _P, _P, _P, _P]),
     "tv_mstep_accumulate": (_I32, [_P, _P, _P, _P, _P, _I64, ctypes.POINTER(Accum), _P]),
@@ -254,6 +256,14 @@ class Context:
             self._p(gamma, torch.float32, "gamma"), self._p(post_idx, torch.int32, "post_idx"),
             self._p(post_val, torch.float32, "post_val"), KP,
             self._p(frame_ll, torch.float64, "frame_ll"), _stream(stream)))
+
+    def ubm_posteriors_static(self, X, post_idx, post_val, frame_ll=None, prec=IVX_FP32,
+                              stream=None):
+        F = X.shape[0]
+        self._check(self.lib.ubm_posteriors_static(
+            self.h, self._p(X, torch.float32, "X"), F, prec,
+            self._p(post_idx, torch.int32, "post_idx"), self._p(post_val, torch.float32, "post_val"),
+            KP, self._p(frame_ll, torch.float64, "frame_ll"), _stream(stream)))
 
     def bw_stats(self, X, utt_off, n, f, S_acc=None, ll_acc=None, prec=IVX_FP32,
                  sel=IVX_SEL_ALL, stream=None):
