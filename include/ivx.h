@@ -401,11 +401,10 @@ ivx_status ivx_selector_counts(ivx_ctx* ctx, int64_t* fallback_frames, int64_t* 
  *                   components) or 2 (128 components, two frame blocks per
  *                   wave)
  *   frame_ncb_bf16  the same for the BF16 split form
- *   nf_block        components per n/f statistics workgroup (128 or 256)
  *   b_split         K-splits of the linear-term GEMM b = p + F V (0: chosen
  *                   from the grid size; else 1..max) */
 typedef struct {
-  int32_t frame_ncb, frame_ncb_bf16, nf_block, b_split;
+  int32_t frame_ncb, frame_ncb_bf16, b_split;
 } ivx_tuning;
 
 /* Times the candidate launch shapes on the given workload (X, utt_off as in

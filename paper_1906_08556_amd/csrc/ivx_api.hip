@@ -128,7 +128,7 @@ void ivx_destroy(ivx_ctx* ctx) {
                   ctx->Y32, ctx->V32, ctx->Utp, ctx->Psig, ctx->sig_logdet, ctx->Lbuf, ctx->Wbuf, ctx->Psi64,
                   ctx->bpart, ctx->colpart, ctx->bvec, ctx->llu, ctx->n_ws, ctx->f_ws, ctx->Tnew, ctx->obj_part,
                   ctx->Gmat, ctx->Mmat, ctx->Winv, ctx->Ut16hi, ctx->Ut16lo, ctx->n16hi,
-                  ctx->n16lo, ctx->mvec, ctx->mstat, ctx->dev_err};
+                  ctx->n16lo, ctx->mvec, ctx->mstat, ctx->dev_err, ctx->nf_acc, ctx->umap};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete ctx;
@@ -155,8 +155,13 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   IVX_HIP(hipSetDevice(device));
   IVX_HIP(static_scratch_init(device));
 
+  int ncu = 0;
+  IVX_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
+  IVX_CHECK(ncu >= 1, "ivx_create: device %d reports %d compute units", device, ncu);
+
   ivx_ctx* c = new ivx_ctx();
   c->device = device;
+  c->ncu = ncu;
   c->C = dims->C;
   c->D = dims->D;
   c->R = dims->R;
@@ -215,6 +220,8 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
   A(dalloc(&c->bvec, U * R));
   A(dalloc(&c->llu, U));
   A(dalloc(&c->n_ws, U * C));
+  A(dalloc(&c->nf_acc, U * C * (D + 1)));
+  A(dalloc(&c->umap, F));
   A(dalloc(&c->f_ws, U * C * D));
   A(dalloc(&c->Tnew, C * D * R));
   A(dalloc(&c->obj_part, C));
@@ -238,7 +245,9 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
     return IVX_ENOMEM;
   }
   // the tile-packed U_c keeps zero padding (its GEMM never writes it)
-  if (hipMemset(c->Utp, 0, sizeof(float) * C * TP) != hipSuccess) {
+  // the fixed-point n/f sums start (and are kept) at zero
+  if (hipMemset(c->Utp, 0, sizeof(float) * C * TP) != hipSuccess ||
+      hipMemset(c->nf_acc, 0, sizeof(unsigned long long) * U * C * (D + 1)) != hipSuccess) {
     ivx_destroy(c);
     set_error("ivx_create: memset failed");
     return IVX_EDEVICE;
@@ -436,14 +445,18 @@ ivx_status bw_stats(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_
                     double* ll_acc, void* stream) {
   ivx_status st = check_frame_args(ctx, "bw_stats", X, F, prec, sel);
   if (st != IVX_OK) return st;
-  IVX_CHECK(U >= 1 && U <= (int64_t)1 << 30, "bw_stats: U=%lld must be >= 1", (long long)U);
+  IVX_CHECK(U >= 1 && U <= ctx->maxU, "bw_stats: U=%lld outside [1, max_batch_utts=%d]",
+            (long long)U, ctx->maxU);
   IVX_CHECK(utt_off && n && f, "bw_stats: null utt_off / n / f");
   if (set_device(ctx) != IVX_OK) return IVX_EDEVICE;
   hipStream_t s = as_stream(stream);
-  launch_posteriors(ctx, X, F, prec, sel, ctx->post_idx, ctx->post_val, ctx->frame_ll, s);
+  // n/f are accumulated beside the posteriors (in the rescoring pass of the
+  // all-component form) and converted once all frames are in
+  const NfTarget nf = launch_frame_utt(ctx, utt_off, U, F, s);
+  launch_posteriors(ctx, X, F, prec, sel, ctx->post_idx, ctx->post_val, ctx->frame_ll, s, &nf);
   {
     ProfScope ps(ctx, PK_STATS_NF, s);
-    launch_stats_nf(ctx, X, utt_off, U, F, n, f, s);
+    launch_nf_finish(ctx, U, n, f, s);
   }
   if (S_acc) {
     ProfScope ps(ctx, PK_STATS_S, s);

@@ -39,18 +39,21 @@ void presel_free(ivx_ctx* ctx) {
 // Posterior lists for frames [0, F): every component, the learned selection
 // with the all-component fallback, or the pruned alignment.
 void launch_posteriors(ivx_ctx* ctx, const float* X, int64_t F, int prec, int sel, int* post_idx,
-                       float* post_val, double* frame_ll, hipStream_t s) {
-  if (sel == IVX_SEL_PRUNED) {
-    launch_select_pruned(ctx, X, F, post_idx, post_val, frame_ll, s);
-    return;
-  }
-  if (sel == IVX_SEL_LEARNED) {
-    launch_select_learned(ctx, X, F, prec, post_idx, post_val, frame_ll, s);
+                       float* post_val, double* frame_ll, hipStream_t s, const NfTarget* nf) {
+  if (sel == IVX_SEL_PRUNED || sel == IVX_SEL_LEARNED) {
+    if (sel == IVX_SEL_PRUNED)
+      launch_select_pruned(ctx, X, F, post_idx, post_val, frame_ll, s);
+    else
+      launch_select_learned(ctx, X, F, prec, post_idx, post_val, frame_ll, s);
+    if (nf) {
+      ProfScope ps(ctx, PK_STATS_NF, s);
+      launch_nf_accum(ctx, X, F, post_idx, post_val, *nf, s);
+    }
     return;
   }
   launch_frame_select(ctx, X, F, prec, s);
   ProfScope ps(ctx, PK_RESCORE, s);
-  launch_rescore(ctx, X, F, prec, post_idx, post_val, frame_ll, s);
+  launch_rescore(ctx, X, F, prec, post_idx, post_val, frame_ll, s, nullptr, nullptr, nf);
 }
 
 }  // namespace ivx

@@ -216,10 +216,11 @@ ivx_status extract_ivectors(ivx_ctx* ctx, const float* X, const int64_t* utt_off
     return IVX_EDEVICE;
   }
   hipStream_t s = as_stream(stream);
-  launch_posteriors(ctx, X, F, prec, sel, ctx->post_idx, ctx->post_val, ctx->frame_ll, s);
+  const NfTarget nf = launch_frame_utt(ctx, utt_off, U, F, s);
+  launch_posteriors(ctx, X, F, prec, sel, ctx->post_idx, ctx->post_val, ctx->frame_ll, s, &nf);
   {
     ProfScope ps(ctx, PK_STATS_NF, s);
-    launch_stats_nf(ctx, X, utt_off, U, F, ctx->n_ws, ctx->f_ws, s);
+    launch_nf_finish(ctx, U, ctx->n_ws, ctx->f_ws, s);
   }
   ivx_status st = after_launch("extract_ivectors");
   if (st != IVX_OK) return st;

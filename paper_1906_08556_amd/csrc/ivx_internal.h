@@ -142,6 +142,7 @@ __device__ inline void raise_error(int* err, int code, int source, int index = -
 
 struct ivx_ctx {
   int device = 0;
+  int ncu = 0;     // compute units of the device (persistent grids)
   int C = 0, D = 0, R = 0;
   int maxU = 0;
   int64_t maxF = 0;
@@ -210,6 +211,8 @@ struct ivx_ctx {
   float* bvec = nullptr;      // [maxU][R]
   double* llu = nullptr;      // [maxU]
   float* n_ws = nullptr;      // [maxU][C]   (extract_ivectors)
+  unsigned long long* nf_acc = nullptr;  // [maxU][C][D+1] fixed-point n/f sums, kept at zero
+  int* umap = nullptr;        // [maxF] frame -> utterance of the current batch
   float* f_ws = nullptr;      // [maxU][C][D]
 
   // M-step / minimum-divergence workspace
@@ -231,7 +234,7 @@ struct ivx_ctx {
   int* dev_err = nullptr;     // [4]: see raise_error
 
   // launch shapes picked by the autotuner (ivx_autotune); defaults below
-  ivx_tuning tune = {8, 8, 256, 0};
+  ivx_tuning tune = {8, 8, 0};
 
   // learned Gaussian selection (ivx_selector_set), null until set
   ivx::Selector* sel = nullptr;
@@ -267,6 +270,17 @@ void launch_init_tv_standard(ivx_ctx* ctx, const double* T_rand, hipStream_t s);
 void launch_bias32(ivx_ctx* ctx, hipStream_t s);
 void launch_update_means(ivx_ctx* ctx, hipStream_t s);
 
+// Target of the zeroth- and first-order statistics accumulated beside the
+// posteriors: frame -> utterance map (k_frame_utt), utterance count, FP32
+// bias of the standard formulation (or null) and the fixed-point sums
+// [U][C][D+1] (k_nf.h).
+struct NfTarget {
+  const int* umap;
+  int64_t U;
+  const float* mb;
+  unsigned long long* acc;
+};
+
 // ---- k_frame.hip
 bool frame_set_attributes(const ivx_ctx* ctx);
 bool mstep_set_attributes();
@@ -274,15 +288,24 @@ bool mstep_set_attributes();
 // grid is sized for F).  fmap (optional): output row of compact frame i.
 void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, int prec, hipStream_t s,
                          const int* Fdev = nullptr);
+// nf (optional): n/f of every frame's kept posteriors are added to nf->acc.
 void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int prec, int* post_idx,
                     float* post_val, double* frame_ll, hipStream_t s, const int* Fdev = nullptr,
-                    const int* fmap = nullptr);
+                    const int* fmap = nullptr, const NfTarget* nf = nullptr);
 void launch_dense_gamma(ivx_ctx* ctx, int64_t F, const int* post_idx, const float* post_val,
                         float* gamma, hipStream_t s);
 
 // ---- k_stats.hip
-void launch_stats_nf(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_t U, int64_t F,
-                     float* n, float* f, hipStream_t s);
+// Frame -> utterance map of the batch in ctx->umap (offsets checked; bad
+// ones raise IVX_EINVAL); returns the n/f target of the batch.
+NfTarget launch_frame_utt(ivx_ctx* ctx, const int64_t* utt_off, int64_t U, int64_t F,
+                          hipStream_t s);
+// n/f sums of the posterior lists (paths whose posteriors are not produced
+// by launch_rescore)
+void launch_nf_accum(ivx_ctx* ctx, const float* X, int64_t F, const int* post_idx,
+                     const float* post_val, const NfTarget& nf, hipStream_t s);
+// n [U][C], f [U][C][D] from the sums, which are reset
+void launch_nf_finish(ivx_ctx* ctx, int64_t U, float* n, float* f, hipStream_t s);
 void launch_stats_S(ivx_ctx* ctx, const float* X, int64_t F, double* S_acc, hipStream_t s);
 void launch_sum_f64(ivx_ctx* ctx, const double* x, int64_t n, double* acc, hipStream_t s);
 // lscore[slot] = exact FP64 log w_c N(x_g; mu_c, Sigma_c) for the slots of
@@ -303,8 +326,10 @@ hipError_t static_scratch_init(int device);
 // ---- ivx_api_sel.hip
 void selector_free(ivx_ctx* ctx);
 void presel_free(ivx_ctx* ctx);
+// nf (optional): also accumulate n/f of the posteriors (launch_frame_utt)
 void launch_posteriors(ivx_ctx* ctx, const float* X, int64_t F, int prec, int sel, int* post_idx,
-                       float* post_val, double* frame_ll, hipStream_t s);
+                       float* post_val, double* frame_ll, hipStream_t s,
+                       const NfTarget* nf = nullptr);
 
 // ---- k_select.hip
 bool select_set_attributes();

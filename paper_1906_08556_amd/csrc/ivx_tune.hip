@@ -23,7 +23,7 @@ namespace {
 bool valid_tuning(const ivx_tuning& t) {
   auto ncb_ok = [](int v) { return v == 2 || v == 4 || v == 8; };
   return ncb_ok(t.frame_ncb) && ncb_ok(t.frame_ncb_bf16) &&
-         (t.nf_block == 128 || t.nf_block == 256) && t.b_split >= 0 && t.b_split <= 1024;
+         t.b_split >= 0 && t.b_split <= 1024;
 }
 
 struct Timer {
@@ -110,20 +110,13 @@ ivx_status ivx_autotune(ivx_ctx* ctx, const float* X, const int64_t* utt_off, in
     }
   }
   ctx->tune = best;
-  // posteriors for the statistics candidates
-  launch_frame_select(ctx, X, F, IVX_FP32, s);
-  launch_rescore(ctx, X, F, IVX_FP32, ctx->post_idx, ctx->post_val, ctx->frame_ll, s);
+  // statistics of the workload: the first-order ones are the linear term's input
   {
-    float tb = INFINITY;
-    for (int nfb : {256, 128}) {
-      ctx->tune.nf_block = nfb;
-      const float t = tm.best([&] { launch_stats_nf(ctx, X, utt_off, U, F, ctx->n_ws, ctx->f_ws, s); });
-      if (t < tb) {
-        tb = t;
-        best.nf_block = nfb;
-      }
-    }
-    ctx->tune = best;
+    const NfTarget nf = launch_frame_utt(ctx, utt_off, U, F, s);
+    launch_frame_select(ctx, X, F, IVX_FP32, s);
+    launch_rescore(ctx, X, F, IVX_FP32, ctx->post_idx, ctx->post_val, ctx->frame_ll, s, nullptr,
+                   nullptr, &nf);
+    launch_nf_finish(ctx, U, ctx->n_ws, ctx->f_ws, s);
   }
   ivx_status st = ensure_tv_ready(ctx, s);
   if (st == IVX_OK) {

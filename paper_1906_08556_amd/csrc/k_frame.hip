@@ -5,9 +5,12 @@
 // x~ = [1, x - s], with the component's coefficient row (see k_ubm.hip).  The
 // product runs on MFMA (v_mfma_f32_32x32x2_f32) with components on the M side
 // and frames on the N side, so each lane ends a component tile holding 128
-// log-likelihoods of one frame.  A running per-frame maximum and a short list
-// of components within the candidate margin of it are kept across component tiles:
-// the [F x C] log-likelihood matrix never leaves registers.
+// log-likelihoods of one frame.  One persistent launch: each workgroup takes
+// 128-frame tiles in turn and sweeps all C components over each, keeping the
+// frames' running maximum, candidate count and overflow flag in registers
+// and adding the components within the candidate margin to the frame's list
+// as they appear; the [F x C] log-likelihood matrix never leaves registers
+// and each frame is read once.
 //
 // Stage 2 (k_exact_sorted, k_rescore): every surviving candidate is rescored
 // exactly in FP64 (candidates bucketed by component first, so that each
@@ -15,10 +18,12 @@
 // l = const_c - 1/2 || L_c^{-1} (x - mu_c) ||^2, and the posteriors follow
 // from a log-sum-exp over the candidates.  Frames whose candidate list
 // overflowed are rescored over all C components and keep the KP best.
+#include <algorithm>
 #include <cmath>
 
 #include "ivx_internal.h"
 #include "k_exact.h"
+#include "k_nf.h"
 
 namespace ivx {
 namespace {
@@ -45,9 +50,10 @@ __device__ inline int compact_cands(int2* __restrict__ lst, float thr) {
   return w;
 }
 
-// Per-frame candidate state of one lane-half, carried between launches in
-// global memory: running maximum M, candidate list (CAPL slots of the
-// lane-half), overflow flag.
+// Candidate state of one lane-half of a frame, in registers for the whole
+// sweep over the components: running maximum M, number of filled list slots,
+// overflow flag.  The list itself (CAPL slots of the lane-half, filled from
+// slot 0) is in global memory, written only when a candidate is added.
 struct FrameState {
   int64_t g;
   bool valid;
@@ -57,25 +63,16 @@ struct FrameState {
   bool ov;
 };
 
-__device__ inline void frame_state_load(FrameState& st, int64_t g, int64_t F, int h, int first,
-                                        int2* __restrict__ cand, const float* __restrict__ cM,
-                                        const int* __restrict__ cflag) {
+__device__ inline void frame_state_init(FrameState& st, int64_t g, int64_t F, int h,
+                                        int2* __restrict__ cand) {
   st.g = g;
   st.valid = g < F;
   st.lst = cand + (st.valid ? g : 0) * KP + h * CAPL;
   st.M = -INFINITY;
   st.cnt = 0;
   st.ov = false;
-  if (st.valid) {
-    if (first) {
-      for (int s = 0; s < CAPL; ++s) st.lst[s] = make_int2(-1, 0);
-    } else {
-      st.M = cM[g];
-      st.ov = cflag[g] != 0;
-      for (int s = 0; s < CAPL; ++s)
-        if (st.lst[s].x >= 0) st.cnt = s + 1;
-    }
-  }
+  if (st.valid)
+    for (int s = 0; s < CAPL; ++s) st.lst[s] = make_int2(-1, 0);
 }
 
 // Epilogue of one 32-frame block: lane holds frame l32 and rows
@@ -84,7 +81,7 @@ __device__ inline void frame_state_load(FrameState& st, int64_t g, int64_t F, in
 // keep acc[] in registers: count this tile's hits, make room once, store.
 template <int NCB>
 __device__ inline void frame_epilogue(const floatx16 (&acc)[NCB], FrameState& st, int h, int c0,
-                                      int C, float margin, float* __restrict__ cM,
+                                      int C, float margin, bool last, float* __restrict__ cM,
                                       int* __restrict__ cflag) {
   float vmax = -INFINITY;
 #pragma unroll
@@ -118,6 +115,7 @@ __device__ inline void frame_epilogue(const floatx16 (&acc)[NCB], FrameState& st
         }
       }
   }
+  if (!last) return;
   const int ovi = st.ov ? 1 : 0;
   const int ovp = __shfl_xor(ovi, 32);
   if (st.valid && h == 0) {
@@ -138,47 +136,47 @@ __device__ inline void load_frames(float* xs, int nfr, int DS, const float* __re
   }
 }
 
-// One launch per tile of CT = 32 NCB components [c0, c0 + CT); each wave
-// handles FB blocks of 32 frames (FT FB frames per workgroup).  All
-// workgroups of a launch stream the same slice of W, so it stays resident in
-// every XCD's L2; chunks of 8 expanded features are staged through LDS
-// (double buffered) and shared by the 4 waves, and each staged coefficient
-// serves the FB frame blocks of a wave.  The per-frame running maximum,
-// candidate lists and overflow flag persist in global memory between launches.
+// Persistent: workgroup b takes frame tiles b, b + G, b + 2G, ... (G the
+// grid size, a few workgroups per CU), so the workgroups move through the
+// frames together.  For each tile it sweeps the component tiles of CT =
+// 32 NCB components in order; each wave handles FB blocks of 32 frames (FT FB
+// frames per workgroup).  The workgroups of the grid start together and
+// spend the same time per component tile, so at any moment they stream
+// nearby slices of W, which stay in every XCD's L2.  Chunks of 8 expanded
+// features are staged through LDS (double buffered) and shared by the 4
+// waves, and each staged coefficient serves the FB frame blocks of a wave.
 //
 // W layout (k_ubm_prepare): chunk-major, coefficient (c, k) at
-// ((k / 8) * Cpad + c) * 8 + k % 8, so a chunk of a tile is contiguous.
+// ((k / 8) * Cpad + c) * 8 + k % 8, so a chunk of a component tile is contiguous.
 template <int NCB, int FB>
 __global__ void __launch_bounds__(256, FB == 1 ? 2 : 1)
 k_frame_tile(const float* __restrict__ X, int64_t F, int D, const float* __restrict__ shift,
              const float* __restrict__ W, int C, int Cpad, int Kpad,
-             const uint16_t* __restrict__ pairs, float margin, int c0, int first,
-             int2* __restrict__ cand, float* __restrict__ cM, int* __restrict__ cflag,
-             const int* __restrict__ Fdev) {
-  constexpr int CT = 32 * NCB;   // components per launch
+             const uint16_t* __restrict__ pairs, float margin, int2* __restrict__ cand,
+             float* __restrict__ cM, int* __restrict__ cflag, const int* __restrict__ Fdev) {
+  constexpr int CT = 32 * NCB;   // components per component tile
   constexpr int TPC = 256 / CT;  // threads per staged component
   constexpr int NV = 2 / TPC;    // float4 per thread and chunk
-  constexpr int FTB = FT * FB;   // frames per workgroup
+  constexpr int FTB = FT * FB;   // frames per workgroup tile
   extern __shared__ float smem[];
   if (Fdev && (int64_t)Fdev[0] < F) F = Fdev[0];
-  if ((int64_t)blockIdx.x * FTB >= F) return;  // whole workgroup, before any barrier
+  const int64_t ntile = (F + FTB - 1) / FTB;
+  if ((int64_t)blockIdx.x >= ntile) return;  // whole workgroup, before any barrier
   const int DS = D + 1;
   float* Ws = smem;                                              // [2][CT][WLD]
   float* xs = smem + 2 * CT * WLD;                               // [FTB][DS]
   uint32_t* prs = reinterpret_cast<uint32_t*>(xs + FTB * DS);    // [Kpad/2] index pairs
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t f0 = (int64_t)blockIdx.x * FTB;
+  const int h = lane >> 5, l32 = lane & 31;
   const int nq = Kpad / 8;
-
   for (int i = tid; i < Kpad / 2; i += 256) prs[i] = reinterpret_cast<const uint32_t*>(pairs)[i];
-  load_frames(xs, FTB, DS, X, f0, F, D, shift);
   // W chunk loader: TPC threads stage the 8 coefficients of one component
   // (named registers, not an array: an array captured by the lambdas ends
   // up in scratch memory)
   const int lc = tid / TPC, part = tid % TPC;
   float4 r0, r1;
-  auto gload = [&](int q) {
+  auto gload = [&](int q, int c0) {
     const float4* p =
         reinterpret_cast<const float4*>(W + ((size_t)q * Cpad + c0 + lc) * 8 + part * 4 * NV);
     r0 = p[0];
@@ -189,50 +187,57 @@ k_frame_tile(const float* __restrict__ X, int64_t F, int D, const float* __restr
     *reinterpret_cast<float4*>(d) = r0;
     if constexpr (NV == 2) *reinterpret_cast<float4*>(d + 4) = r1;
   };
-  gload(0);
-  sstore(0);
-
-  const int h = lane >> 5, l32 = lane & 31;
-  FrameState st[FB];
-#pragma unroll
-  for (int fb = 0; fb < FB; ++fb)
-    frame_state_load(st[fb], f0 + (wave * FB + fb) * FR + l32, F, h, first, cand, cM, cflag);
-  __syncthreads();
-
-  floatx16 acc[FB][NCB];
-#pragma unroll
-  for (int fb = 0; fb < FB; ++fb)
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[fb][cb] = floatx16{0};
   const float* xw = xs + (wave * FB * FR + l32) * DS;
-  for (int q = 0; q < nq; ++q) {
-    const int cur = q & 1;
-    if (q + 1 < nq) gload(q + 1);
-    const float* wb = Ws + (cur * CT + l32) * WLD + 4 * h;
-    float4 wv[NCB];
+
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t f0 = tile * FTB;
+    __syncthreads();  // the previous tile's readers of xs and Ws are done
+    load_frames(xs, FTB, DS, X, f0, F, D, shift);
+    FrameState st[FB];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) wv[cb] = *reinterpret_cast<const float4*>(wb + cb * 32 * WLD);
-    const uint32_t pw0 = prs[4 * q + 2 * h], pw1 = prs[4 * q + 2 * h + 1];
+    for (int fb = 0; fb < FB; ++fb)
+      frame_state_init(st[fb], f0 + (wave * FB + fb) * FR + l32, F, h, cand);
+    for (int c0 = 0; c0 < Cpad; c0 += CT) {
+      gload(0, c0);
+      sstore(0);
+      __syncthreads();
+      floatx16 acc[FB][NCB];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const uint32_t pr = ((s < 2) ? pw0 : pw1) >> ((s & 1) * 16);
-      const int a = pr & 0xff, b = (pr >> 8) & 0xff;
+      for (int fb = 0; fb < FB; ++fb)
 #pragma unroll
-      for (int fb = 0; fb < FB; ++fb) {
-        const float* xf = xw + fb * FR * DS;
-        const float bv = xf[a] * xf[b];
+        for (int cb = 0; cb < NCB; ++cb) acc[fb][cb] = floatx16{0};
+      for (int q = 0; q < nq; ++q) {
+        const int cur = q & 1;
+        if (q + 1 < nq) gload(q + 1, c0);
+        const float* wb = Ws + (cur * CT + l32) * WLD + 4 * h;
+        float4 wv[NCB];
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          const float av = (s == 0) ? wv[cb].x : (s == 1) ? wv[cb].y : (s == 2) ? wv[cb].z : wv[cb].w;
-          acc[fb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[fb][cb], 0, 0, 0);
+        for (int cb = 0; cb < NCB; ++cb) wv[cb] = *reinterpret_cast<const float4*>(wb + cb * 32 * WLD);
+        const uint32_t pw0 = prs[4 * q + 2 * h], pw1 = prs[4 * q + 2 * h + 1];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const uint32_t pr = ((s < 2) ? pw0 : pw1) >> ((s & 1) * 16);
+          const int a = pr & 0xff, b = (pr >> 8) & 0xff;
+#pragma unroll
+          for (int fb = 0; fb < FB; ++fb) {
+            const float* xf = xw + fb * FR * DS;
+            const float bv = xf[a] * xf[b];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+              const float av = (s == 0) ? wv[cb].x : (s == 1) ? wv[cb].y : (s == 2) ? wv[cb].z : wv[cb].w;
+              acc[fb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[fb][cb], 0, 0, 0);
+            }
+          }
         }
+        if (q + 1 < nq) sstore(cur ^ 1);
+        __syncthreads();
       }
-    }
-    if (q + 1 < nq) sstore(cur ^ 1);
-    __syncthreads();
-  }
+      const bool last = c0 + CT >= Cpad;
 #pragma unroll
-  for (int fb = 0; fb < FB; ++fb) frame_epilogue<NCB>(acc[fb], st[fb], h, c0, C, margin, cM, cflag);
+      for (int fb = 0; fb < FB; ++fb)
+        frame_epilogue<NCB>(acc[fb], st[fb], h, c0, C, margin, last, cM, cflag);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- BF16 form
@@ -247,36 +252,35 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int WB16 = 40;  // LDS row stride (bf16) of a staged comp: 16 hi, 16 lo, 8 pad
 
 // W16 layout (k_ubm_prepare): [Kpad/16][Cpad][32] bf16, per component 16 hi
-// then 16 lo coefficients of the chunk.
+// then 16 lo coefficients of the chunk.  Persistent over frame tiles and
+// component tiles as k_frame_tile.
 template <int NCB, int FB>
 __global__ void __launch_bounds__(256, FB == 1 ? 2 : 1)
 k_frame_tile_bf16(const float* __restrict__ X, int64_t F, int D, const float* __restrict__ shift,
                   const __bf16* __restrict__ W16, int C, int Cpad, int Kpad,
-                  const uint16_t* __restrict__ pairs, float margin, int c0, int first,
-                  int2* __restrict__ cand, float* __restrict__ cM, int* __restrict__ cflag,
-                  const int* __restrict__ Fdev) {
-  constexpr int CT = 32 * NCB;   // components per launch
+                  const uint16_t* __restrict__ pairs, float margin, int2* __restrict__ cand,
+                  float* __restrict__ cM, int* __restrict__ cflag, const int* __restrict__ Fdev) {
+  constexpr int CT = 32 * NCB;   // components per component tile
   constexpr int TPC = 256 / CT;  // threads per staged component
   constexpr int NV = 4 / TPC;    // uint4 (8 bf16) per thread and chunk
-  constexpr int FTB = FT * FB;   // frames per workgroup
+  constexpr int FTB = FT * FB;   // frames per workgroup tile
   extern __shared__ float smem[];
   if (Fdev && (int64_t)Fdev[0] < F) F = Fdev[0];
-  if ((int64_t)blockIdx.x * FTB >= F) return;  // whole workgroup, before any barrier
+  const int64_t ntile = (F + FTB - 1) / FTB;
+  if ((int64_t)blockIdx.x >= ntile) return;  // whole workgroup, before any barrier
   const int DS = D + 1;
   __bf16* Ws = reinterpret_cast<__bf16*>(smem);                  // [2][CT][WB16]
   float* xs = smem + (2 * CT * WB16) / 2;                         // [FTB][DS]
   uint32_t* prs = reinterpret_cast<uint32_t*>(xs + FTB * DS);     // [Kpad/2]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t f0 = (int64_t)blockIdx.x * FTB;
+  const int h = lane >> 5, l32 = lane & 31;
   const int nq = Kpad / 16;
-
   for (int i = tid; i < Kpad / 2; i += 256) prs[i] = reinterpret_cast<const uint32_t*>(pairs)[i];
-  load_frames(xs, FTB, DS, X, f0, F, D, shift);
   // chunk loader: TPC threads stage the 32 bf16 (64 B) of one component
   const int lc = tid / TPC, part = tid % TPC;
   uint4 r0, r1, r2, r3;  // named registers (see k_frame_tile)
-  auto gload = [&](int q) {
+  auto gload = [&](int q, int c0) {
     const uint4* p =
         reinterpret_cast<const uint4*>(W16 + ((size_t)q * Cpad + c0 + lc) * 32 + part * 8 * NV);
     r0 = p[0];
@@ -295,65 +299,72 @@ k_frame_tile_bf16(const float* __restrict__ X, int64_t F, int D, const float* __
       d[3] = r3;
     }
   };
-  gload(0);
-  sstore(0);
-
-  const int h = lane >> 5, l32 = lane & 31;
-  FrameState st[FB];
-#pragma unroll
-  for (int fb = 0; fb < FB; ++fb)
-    frame_state_load(st[fb], f0 + (wave * FB + fb) * FR + l32, F, h, first, cand, cM, cflag);
-  __syncthreads();
-
-  floatx16 acc[FB][NCB];
-#pragma unroll
-  for (int fb = 0; fb < FB; ++fb)
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[fb][cb] = floatx16{0};
   const float* xw = xs + (wave * FB * FR + l32) * DS;
-  for (int q = 0; q < nq; ++q) {
-    const int cur = q & 1;
-    if (q + 1 < nq) gload(q + 1);
-    // B operand: products for k = 16 q + 8 h + e, e = 0..7, split hi / lo
-    const uint4 pw = *reinterpret_cast<const uint4*>(prs + 8 * q + 4 * h);
-    bf16x8 bh[FB], bl[FB];
+
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t f0 = tile * FTB;
+    __syncthreads();  // the previous tile's readers of xs and Ws are done
+    load_frames(xs, FTB, DS, X, f0, F, D, shift);
+    FrameState st[FB];
 #pragma unroll
-    for (int fb = 0; fb < FB; ++fb) {
-      const float* xf = xw + fb * FR * DS;
+    for (int fb = 0; fb < FB; ++fb)
+      frame_state_init(st[fb], f0 + (wave * FB + fb) * FR + l32, F, h, cand);
+    for (int c0 = 0; c0 < Cpad; c0 += CT) {
+      gload(0, c0);
+      sstore(0);
+      __syncthreads();
+      floatx16 acc[FB][NCB];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint32_t w32 = (e < 2) ? pw.x : (e < 4) ? pw.y : (e < 6) ? pw.z : pw.w;
-        const uint32_t pr = w32 >> ((e & 1) * 16);
-        const float v = xf[pr & 0xff] * xf[(pr >> 8) & 0xff];
-        const __bf16 hi = (__bf16)v;
-        bh[fb][e] = hi;
-        bl[fb][e] = (__bf16)(v - (float)hi);
+      for (int fb = 0; fb < FB; ++fb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[fb][cb] = floatx16{0};
+      for (int q = 0; q < nq; ++q) {
+        const int cur = q & 1;
+        if (q + 1 < nq) gload(q + 1, c0);
+        // B operand: products for k = 16 q + 8 h + e, e = 0..7, split hi / lo
+        const uint4 pw = *reinterpret_cast<const uint4*>(prs + 8 * q + 4 * h);
+        bf16x8 bh[FB], bl[FB];
+#pragma unroll
+        for (int fb = 0; fb < FB; ++fb) {
+          const float* xf = xw + fb * FR * DS;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const uint32_t w32 = (e < 2) ? pw.x : (e < 4) ? pw.y : (e < 6) ? pw.z : pw.w;
+            const uint32_t pr = w32 >> ((e & 1) * 16);
+            const float v = xf[pr & 0xff] * xf[(pr >> 8) & 0xff];
+            const __bf16 hi = (__bf16)v;
+            bh[fb][e] = hi;
+            bl[fb][e] = (__bf16)(v - (float)hi);
+          }
+        }
+        const __bf16* wb = Ws + (cur * CT + l32) * WB16 + 8 * h;
+        bf16x8 wh[NCB], wl[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          wh[cb] = *reinterpret_cast<const bf16x8*>(wb + cb * 32 * WB16);
+          wl[cb] = *reinterpret_cast<const bf16x8*>(wb + cb * 32 * WB16 + 16);
+        }
+#pragma unroll
+        for (int fb = 0; fb < FB; ++fb) {
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            acc[fb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[cb], bh[fb], acc[fb][cb], 0, 0, 0);
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            acc[fb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[cb], bl[fb], acc[fb][cb], 0, 0, 0);
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            acc[fb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl[cb], bh[fb], acc[fb][cb], 0, 0, 0);
+        }
+        if (q + 1 < nq) sstore(cur ^ 1);
+        __syncthreads();
       }
+      const bool last = c0 + CT >= Cpad;
+#pragma unroll
+      for (int fb = 0; fb < FB; ++fb)
+        frame_epilogue<NCB>(acc[fb], st[fb], h, c0, C, margin, last, cM, cflag);
     }
-    const __bf16* wb = Ws + (cur * CT + l32) * WB16 + 8 * h;
-    bf16x8 wh[NCB], wl[NCB];
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      wh[cb] = *reinterpret_cast<const bf16x8*>(wb + cb * 32 * WB16);
-      wl[cb] = *reinterpret_cast<const bf16x8*>(wb + cb * 32 * WB16 + 16);
-    }
-#pragma unroll
-    for (int fb = 0; fb < FB; ++fb) {
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
-        acc[fb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[cb], bh[fb], acc[fb][cb], 0, 0, 0);
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
-        acc[fb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[cb], bl[fb], acc[fb][cb], 0, 0, 0);
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
-        acc[fb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl[cb], bh[fb], acc[fb][cb], 0, 0, 0);
-    }
-    if (q + 1 < nq) sstore(cur ^ 1);
-    __syncthreads();
   }
-#pragma unroll
-  for (int fb = 0; fb < FB; ++fb) frame_epilogue<NCB>(acc[fb], st[fb], h, c0, C, margin, cM, cflag);
 }
 
 // ---- exact FP64 scores of the kept candidates, sorted by component --------
@@ -465,7 +476,9 @@ k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __
           const int2* __restrict__ cand, const float* __restrict__ cM, float margin,
           const int* __restrict__ cflag, const double* __restrict__ lscore,
           int* __restrict__ post_idx, float* __restrict__ post_val, double* __restrict__ frame_ll,
-          int* __restrict__ err, const int* __restrict__ Fdev, const int* __restrict__ fmap) {
+          int* __restrict__ err, const int* __restrict__ Fdev, const int* __restrict__ fmap,
+          const int* __restrict__ umap, int64_t U, const float* __restrict__ mb,
+          unsigned long long* __restrict__ nf_acc) {
   __shared__ double dsh[4][64];
   __shared__ double lsh[4][KP];
   __shared__ int ish[4][KP];
@@ -543,9 +556,9 @@ k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __
   if (!isfinite(lse) && lane == 0) raise_error(err, IVX_ENUMERIC, PK_RESCORE, (int)go);
   if (!isnan(full_lse) && lane == 0 && 1.0 - exp(kept - full_lse) > kMaxDroppedMass)
     raise_error(err, IVX_ECAPACITY, PK_RESCORE, (int)go);
+  int id = -1;
+  float v = 0.0f;
   if (lane < KP) {
-    int id = -1;
-    float v = 0.0f;
     if (lane < m) {
       id = ish[wave][lane];
       v = (float)exp(lsh[wave][lane] - lse);
@@ -554,6 +567,16 @@ k_rescore(const float* __restrict__ X, int64_t F, int D, int C, const double* __
     if (post_val) post_val[go * KP + lane] = v;
   }
   if (lane == 0 && frame_ll) frame_ll[go] = lse;
+  // n/f of the frame's utterance from the FP32 posteriors just written (the
+  // same values the list-based accumulation reads)
+  if (nf_acc) {
+    const int u = umap[go];
+    if (u < 0 || u >= U) return;  // offsets rejected by k_frame_utt
+    const float xv = (lane >= 1 && lane <= D) ? X[g * D + (lane - 1)] : 0.0f;
+    for (int sl = 0; sl < m; ++sl)
+      nf_add_entry(nf_acc, (int64_t)u * C, D, lane, xv, mb, __shfl(id, sl),
+                   (double)__shfl(v, sl), err);
+  }
 }
 
 __global__ void k_dense_gamma(int64_t F, int C, const int* __restrict__ post_idx,
@@ -586,26 +609,22 @@ size_t frame_lds_f32(int D, int Kpad) {
 template <int NCB, int FB>
 void frame_launches(ivx_ctx* ctx, const float* X, int64_t F, int prec, hipStream_t s,
                     const int* Fdev) {
-  constexpr int CT = 32 * NCB;
-  const unsigned nblk = (unsigned)((F + FT * FB - 1) / (FT * FB));
+  // persistent grid: as many workgroups as fit on the device at once
+  const int64_t ntile = (F + FT * FB - 1) / (FT * FB);
+  const unsigned nblk =
+      (unsigned)std::min<int64_t>(ntile, (int64_t)ctx->ncu * (FB == 1 ? 2 : 1));
+  ProfScope ps(ctx, PK_FRAME_SELECT, s);
   if (prec == IVX_BF16) {
     const size_t lds = frame_lds_bf16<NCB, FB>(ctx->D, ctx->Kpad);
-    for (int c0 = 0; c0 < ctx->Cpad; c0 += CT) {
-      ProfScope ps(ctx, PK_FRAME_SELECT, s);
-      k_frame_tile_bf16<NCB, FB><<<nblk, 256, lds, s>>>(
-          X, F, ctx->D, ctx->shift, ctx->W16, ctx->C, ctx->Cpad, ctx->Kpad, ctx->pairs,
-          ctx->margin_bf16, c0, c0 == 0 ? 1 : 0, ctx->cand, ctx->cM, ctx->cflag, Fdev);
-    }
+    k_frame_tile_bf16<NCB, FB><<<nblk, 256, lds, s>>>(
+        X, F, ctx->D, ctx->shift, ctx->W16, ctx->C, ctx->Cpad, ctx->Kpad, ctx->pairs,
+        ctx->margin_bf16, ctx->cand, ctx->cM, ctx->cflag, Fdev);
     return;
   }
   const size_t lds = frame_lds_f32<NCB, FB>(ctx->D, ctx->Kpad);
-  for (int c0 = 0; c0 < ctx->Cpad; c0 += CT) {
-    ProfScope ps(ctx, PK_FRAME_SELECT, s);
-    k_frame_tile<NCB, FB><<<nblk, 256, lds, s>>>(X, F, ctx->D, ctx->shift, ctx->Wexp, ctx->C,
-                                                 ctx->Cpad, ctx->Kpad, ctx->pairs, ctx->margin,
-                                                 c0, c0 == 0 ? 1 : 0, ctx->cand, ctx->cM,
-                                                 ctx->cflag, Fdev);
-  }
+  k_frame_tile<NCB, FB><<<nblk, 256, lds, s>>>(X, F, ctx->D, ctx->shift, ctx->Wexp, ctx->C,
+                                               ctx->Cpad, ctx->Kpad, ctx->pairs, ctx->margin,
+                                               ctx->cand, ctx->cM, ctx->cflag, Fdev);
 }
 
 }  // namespace
@@ -644,7 +663,7 @@ void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, int prec, hipS
 
 void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int prec, int* post_idx,
                     float* post_val, double* frame_ll, hipStream_t s, const int* Fdev,
-                    const int* fmap) {
+                    const int* fmap, const NfTarget* nf) {
   if (F <= 0) return;
   const float margin = prec == IVX_BF16 ? ctx->margin_bf16 : ctx->margin;
   // exact scores of the kept candidates, by component
@@ -659,7 +678,9 @@ void launch_rescore(ivx_ctx* ctx, const float* X, int64_t F, int prec, int* post
   const unsigned nblk = (unsigned)((F + 3) / 4);
   k_rescore<<<nblk, 256, 0, s>>>(X, F, ctx->D, ctx->C, ctx->mu, ctx->linv, ctx->cst, ctx->cand,
                                  ctx->cM, margin, ctx->cflag, ctx->lscore, post_idx, post_val,
-                                 frame_ll, ctx->dev_err, Fdev, fmap);
+                                 frame_ll, ctx->dev_err, Fdev, fmap,
+                                 nf ? nf->umap : nullptr, nf ? nf->U : 0,
+                                 nf ? nf->mb : nullptr, nf ? nf->acc : nullptr);
 }
 
 void launch_exact_sorted(ivx_ctx* ctx, const int2* ent, const int* coff, int kpf, const float* X,

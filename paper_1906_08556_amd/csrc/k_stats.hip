@@ -1,8 +1,11 @@
 // Baum-Welch statistics (Sec. 2) from the sparse per-frame posterior lists.
 //
-//  n_c(u), f_c(u): one workgroup per (utterance, block of 256 components)
-//    accumulates [n | f] rows in LDS with LDS float atomics and writes the
-//    block's rows once (zeros included), coalesced.
+//  n_c(u), f_c(u): a map from frame to utterance (k_frame_utt, which also
+//    checks the offsets), then every kept posterior entry is added to its
+//    (utterance, component) row of 64-bit fixed-point sums (k_nf.h; from the
+//    posterior lists in k_nf_accum, or inside the rescoring pass of the
+//    all-component posteriors), and k_nf_finish converts the sums to FP32
+//    n and f (zeros included) and resets them.
 //  S_c = sum_t gamma_tc x_t x_t^T (FP64 totals): the (frame, component)
 //    posterior entries are bucketed by component with a counting sort
 //    (per-block histograms, a scan, a scatter); one workgroup per component
@@ -11,59 +14,76 @@
 //    before it is accumulated, f~_c(u) = sum_t gamma_tc (x_t - m_c) and
 //    S~_c = sum_t gamma_tc (x_t - m_c)(x_t - m_c)^T (the frames staged as
 //    FP64 x - m_c), so no large uncentred sums are formed and cancelled.
+#include <algorithm>
+
 #include "ivx_internal.h"
+#include "k_nf.h"
 
 namespace ivx {
 namespace {
 
-// NFB (template): components per n/f workgroup, 128 or 256 (autotuner)
 constexpr int HB = 8192;       // frames per histogram block
 
-template <int NFB>
+// One workgroup per utterance: checks its offsets (0 = utt_off[0] <= ... <=
+// utt_off[U] = F) and writes the utterance index of each of its frames.
 __global__ void __launch_bounds__(256)
-k_stats_nf(const float* __restrict__ X, const int64_t* __restrict__ utt_off, int64_t U, int64_t F,
-           int D, int C, const int* __restrict__ post_idx, const float* __restrict__ post_val,
-           const float* __restrict__ mb, float* __restrict__ n, float* __restrict__ f,
-           int* __restrict__ err) {
-  extern __shared__ float acc[];  // [NFB][D+1]: n at column 0, f at 1..D
-  const int DS = D + 1;
+k_frame_utt(const int64_t* __restrict__ utt_off, int64_t U, int64_t F, int* __restrict__ umap,
+            int* __restrict__ err) {
   const int64_t u = blockIdx.x;
-  const int c0 = blockIdx.y * NFB;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int64_t t0 = utt_off[u], t1 = utt_off[u + 1];
+  const int64_t t0 = utt_off[u], t1 = utt_off[u + 1];
   const bool bad = (t0 > t1) || (t0 < 0) || (t1 > F) || (u == 0 && t0 != 0) ||
                    (u == U - 1 && t1 != F);
   if (bad) {
-    if (tid == 0 && blockIdx.y == 0) raise_error(err, IVX_EINVAL, PK_STATS_NF, (int)u);
-    t0 = t1 = 0;
+    if (threadIdx.x == 0) raise_error(err, IVX_EINVAL, PK_STATS_NF, (int)u);
+    return;
   }
-  for (int i = tid; i < NFB * DS; i += 256) acc[i] = 0.0f;
-  __syncthreads();
-  for (int64_t t = t0 + wave; t < t1; t += 4) {
-    const int id = (lane < KP) ? post_idx[t * KP + lane] : -1;
-    const float gv = (lane < KP) ? post_val[t * KP + lane] : 0.0f;
-    const bool mine = id >= c0 && id < c0 + NFB;
-    uint64_t mask = __ballot(mine);
-    if (mask == 0) continue;
-    const float xv = (lane == 0) ? 1.0f : ((lane <= D) ? X[t * D + (lane - 1)] : 0.0f);
-    while (mask) {
-      const int s = __ffsll((unsigned long long)mask) - 1;
-      mask &= mask - 1;
-      const int c = __shfl(id, s);
-      const float gm = __shfl(gv, s);
-      // centred term x - m_c (FP32 copy of the bias; lane 0 carries the count)
-      const float xc = (mb && lane >= 1 && lane <= D) ? xv - mb[(size_t)c * D + lane - 1] : xv;
-      if (lane <= D) atomicAdd(&acc[(c - c0) * DS + lane], gm * xc);
-    }
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) umap[t] = (int)u;
+}
+
+// n/f from the posterior lists, one wave per frame (frames of one workgroup
+// consecutive): the kept entries of frame g are added to the fixed-point
+// sums of its utterance (nf_add_entry).
+__global__ void __launch_bounds__(256)
+k_nf_accum(const float* __restrict__ X, int64_t F, int D, int C, const int* __restrict__ post_idx,
+           const float* __restrict__ post_val, const int* __restrict__ umap, int64_t U,
+           const float* __restrict__ mb, unsigned long long* __restrict__ acc,
+           int* __restrict__ err) {
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (g >= F) return;
+  const int u = umap[g];
+  if (u < 0 || u >= U) return;  // offsets rejected by k_frame_utt
+  const int id = (lane < KP) ? post_idx[g * KP + lane] : -1;
+  const float gv = (lane < KP) ? post_val[g * KP + lane] : 0.0f;
+  const float xv = (lane >= 1 && lane <= D) ? X[g * D + (lane - 1)] : 0.0f;
+  uint64_t mask = __ballot(id >= 0 && id < C);
+  while (mask) {
+    const int sl = __ffsll((unsigned long long)mask) - 1;
+    mask &= mask - 1;
+    nf_add_entry(acc, (int64_t)u * C, D, lane, xv, mb, __shfl(id, sl), (double)__shfl(gv, sl),
+                 err);
   }
-  __syncthreads();
-  const int nc = (C - c0) < NFB ? (C - c0) : NFB;
-  float* fo = f + ((size_t)u * C + c0) * D;
-  for (int i = tid; i < nc * D; i += 256) {
-    const int c = i / D, d = i - c * D;
-    fo[i] = acc[c * DS + 1 + d];
+}
+
+// n[u][c] and f[u][c][:] from the fixed-point sums, which are reset to zero
+// for the next call; every (u, c) is written, zeros included.
+__global__ void __launch_bounds__(256)
+k_nf_finish(int64_t U, int C, int D, unsigned long long* __restrict__ acc, float* __restrict__ n,
+            float* __restrict__ f) {
+  const int DS = D + 1;
+  const int64_t total = U * C * DS;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256) {
+    const long long v = (long long)acc[i];
+    acc[i] = 0ull;
+    const float val = (float)((double)v * kFixInv);
+    const int64_t row = i / DS;
+    const int col = (int)(i - row * DS);
+    if (col == 0)
+      n[row] = val;
+    else
+      f[row * D + col - 1] = val;
   }
-  for (int c = tid; c < nc; c += 256) n[(size_t)u * C + c0 + c] = acc[c * DS];
 }
 
 // hist[b][c] = number of posterior entries of component c in frame block b
@@ -247,23 +267,24 @@ __global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ pa
 
 }  // namespace
 
-void launch_stats_nf(ivx_ctx* ctx, const float* X, const int64_t* utt_off, int64_t U, int64_t F,
-                     float* n, float* f, hipStream_t s) {
+NfTarget launch_frame_utt(ivx_ctx* ctx, const int64_t* utt_off, int64_t U, int64_t F,
+                          hipStream_t s) {
+  if (U > 0) k_frame_utt<<<(unsigned)U, 256, 0, s>>>(utt_off, U, F, ctx->umap, ctx->dev_err);
+  return NfTarget{ctx->umap, U, ctx->standard ? ctx->bias32 : nullptr, ctx->nf_acc};
+}
+
+void launch_nf_accum(ivx_ctx* ctx, const float* X, int64_t F, const int* post_idx,
+                     const float* post_val, const NfTarget& nf, hipStream_t s) {
+  if (F <= 0 || nf.U <= 0) return;
+  k_nf_accum<<<(unsigned)((F + 3) / 4), 256, 0, s>>>(X, F, ctx->D, ctx->C, post_idx, post_val,
+                                                     nf.umap, nf.U, nf.mb, nf.acc, ctx->dev_err);
+}
+
+void launch_nf_finish(ivx_ctx* ctx, int64_t U, float* n, float* f, hipStream_t s) {
   if (U <= 0) return;
-  const float* mb = ctx->standard ? ctx->bias32 : nullptr;
-  if (ctx->tune.nf_block == 128) {
-    constexpr int NFB = 128;
-    dim3 grid((unsigned)U, (unsigned)((ctx->C + NFB - 1) / NFB));
-    const size_t lds = sizeof(float) * NFB * (ctx->D + 1);
-    k_stats_nf<NFB><<<grid, 256, lds, s>>>(X, utt_off, U, F, ctx->D, ctx->C, ctx->post_idx,
-                                           ctx->post_val, mb, n, f, ctx->dev_err);
-    return;
-  }
-  constexpr int NFB = 256;
-  dim3 grid((unsigned)U, (unsigned)((ctx->C + NFB - 1) / NFB));
-  const size_t lds = sizeof(float) * NFB * (ctx->D + 1);
-  k_stats_nf<NFB><<<grid, 256, lds, s>>>(X, utt_off, U, F, ctx->D, ctx->C, ctx->post_idx,
-                                         ctx->post_val, mb, n, f, ctx->dev_err);
+  const int64_t total = U * ctx->C * (ctx->D + 1);
+  const int64_t nb = std::min<int64_t>((total + 255) / 256, 8192);
+  k_nf_finish<<<(unsigned)nb, 256, 0, s>>>(U, ctx->C, ctx->D, ctx->nf_acc, n, f);
 }
 
 void launch_stats_S(ivx_ctx* ctx, const float* X, int64_t F, double* S_acc, hipStream_t s) {

@@ -2,8 +2,10 @@
 
 Tolerances: posteriors <= 1e-4 absolute (the target accuracy of the method's
 GPU form); frame log-likelihood 1e-8 absolute (both sides score the kept
-components exactly in FP64); n, f accumulate FP32 posteriors in FP32:
-|err| <= 1e-5 + 1e-5 |ref|; S accumulates FP32-rounded posteriors (relative
+components exactly in FP64); n, f are exact integer sums of the terms
+gamma x (FP32 posteriors, FP32 features) each rounded to a multiple of 2^-32,
+so they differ from the oracle by the posteriors' error alone:
+|err| <= 1e-5 + 1e-5 |ref|, and are bitwise deterministic; S accumulates FP32-rounded posteriors (relative
 rounding <= 6e-8 each) in FP64, so an entry's error is bounded by the rounding
 times sum_t gamma_tc |x_ti x_tj|, not by |S_ij| (mixed signs cancel):
 |err| <= 2e-7 sum_t gamma_tc |x_ti x_tj| + 1e-9.
@@ -73,6 +75,39 @@ def test_posteriors_match_oracle(which, prec, request):
     np.testing.assert_array_equal(gamma[rows[ok], pidx[ok]], pval[ok])
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16"])
+def test_posteriors_over_many_tiles_per_workgroup(prec):
+    """The frame kernel is persistent (two workgroups of 128 frames per CU on
+    a 256-CU device): with ~100k frames every workgroup sweeps several frame
+    tiles.  Sampled frames, the first and last tiles included, are compared
+    with the oracle."""
+    wl = synth.make(2, n_utts=100)
+    assert wl.F > 2 * 256 * 128
+    ctx = make_ctx(wl)
+    X = dev(wl.X)
+    F, C = wl.F, wl.shape.C
+    pi = torch.empty((F, 16), dtype=torch.int32, device="cuda")
+    pv = torch.empty((F, 16), dtype=torch.float32, device="cuda")
+    fl = torch.empty(F, dtype=torch.float64, device="cuda")
+    ctx.ubm_posteriors(X, post_idx=pi, post_val=pv, frame_ll=fl, prec=prec)
+    ctx.sync_status()
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([np.arange(128), np.arange(F - 128, F),
+                                    rng.choice(F, 2500, replace=False)]))
+    ll = oracle.frame_loglik(wl.X[idx], wl.w, wl.mu, wl.cov)
+    g_ref, lse_ref = oracle.posteriors(ll)
+    pidx, pval = pi.cpu().numpy()[idx], pv.cpu().numpy()[idx]
+    g = np.zeros((len(idx), C))
+    rows = np.repeat(np.arange(len(idx))[:, None], 16, 1)
+    ok = pidx >= 0
+    g[rows[ok], pidx[ok]] = pval[ok]
+    err = np.abs(g - g_ref).max()
+    lerr = np.abs(fl.cpu().numpy()[idx] - lse_ref).max()
+    print(f"{F} frames, {len(idx)} sampled: max |dgamma| {err:.2e}, max |dll| {lerr:.2e}")
+    assert err <= 1e-4
+    assert lerr <= 1e-8
+
+
 def _run_stats(wl, with_S=True, prec=0):
     ctx = make_ctx(wl)
     X = dev(wl.X)
@@ -101,6 +136,18 @@ def test_bw_stats_match_oracle(which, prec, request):
     print(which, "S error / bound", ratio)
     assert ratio <= 1.0
     assert abs(ll - lse_ref.sum()) <= 1e-9 * abs(lse_ref.sum())
+
+
+def test_bw_stats_are_bitwise_deterministic():
+    """n and f are integer sums (order-independent): two passes over the same
+    batch give identical bits, in both precision forms."""
+    wl = synth.make(2, n_utts=12)
+    for prec in (0, 1):
+        a = _run_stats(wl, with_S=False, prec=prec)
+        b = _run_stats(wl, with_S=False, prec=prec)
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+        assert a[3] == b[3]
 
 
 def test_ragged_shapes_and_empty_utterance():

@@ -3,8 +3,8 @@
 Every launch shape computes the same posteriors: the candidate lists keep
 every component within the margin of the frame's final best score whatever
 the number of components per launch, and the exact FP64 rescoring is shared,
-so the posterior lists agree exactly.  n and f differ only by the order of
-LDS float additions (<= 1e-6 relative); the split linear-term GEMM changes
+so the posterior lists agree exactly, and n and f (exact fixed-point sums of
+the same posteriors) are identical; the split linear-term GEMM changes
 the FP32 summation order of b(u) (i-vectors <= 1e-4 relative, cond(L) ~1e4).
 """
 import numpy as np
@@ -46,27 +46,27 @@ def test_autotune_returns_a_valid_tuning(setup):
     t = ctx.autotune(X, off)
     print("tuning", t)
     assert t["frame_ncb"] in (2, 4, 8) and t["frame_ncb_bf16"] in (2, 4, 8)
-    assert t["nf_block"] in (128, 256) and t["b_split"] >= 1
+    assert t["b_split"] >= 1
     assert ctx.tuning_get() == t
 
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_every_launch_shape_gives_the_same_results(setup, prec):
     ivx, wl, ctx, X, off = setup
-    ctx.tuning_set(frame_ncb=8, frame_ncb_bf16=8, nf_block=256, b_split=0)
+    ctx.tuning_set(frame_ncb=8, frame_ncb_bf16=8, b_split=0)
     ref = _run(ctx, wl, X, off, prec)
     for kw in (dict(frame_ncb=4, frame_ncb_bf16=4), dict(frame_ncb=2, frame_ncb_bf16=2),
-               dict(nf_block=128), dict(b_split=1), dict(b_split=16)):
+               dict(b_split=1), dict(b_split=16)):
         ctx.tuning_set(**kw)
         out = _run(ctx, wl, X, off, prec)
         np.testing.assert_array_equal(out[0], ref[0])
         np.testing.assert_array_equal(out[1], ref[1])
-        np.testing.assert_allclose(out[2], ref[2], rtol=1e-6, atol=1e-6)
-        np.testing.assert_allclose(out[3], ref[3], rtol=1e-6, atol=1e-5 * np.abs(ref[3]).max())
+        np.testing.assert_array_equal(out[2], ref[2])
+        np.testing.assert_array_equal(out[3], ref[3])
         rel = np.linalg.norm(out[4] - ref[4]) / np.linalg.norm(ref[4])
         print(kw, "phi rel", rel)
         assert rel <= 1e-4
-        ctx.tuning_set(frame_ncb=8, frame_ncb_bf16=8, nf_block=256, b_split=0)
+        ctx.tuning_set(frame_ncb=8, frame_ncb_bf16=8, b_split=0)
 
 
 def test_tuning_set_rejects_unknown_shapes(setup):
@@ -74,4 +74,5 @@ def test_tuning_set_rejects_unknown_shapes(setup):
     with pytest.raises(ivx.IvxError, match="EINVAL"):
         ctx.tuning_set(frame_ncb=6)
     with pytest.raises(ivx.IvxError, match="EINVAL"):
-        ctx.tuning_set(nf_block=512)
+        ctx.tuning_set(b_split=4096)
+
