@@ -64,6 +64,10 @@ def parse():
     ap.add_argument("--learned-steps", type=int, default=3000,
                     help="training steps of the learned selector (0: skip the learned form)")
     ap.add_argument("--learned-batch", type=int, default=4096)
+    ap.add_argument("--learned-sweep", type=str, default="",
+                    help="widths:training-utterances:steps lists, e.g. '512,1024,2048:400,1600:3000': "
+                         "train the selector at each width and training-set size and report "
+                         "held-out loss, missed mass and fallback (off by default)")
     ap.add_argument("--no-standard", action="store_true",
                     help="skip the standard-formulation timing")
     ap.add_argument("--no-stream", action="store_true",
@@ -407,6 +411,80 @@ def batching_block(args, wl, tuning, dev):
     return out
 
 
+def learned_sweep(args, ctx, wl, X, dev):
+    """Selector width and training-set size against held-out accuracy on the
+    workload's own data: for each (H, training utterances) a 60-H-H-C network
+    is trained from the same initialisation recipe on the exact all-component
+    posteriors of the first utterances and evaluated on the last tenth of the
+    utterances (cross-entropy against the exact posteriors, mass the top-k
+    proposals miss, fallback fraction)."""
+    import numpy as np
+    import torch
+
+    import synth
+    widths, sizes, steps = args.learned_sweep.split(":")
+    widths = [int(v) for v in widths.split(",")]
+    sizes = [int(v) for v in sizes.split(",")]
+    steps = int(steps)
+    C, D, U, F = wl.shape.C, wl.shape.D, wl.U, wl.F
+    k, B = 20, args.learned_batch
+    pi = torch.empty((F, 16), dtype=torch.int32, device=dev)
+    pv = torch.empty((F, 16), dtype=torch.float32, device=dev)
+    ctx.ubm_posteriors(X, post_idx=pi, post_val=pv)
+    Ue = U - U // 10
+    Fe0 = int(wl.utt_off[Ue])
+    Xe = X[Fe0:]
+    Fe = F - Fe0
+    eidx = torch.arange(Fe0, min(F, Fe0 + (1 << 16)), dtype=torch.int64, device=dev)
+    out = []
+    for H in widths:
+        for Utr in sizes:
+            Utr = min(Utr, Ue)
+            Ftr = int(wl.utt_off[Utr])
+            mean, std = ctx.feature_stats(X[:Ftr])
+            params = torch.from_numpy(synth.mlp_init(D, H, H, C, seed=args.seed)).to(dev)
+            ctx.selector_set(params, mean, std, H1=H, H2=H, k=k, min_mass=0.99, max_train_batch=B)
+            loss = torch.zeros(1, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(steps):
+                fidx = torch.from_numpy(synth.sample_frames(Ftr, B, seed=i)).to(dev)
+                ctx.selector_train_step(X, fidx, pi, pv, 1e-3 if i < 0.7 * steps else 3e-4,
+                                        loss=loss)
+            torch.cuda.synchronize()
+            t_train = time.perf_counter() - t0
+            train_loss = loss.item()
+            # held-out cross-entropy on up to 65,536 frames of the last utterances
+            hl = torch.zeros(1, dtype=torch.float64, device=dev)
+            tot, nbt = 0.0, 0
+            for b0 in range(0, eidx.shape[0], B):
+                ctx.selector_grad(X, eidx[b0:b0 + B], pi, pv, loss=hl)
+                tot += hl.item()
+                nbt += 1
+            held_loss = tot / max(1, nbt)
+            prop = torch.empty((Fe, k), dtype=torch.int32, device=dev)
+            mass = torch.empty(Fe, dtype=torch.float32, device=dev)
+            ctx.selector_forward(Xe, prop=prop, mass=mass)
+            miss = torch.empty(Fe, dtype=torch.float64, device=dev)
+            for r0 in range(0, Fe, 1 << 18):
+                r1 = min(Fe, r0 + (1 << 18))
+                a = pi[Fe0 + r0:Fe0 + r1].long()
+                hit = ((a.unsqueeze(2) == prop[r0:r1].long().unsqueeze(1)) & (a.unsqueeze(2) >= 0)).any(2)
+                miss[r0:r1] = 1.0 - (pv[Fe0 + r0:Fe0 + r1].double() * hit).sum(1)
+            ctx.sync_status()
+            row = {"H": H, "train_utterances": Utr, "train_frames": Ftr, "steps": steps,
+                   "batch": B, "train_seconds": round(t_train, 2),
+                   "train_loss_last_batch": round(train_loss, 4),
+                   "heldout_loss": round(held_loss, 4),
+                   "heldout_missed_mass_mean": round(float(miss.mean()), 4),
+                   "heldout_fallback_fraction": round(float((mass < 0.99).float().mean()), 4)}
+            log(f"[bench] learned sweep: {row}")
+            out.append(row)
+    return {"workload_frames": F, "heldout_utterances": U - Ue, "k": k,
+            "loss": "soft-target cross-entropy against the exact all-component posteriors",
+            "runs": out}
+
+
 def backend_block(ctx, wl0, dev):
     """Sec. 4.1 back-end at the paper's dimensions on synthetic speakers drawn
     from a full-size model (D 60, C 2048, R 400): i-vectors extracted with it in the
@@ -591,22 +669,21 @@ def main():
     em_utts_per_s = U * K / (phase["em"] / 1e3)
 
     # roofline of the dominant kernel: the expanded-feature frame GEMM, one
-    # launch per tile of 32 * frame_ncb components (Cpad / tile launches per
-    # pass over the frames)
+    # persistent launch per pass that scores every frame against all C
+    # components (2 K C FLOPs per frame, the method's count)
     Kexp = (D + 1) * (D + 2) // 2
     tune_now = ctx.tuning_get()
-    tile = 256 if tune_now["frame_ncb"] == 8 else 128
-    flop_per_frame_tile = 2.0 * Kexp * tile
+    flop_per_frame = 2.0 * Kexp * C
     fs_ms, fs_calls = prof["frame_select"]
     fs_avg_s = fs_ms / max(fs_calls, 1) / 1e3
-    achieved = flop_per_frame_tile * F / fs_avg_s / 1e12
+    achieved = flop_per_frame * F / fs_avg_s / 1e12
     roof = {"kernel": "k_frame_tile", "bound": "mfma", "achieved": round(achieved, 2),
             "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
             "traffic": measured_traffic("k_frame_tile", f"shape{args.shape}", F),
             "avg_launch_ms": round(fs_avg_s * 1e3, 3), "launches_per_step": fs_calls // K,
-            "flop_per_frame_per_launch": flop_per_frame_tile, "frames_per_launch": F,
-            "components_per_launch": tile}
+            "flop_per_frame_per_launch": flop_per_frame, "frames_per_launch": F,
+            "components_per_launch": C}
     log("[bench] FP32 kernel groups (ms per step): " + ", ".join(
         f"{k}={v[0] / K:.2f}" for k, v in prof.items() if v[1]))
     log(f"[bench] objective after last step: {obj.item():.6e}")
@@ -617,10 +694,9 @@ def main():
         fs16_ms, fs16_calls = prof16["frame_select"]
         fs16_avg_s = fs16_ms / max(fs16_calls, 1) / 1e3
         bf16_peak = 2500.0
-        tile16 = 256 if tune_now["frame_ncb_bf16"] == 8 else 128
         # the method's FLOPs (2 K per frame and component) counted once; the
         # MFMA instructions execute more (split operands), reported apart
-        ach16 = 2.0 * Kexp * tile16 * F / fs16_avg_s / 1e12
+        ach16 = flop_per_frame * F / fs16_avg_s / 1e12
         log("[bench] BF16 kernel groups (ms per step): " + ", ".join(
             f"{k}={v[0] / Ks:.2f}" for k, v in prof16.items() if v[1]))
         # one iteration of each form from the same initial model: BF16 vs FP32
@@ -642,7 +718,7 @@ def main():
                                  "mfma_products_per_method_product": BF16_PRODUCTS,
                                  "hardware_mfma_tflops": round(BF16_PRODUCTS * ach16, 2),
                                  "avg_launch_ms": round(fs16_avg_s * 1e3, 3),
-                                 "components_per_launch": tile16},
+                                 "components_per_launch": C},
                 "vs_fp32_form_first_iteration": {
                     "ivector_min_cosine": float(cos.min()),
                     "objective_rel_diff": abs(outs[1][1] - outs[0][1]) / abs(outs[0][1])}}
@@ -760,6 +836,10 @@ def main():
         learned = learned_form(args, ctx, wl, X, step, timed, reset_model, phi, Ks, Ws, dev)
         log(f"[bench] learned selection: {learned}")
 
+    sweep = None
+    if args.learned_sweep:
+        sweep = learned_sweep(args, ctx, wl, X, dev)
+
     batching = None
     if gen4 is not None:
         wl4 = gen4.join()
@@ -808,6 +888,7 @@ def main():
         "streamed_from_host": streamed,
         "pruned_alignment": pruned,
         "learned_selection": learned,
+        "learned_sweep": sweep,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
