@@ -402,9 +402,12 @@ ivx_status ivx_selector_counts(ivx_ctx* ctx, int64_t* fallback_frames, int64_t* 
  *                   wave)
  *   frame_ncb_bf16  the same for the BF16 split form
  *   b_split         K-splits of the linear-term GEMM b = p + F V (0: chosen
- *                   from the grid size; else 1..max) */
+ *                   from the grid size; else 1..max)
+ *   frame_direct    FP32 frame GEMM with one 32-frame block per wave: 1 reads
+ *                   the coefficients straight into registers (no LDS staging,
+ *                   no barrier in the k loop), 0 stages them through LDS */
 typedef struct {
-  int32_t frame_ncb, frame_ncb_bf16, b_split;
+  int32_t frame_ncb, frame_ncb_bf16, b_split, frame_direct;
 } ivx_tuning;
 
 /* Times the candidate launch shapes on the given workload (X, utt_off as in

@@ -23,7 +23,7 @@ namespace {
 bool valid_tuning(const ivx_tuning& t) {
   auto ncb_ok = [](int v) { return v == 2 || v == 4 || v == 8; };
   return ncb_ok(t.frame_ncb) && ncb_ok(t.frame_ncb_bf16) &&
-         t.b_split >= 0 && t.b_split <= 1024;
+         t.b_split >= 0 && t.b_split <= 1024 && (t.frame_direct == 0 || t.frame_direct == 1);
 }
 
 struct Timer {
@@ -93,19 +93,29 @@ ivx_status ivx_autotune(ivx_ctx* ctx, const float* X, const int64_t* utt_off, in
   const bool prof = ctx->prof_on;
   ctx->prof_on = false;
   ivx_tuning best = ctx->tune;
-  // frame GEMM, both forms
+  // frame GEMM, both forms; the FP32 one staged through LDS or direct
   for (int prec = 0; prec < 2; ++prec) {
     float tb = INFINITY;
-    for (int ncb : {8, 4, 2}) {
-      if (prec == IVX_BF16)
+    for (int v = 0; v < (prec == IVX_BF16 ? 3 : 5); ++v) {
+      const int ncb = v < 3 ? (v == 0 ? 8 : v == 1 ? 4 : 2) : (v == 3 ? 8 : 4);
+      const int direct = v >= 3 ? 1 : 0;
+      if (prec == IVX_BF16) {
         ctx->tune.frame_ncb_bf16 = ncb;
-      else
+      } else {
         ctx->tune.frame_ncb = ncb;
+        ctx->tune.frame_direct = direct;
+      }
       const float t = tm.best([&] { launch_frame_select(ctx, X, F, prec, s); });
-      // the 256-component launch is kept unless the other is clearly faster
+      // the first candidate (256 components, staged) is kept unless another
+      // is clearly faster
       if (t < 0.99f * tb) {
         tb = t;
-        (prec == IVX_BF16 ? best.frame_ncb_bf16 : best.frame_ncb) = ncb;
+        if (prec == IVX_BF16) {
+          best.frame_ncb_bf16 = ncb;
+        } else {
+          best.frame_ncb = ncb;
+          best.frame_direct = direct;
+        }
       }
     }
   }

@@ -240,6 +240,82 @@ k_frame_tile(const float* __restrict__ X, int64_t F, int D, const float* __restr
   }
 }
 
+// The same persistent FP32 kernel with the coefficient operand read by each
+// lane straight from the caches into registers (two chunks double
+// buffered) instead of being staged through LDS: the waves of a workgroup
+// share only the frames, so the k loop has no barrier and every wave runs
+// ahead on its own.  Each lane reads the float4 of its component row and
+// k-half of every 32-component block (NCB float4 per chunk of 8 features;
+// the four waves of a workgroup read the same 8 KB, mostly from L1).
+template <int NCB>
+__global__ void __launch_bounds__(256, 2)
+k_frame_tile_direct(const float* __restrict__ X, int64_t F, int D,
+                    const float* __restrict__ shift, const float* __restrict__ W, int C, int Cpad,
+                    int Kpad, const uint16_t* __restrict__ pairs, float margin,
+                    int2* __restrict__ cand, float* __restrict__ cM, int* __restrict__ cflag,
+                    const int* __restrict__ Fdev) {
+  constexpr int CT = 32 * NCB;  // components per component tile
+  extern __shared__ float smem[];
+  if (Fdev && (int64_t)Fdev[0] < F) F = Fdev[0];
+  const int64_t ntile = (F + FT - 1) / FT;
+  if ((int64_t)blockIdx.x >= ntile) return;  // whole workgroup, before any barrier
+  const int DS = D + 1;
+  float* xs = smem;                                              // [FT][DS]
+  uint32_t* prs = reinterpret_cast<uint32_t*>(xs + FT * DS);     // [Kpad/2] index pairs
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int nq = Kpad / 8;  // even: Kpad is a multiple of 16
+  for (int i = tid; i < Kpad / 2; i += 256) prs[i] = reinterpret_cast<const uint32_t*>(pairs)[i];
+  const float* xw = xs + (wave * FR + l32) * DS;
+
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t f0 = tile * FT;
+    __syncthreads();  // the previous tile's readers of xs are done
+    load_frames(xs, FT, DS, X, f0, F, D, shift);
+    FrameState st;
+    frame_state_init(st, f0 + wave * FR + l32, F, h, cand);
+    __syncthreads();
+    for (int c0 = 0; c0 < Cpad; c0 += CT) {
+      // lane's coefficients: chunk q, component c0 + 32 cb + l32, features 4h..4h+3
+      const float* wl = W + ((size_t)c0 + l32) * 8 + 4 * h;
+      const size_t qs = (size_t)Cpad * 8;  // stride between chunks
+      float4 wa[NCB], wb[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) wa[cb] = *reinterpret_cast<const float4*>(wl + cb * 256);
+      floatx16 acc[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[cb] = floatx16{0};
+      auto chunk = [&](int q, const float4 (&wv)[NCB]) {
+        const uint32_t pw0 = prs[4 * q + 2 * h], pw1 = prs[4 * q + 2 * h + 1];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const uint32_t pr = ((s < 2) ? pw0 : pw1) >> ((s & 1) * 16);
+          const float bv = xw[pr & 0xff] * xw[(pr >> 8) & 0xff];
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) {
+            const float av = (s == 0) ? wv[cb].x : (s == 1) ? wv[cb].y : (s == 2) ? wv[cb].z : wv[cb].w;
+            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[cb], 0, 0, 0);
+          }
+        }
+      };
+      for (int q = 0; q < nq; q += 2) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          wb[cb] = *reinterpret_cast<const float4*>(wl + (q + 1) * qs + cb * 256);
+        chunk(q, wa);
+        if (q + 2 < nq) {
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            wa[cb] = *reinterpret_cast<const float4*>(wl + (q + 2) * qs + cb * 256);
+        }
+        chunk(q + 1, wb);
+      }
+      frame_epilogue<NCB>(acc, st, h, c0, C, margin, c0 + CT >= Cpad, cM, cflag);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- BF16 form
 // Same tiling as k_frame_tile, with the dot products on
 // v_mfma_f32_32x32x16_bf16 and FP32 accumulation.  Both operands are split
@@ -600,6 +676,9 @@ size_t frame_lds_bf16(int D, int Kpad) {
   return sizeof(__bf16) * 2 * (32 * NCB) * WB16 + sizeof(float) * (size_t)FT * FB * (D + 1) +
          sizeof(uint16_t) * Kpad;
 }
+size_t frame_lds_direct(int D, int Kpad) {
+  return sizeof(float) * (size_t)FT * (D + 1) + sizeof(uint16_t) * Kpad;
+}
 template <int NCB, int FB>
 size_t frame_lds_f32(int D, int Kpad) {
   return sizeof(float) * (2 * (32 * NCB) * WLD + (size_t)FT * FB * (D + 1)) +
@@ -619,6 +698,15 @@ void frame_launches(ivx_ctx* ctx, const float* X, int64_t F, int prec, hipStream
     k_frame_tile_bf16<NCB, FB><<<nblk, 256, lds, s>>>(
         X, F, ctx->D, ctx->shift, ctx->W16, ctx->C, ctx->Cpad, ctx->Kpad, ctx->pairs,
         ctx->margin_bf16, ctx->cand, ctx->cM, ctx->cflag, Fdev);
+    return;
+  }
+  if (FB == 1 && ctx->tune.frame_direct) {
+    // the 128-component direct kernel fits three workgroups per CU
+    const unsigned nd =
+        (unsigned)std::min<int64_t>(ntile, (int64_t)ctx->ncu * (NCB == 4 ? 3 : 2));
+    k_frame_tile_direct<NCB><<<nd, 256, frame_lds_direct(ctx->D, ctx->Kpad), s>>>(
+        X, F, ctx->D, ctx->shift, ctx->Wexp, ctx->C, ctx->Cpad, ctx->Kpad, ctx->pairs,
+        ctx->margin, ctx->cand, ctx->cM, ctx->cflag, Fdev);
     return;
   }
   const size_t lds = frame_lds_f32<NCB, FB>(ctx->D, ctx->Kpad);
