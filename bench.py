@@ -65,9 +65,10 @@ def parse():
                     help="training steps of the learned selector (0: skip the learned form)")
     ap.add_argument("--learned-batch", type=int, default=4096)
     ap.add_argument("--learned-sweep", type=str, default="",
-                    help="widths:training-utterances:steps lists, e.g. '512,1024,2048:400,1600:3000': "
-                         "train the selector at each width and training-set size and report "
-                         "held-out loss, missed mass and fallback (off by default)")
+                    help="widths:training-utterances:steps lists, e.g. '512,1024,2048:400,1600:3000', "
+                         "several separated by ';': train the selector at each width and "
+                         "training-set size and report held-out loss, missed mass and fallback "
+                         "(off by default)")
     ap.add_argument("--no-standard", action="store_true",
                     help="skip the standard-formulation timing")
     ap.add_argument("--no-stream", action="store_true",
@@ -422,10 +423,10 @@ def learned_sweep(args, ctx, wl, X, dev):
     import torch
 
     import synth
-    widths, sizes, steps = args.learned_sweep.split(":")
-    widths = [int(v) for v in widths.split(",")]
-    sizes = [int(v) for v in sizes.split(",")]
-    steps = int(steps)
+    runs = []
+    for spec in args.learned_sweep.split(";"):
+        widths, sizes, steps = spec.split(":")
+        runs += [(int(h), int(n), int(steps)) for h in widths.split(",") for n in sizes.split(",")]
     C, D, U, F = wl.shape.C, wl.shape.D, wl.U, wl.F
     k, B = 20, args.learned_batch
     pi = torch.empty((F, 16), dtype=torch.int32, device=dev)
@@ -437,8 +438,8 @@ def learned_sweep(args, ctx, wl, X, dev):
     Fe = F - Fe0
     eidx = torch.arange(Fe0, min(F, Fe0 + (1 << 16)), dtype=torch.int64, device=dev)
     out = []
-    for H in widths:
-        for Utr in sizes:
+    for H, Utr, steps in runs:
+        if True:
             Utr = min(Utr, Ue)
             Ftr = int(wl.utt_off[Utr])
             mean, std = ctx.feature_stats(X[:Ftr])
