@@ -405,9 +405,12 @@ ivx_status ivx_selector_counts(ivx_ctx* ctx, int64_t* fallback_frames, int64_t* 
  *                   from the grid size; else 1..max)
  *   frame_direct    FP32 frame GEMM with one 32-frame block per wave: 1 reads
  *                   the coefficients straight into registers (no LDS staging,
- *                   no barrier in the k loop), 0 stages them through LDS */
+ *                   no barrier in the k loop), 0 stages them through LDS
+ *   mstep_left      M-step Cholesky of A_c: 1 left-looking (each block column
+ *                   formed in LDS from the finished ones and written once),
+ *                   0 right-looking (trailing tiles updated in place) */
 typedef struct {
-  int32_t frame_ncb, frame_ncb_bf16, b_split, frame_direct;
+  int32_t frame_ncb, frame_ncb_bf16, b_split, frame_direct, mstep_left;
 } ivx_tuning;
 
 /* Times the candidate launch shapes on the given workload (X, utt_off as in

@@ -234,7 +234,7 @@ struct ivx_ctx {
   int* dev_err = nullptr;     // [4]: see raise_error
 
   // launch shapes picked by the autotuner (ivx_autotune); defaults below
-  ivx_tuning tune = {8, 8, 0, 0};
+  ivx_tuning tune = {8, 8, 0, 0, 0};
 
   // learned Gaussian selection (ivx_selector_set), null until set
   ivx::Selector* sel = nullptr;

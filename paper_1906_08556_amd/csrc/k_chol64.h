@@ -153,6 +153,138 @@ __device__ inline int chol_tp64(double* __restrict__ A, int nb, double* __restri
   return 0;
 }
 
+// Factors the diagonal tile held in dg [256] (lower part used) by wave 0:
+// G_kk to dg and to Akk, W_kk = G_kk^{-1} (row-major, upper part zero) to W.
+// Sets *s_bad to 1 + the first row whose pivot was not positive.
+__device__ inline void diag_factor64(double* dg, double* __restrict__ Akk,
+                                     double* __restrict__ W, int row0, int* s_bad) {
+  const int lane = threadIdx.x & 63;
+  for (int j = 0; j < 16; ++j) {
+    const double piv = dg[j * 16 + j];
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      if (lane == 0) *s_bad = row0 + j + 1;
+      break;  // piv is the same in every lane: uniform exit
+    }
+    const double ljj = sqrt(piv);
+    __builtin_amdgcn_wave_barrier();
+    if (lane > j && lane < 16) dg[lane * 16 + j] /= ljj;
+    if (lane == j) dg[j * 16 + j] = ljj;
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane; e < 256; e += 64) {
+      const int i = e >> 4, c = e & 15;
+      if (c > j && i >= c) dg[e] -= dg[i * 16 + j] * dg[c * 16 + j];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int e = lane; e < 256; e += 64) {
+    const int i = e >> 4, c = e & 15;
+    const double v = (c <= i) ? dg[e] : 0.0;
+    dg[e] = v;
+    Akk[e] = v;
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane < 16 && *s_bad == 0) {
+    const int j = lane;
+    double w[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int l = 0; l < i; ++l) s -= dg[i * 16 + l] * w[l];
+      w[i] = (i >= j) ? s / dg[i * 16 + i] : 0.0;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) W[i * 16 + j] = w[i];
+  }
+}
+
+// Left-looking blocked Cholesky A = G G^T with the same contract as
+// chol_tp64 (lower tiles in place, W_k = G_kk^{-1} to Winv[k * 256]).  Block
+// column k is formed in LDS from the finished columns j < k,
+// A_(k+i),k - sum_j G_(k+i),j G_k,j^T on MFMA (each wave two tile rows with
+// independent accumulators, the next j's tiles requested before the current
+// MFMAs), then its diagonal tile is factored and inverted and the rest
+// multiplied by that inverse; the column is written once.  A finished tile
+// is read once for every later block column it feeds and never rewritten,
+// where the right-looking form reads and writes every trailing tile at each
+// step.  LDS: dg [256], pan [nb * 256].
+__device__ inline int chol_ll64(double* __restrict__ A, int nb, double* __restrict__ Winv,
+                                double* dg, double* pan, int* s_bad) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, q16 = lane >> 4;
+  const int eo = l16 * 16 + q16;  // element (l16, 4 q + q16) is at eo + 4 q
+  if (tid == 0) *s_bad = 0;
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    const int m1 = nb - k;  // tiles of block column k, the diagonal one first
+    for (int it0 = wave; it0 < m1; it0 += 8) {
+      const int itA = it0, itB = it0 + 4 < m1 ? it0 + 4 : it0;
+      const double* At = A + tp_off(k + itA, k);
+      const double* Bt = A + tp_off(k + itB, k);
+      doublex4 accA, accB;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        accA[r] = At[(4 * r + q16) * 16 + l16];
+        accB[r] = Bt[(4 * r + q16) * 16 + l16];
+      }
+      double ck[4], ca[4], cb[4], nk[4], na[4], nb4[4];
+      auto load = [&](int j, double (&gk)[4], double (&ga)[4], double (&gb)[4]) {
+        const double* Gk = A + tp_off(k, j);
+        const double* Ga = A + tp_off(k + itA, j);
+        const double* Gb = A + tp_off(k + itB, j);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          gk[q] = Gk[eo + 4 * q];
+          ga[q] = Ga[eo + 4 * q];
+          gb[q] = Gb[eo + 4 * q];
+        }
+      };
+      if (k > 0) load(0, ck, ca, cb);
+      for (int j = 0; j < k; ++j) {
+        if (j + 1 < k) load(j + 1, nk, na, nb4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ca[q], ck[q], accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-cb[q], ck[q], accB, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ck[q] = nk[q];
+          ca[q] = na[q];
+          cb[q] = nb4[q];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        pan[itA * 256 + (4 * r + q16) * 16 + l16] = accA[r];
+        if (itB != itA) pan[itB * 256 + (4 * r + q16) * 16 + l16] = accB[r];
+      }
+    }
+    __syncthreads();
+    if (wave == 0) {
+      for (int e = lane; e < 256; e += 64) dg[e] = pan[e];
+      __builtin_amdgcn_wave_barrier();
+      diag_factor64(dg, A + tp_off(k, k), Winv + k * 256, k * 16, s_bad);
+    }
+    __syncthreads();
+    if (*s_bad) return *s_bad;
+    const double* W = Winv + k * 256;
+    // panel: G_(k+i),k = pan_i W_kk^T, written once
+    for (int it = 1 + wave; it < m1; it += 4) {
+      const double* Pt = pan + it * 256;
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16_xyt([&](int i, int l) { return Pt[i * 16 + l]; },
+                      [&](int j, int l) { return W[j * 16 + l]; }, acc, 1.0);
+      double* Gt = A + tp_off(k + it, k);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Gt[(4 * r + q16) * 16 + l16] = acc[r];
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
 // Solves (G G^T) X = B in place for B of nrow (<= nb * 16) rows and ncol
 // (<= 64) columns, element (r, d) at B[d * ldb + r]; rows >= nrow and
 // columns >= ncol are treated as zero and never written.  G and Winv come

@@ -85,11 +85,11 @@ k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
               const double* __restrict__ Cc, const double* __restrict__ N,
               const double* __restrict__ S, int update_sigma, double* __restrict__ T,
               double* __restrict__ Sigma, double* __restrict__ Winv_all,
-              int* __restrict__ status, int* __restrict__ err) {
+              int* __restrict__ status, int* __restrict__ err, int left) {
   extern __shared__ double sm[];
   double* dg = sm;            // [256]
   double* zb = sm + 256;      // [16 * 64]
-  double* big = sm + 1280;    // max((nb - 1) * 256, 4096 + D * D)
+  double* big = sm + 1280;    // max(nb * 256, 4096 + D * D)
   __shared__ int s_bad;
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, q16 = lane >> 4;
@@ -103,7 +103,8 @@ k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
   // identity on the padded diagonal so the padding factors trivially
   for (int d = R + tid; d < nb * 16; d += 256) Ac[tp_off(d >> 4, d >> 4) + (d & 15) * 17] = 1.0;
   __syncthreads();
-  const int bad = chol_tp64(Ac, nb, Winv, dg, big, &s_bad);
+  const int bad = left ? chol_ll64(Ac, nb, Winv, dg, big, &s_bad)
+                       : chol_tp64(Ac, nb, Winv, dg, big, &s_bad);
   if (bad) {
     if (tid == 0) {
       status[c] = 3;
@@ -400,7 +401,7 @@ bool mstep_set_attributes() {
 
 size_t mstep_lds_bytes(int R, int D) {
   const int nb = (R + 15) / 16;
-  size_t nbig = (size_t)(nb - 1) * 256;
+  size_t nbig = (size_t)nb * 256;  // the left-looking form keeps a whole block column
   if ((size_t)4096 + (size_t)D * D > nbig) nbig = (size_t)4096 + (size_t)D * D;
   return sizeof(double) * (1280 + nbig);
 }
@@ -410,7 +411,7 @@ void launch_mstep_solve(ivx_ctx* ctx, const ivx_accum* acc, const double* S, int
   const int nb = (ctx->R + 15) / 16;
   k_mstep_solve<<<ctx->C, 256, mstep_lds_bytes(ctx->R, ctx->D), s>>>(
       ctx->C, ctx->D, ctx->R, nb, ctx->TP, acc->A, acc->Cc, acc->N, S, update_sigma, ctx->T,
-      ctx->Sigma, ctx->Winv, status, ctx->dev_err);
+      ctx->Sigma, ctx->Winv, status, ctx->dev_err, ctx->tune.mstep_left);
 }
 
 ivx_status launch_mindiv(ivx_ctx* ctx, const ivx_accum* acc, bool standard, bool update_mean,

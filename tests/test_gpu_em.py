@@ -199,9 +199,11 @@ def _accum_from_oracle(ctx, ref):
     return acc
 
 
-def test_mstep_solve_and_objective_match_oracle(cfg1):
+@pytest.mark.parametrize("left", [0, 1], ids=["right-looking", "left-looking"])
+def test_mstep_solve_and_objective_match_oracle(cfg1, left):
     wl, n, f, S, tv = cfg1
     ctx = _ctx_tv(wl, tv)
+    ctx.tuning_set(mstep_left=left)
     e = oracle.estep(n, f, *tv)
     ref = oracle.accumulate(n, f, e["phi"], e["Phi"])
     acc = _accum_from_oracle(ctx, ref)
@@ -370,11 +372,13 @@ def full_shape():
     return wl, tv, r
 
 
-def _full_shape_iteration(wl, tv, r, prec):
+def _full_shape_iteration(wl, tv, r, prec, **tuning):
     """One GPU iteration (posteriors, statistics, E-step, accumulation,
     M-step, minimum divergence, realignment) from the oracle's initial state
     in the given precision form, compared with the oracle's iteration."""
     ctx = make_ctx(wl)
+    if tuning:
+        ctx.tuning_set(**tuning)
     ctx.set_tv(dev(tv[0]), dev(tv[1]), dev(tv[2]))
     U, C, D, R = wl.U, wl.shape.C, wl.shape.D, wl.shape.R
     assert U > 256  # interior 256-row tiles of the E-step GEMMs
@@ -426,6 +430,19 @@ def _full_shape_iteration(wl, tv, r, prec):
 @pytest.mark.timeout(900)
 def test_em_iteration_full_shape_matches_oracle(full_shape):
     e = _full_shape_iteration(*full_shape, prec=0)
+    assert e["cos"] >= 0.9999
+    assert e["obj"] <= 1e-6
+    assert e["t_max"] <= 1e-3
+    assert e["sigma"] <= 1e-4
+    assert e["p0"] <= 1e-4
+    assert e["mu"] <= 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_em_iteration_full_shape_left_looking_mstep(full_shape):
+    """The M-step with the left-looking Cholesky of A_c (tuning field
+    mstep_left) meets the same bounds at the full model shape."""
+    e = _full_shape_iteration(*full_shape, prec=0, mstep_left=1)
     assert e["cos"] >= 0.9999
     assert e["obj"] <= 1e-6
     assert e["t_max"] <= 1e-3

@@ -53,7 +53,7 @@ def test_autotune_returns_a_valid_tuning(setup):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_every_launch_shape_gives_the_same_results(setup, prec):
     ivx, wl, ctx, X, off = setup
-    ctx.tuning_set(frame_ncb=8, frame_ncb_bf16=8, b_split=0, frame_direct=0)
+    ctx.tuning_set(frame_ncb=8, frame_ncb_bf16=8, b_split=0, frame_direct=0, mstep_left=0)
     ref = _run(ctx, wl, X, off, prec)
     for kw in (dict(frame_ncb=4, frame_ncb_bf16=4), dict(frame_ncb=2, frame_ncb_bf16=2),
                dict(frame_ncb=8, frame_direct=1), dict(frame_ncb=4, frame_direct=1),
@@ -67,7 +67,7 @@ def test_every_launch_shape_gives_the_same_results(setup, prec):
         rel = np.linalg.norm(out[4] - ref[4]) / np.linalg.norm(ref[4])
         print(kw, "phi rel", rel)
         assert rel <= 1e-4
-        ctx.tuning_set(frame_ncb=8, frame_ncb_bf16=8, b_split=0, frame_direct=0)
+        ctx.tuning_set(frame_ncb=8, frame_ncb_bf16=8, b_split=0, frame_direct=0, mstep_left=0)
 
 
 def test_tuning_set_rejects_unknown_shapes(setup):
@@ -78,4 +78,6 @@ def test_tuning_set_rejects_unknown_shapes(setup):
         ctx.tuning_set(b_split=4096)
     with pytest.raises(ivx.IvxError, match="EINVAL"):
         ctx.tuning_set(frame_direct=2)
+    with pytest.raises(ivx.IvxError, match="EINVAL"):
+        ctx.tuning_set(mstep_left=2)
 
