@@ -82,6 +82,9 @@ def parse():
                     help="skip the pruned alignment (diagonal-UBM top-20, drop < 0.025)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of timing the candidates")
+    ap.add_argument("--tune", type=str, default="",
+                    help="launch-shape fields set after the autotuner, e.g. 'estep_global=1,"
+                         "mstep_left=0' (see ivx_tuning)")
     return ap.parse_args()
 
 
@@ -653,6 +656,10 @@ def main():
         t0 = time.time()
         tuning = ctx.autotune(X, off)
         log(f"[bench] autotuned launch shapes {tuning} in {time.time() - t0:.1f}s")
+    if args.tune:
+        ctx.tuning_set(**{k: int(v) for k, v in (kv.split("=") for kv in args.tune.split(","))})
+        tuning = ctx.tuning_get()
+        log(f"[bench] launch shapes set to {tuning}")
     K = args.steps
     Ks, Ws = max(1, min(K, args.form_steps)), min(args.warmup, 2)
     elapsed, phase, prof = timed(0, K, args.warmup)

@@ -408,9 +408,18 @@ ivx_status ivx_selector_counts(ivx_ctx* ctx, int64_t* fallback_frames, int64_t* 
  *                   no barrier in the k loop), 0 stages them through LDS
  *   mstep_left      M-step Cholesky of A_c: 1 left-looking (each block column
  *                   formed in LDS from the finished ones and written once),
- *                   0 right-looking (trailing tiles updated in place) */
+ *                   0 right-looking (trailing tiles updated in place)
+ *   estep_global    per-utterance E-step factorisation: 0 holds the whole
+ *                   precision matrix in the registers of one workgroup
+ *                   (R <= 400; larger R always use the other form), 1 works
+ *                   on the matrix in device memory tile by tile
+ *   mstep_global    M-step solve: 0 keeps the right-hand sides in registers
+ *                   and runs the forward solve inside a left-looking Cholesky
+ *                   (R <= 400), 1 the form chosen by mstep_left, with the
+ *                   right-hand sides in device memory */
 typedef struct {
-  int32_t frame_ncb, frame_ncb_bf16, b_split, frame_direct, mstep_left;
+  int32_t frame_ncb, frame_ncb_bf16, b_split, frame_direct, mstep_left, estep_global,
+      mstep_global;
 } ivx_tuning;
 
 /* Times the candidate launch shapes on the given workload (X, utt_off as in

@@ -261,7 +261,8 @@ ivx_status ivx_create(const ivx_dims* dims, int device, ivx_ctx** out) {
     set_error("ivx_create: upload failed");
     return IVX_EDEVICE;
   }
-  if (!frame_set_attributes(c) || !select_set_attributes() || !mstep_set_attributes()) {
+  if (!frame_set_attributes(c) || !select_set_attributes() || !mstep_set_attributes() ||
+      !estep_rr_setup()) {
     ivx_destroy(c);
     set_error("ivx_create: hipFuncSetAttribute failed for a large-LDS kernel");
     return IVX_EDEVICE;

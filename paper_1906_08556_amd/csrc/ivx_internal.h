@@ -234,7 +234,7 @@ struct ivx_ctx {
   int* dev_err = nullptr;     // [4]: see raise_error
 
   // launch shapes picked by the autotuner (ivx_autotune); defaults below
-  ivx_tuning tune = {8, 8, 0, 0, 0};
+  ivx_tuning tune = {8, 8, 0, 0, 0, 0, 0};
 
   // learned Gaussian selection (ivx_selector_set), null until set
   ivx::Selector* sel = nullptr;
@@ -284,6 +284,7 @@ struct NfTarget {
 // ---- k_frame.hip
 bool frame_set_attributes(const ivx_ctx* ctx);
 bool mstep_set_attributes();
+bool estep_rr_setup();
 // Fdev (optional): device frame count, at most F, read by the kernels (the
 // grid is sized for F).  fmap (optional): output row of compact frame i.
 void launch_frame_select(ivx_ctx* ctx, const float* X, int64_t F, int prec, hipStream_t s,

@@ -24,7 +24,8 @@ bool valid_tuning(const ivx_tuning& t) {
   auto ncb_ok = [](int v) { return v == 2 || v == 4 || v == 8; };
   return ncb_ok(t.frame_ncb) && ncb_ok(t.frame_ncb_bf16) &&
          t.b_split >= 0 && t.b_split <= 1024 && (t.frame_direct == 0 || t.frame_direct == 1) &&
-         (t.mstep_left == 0 || t.mstep_left == 1);
+         (t.mstep_left == 0 || t.mstep_left == 1) && (t.estep_global == 0 || t.estep_global == 1) &&
+         (t.mstep_global == 0 || t.mstep_global == 1);
 }
 
 struct Timer {

@@ -158,7 +158,10 @@ __device__ inline int chol_tp64(double* __restrict__ A, int nb, double* __restri
 // Sets *s_bad to 1 + the first row whose pivot was not positive.
 __device__ inline void diag_factor64(double* dg, double* __restrict__ Akk,
                                      double* __restrict__ W, int row0, int* s_bad) {
-  const int lane = threadIdx.x & 63;
+  // the lane-dependent selects below stay inside the call (hoisting them out
+  // of a caller's step loop would hold dozens of scalar masks live)
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
   for (int j = 0; j < 16; ++j) {
     const double piv = dg[j * 16 + j];
     if (!(piv > 0.0) || !isfinite(piv)) {

@@ -75,6 +75,74 @@ k_objective_finish(const double* __restrict__ part, int C, const double* __restr
   if (threadIdx.x == 0) out[0] = s + (ll_sum ? ll_sum[0] : 0.0);
 }
 
+// Sigma_c = sym((S_c - T_c Cc_c^T) / N_c), stored only if it is positive
+// definite (status 0; else status 2 and Sigma_c unchanged).  T_c Cc_c^T runs
+// on MFMA; called by all threads of the workgroup (any multiple of 64, at
+// least D), after T_c has been written.  LDS: big [4096 + D * D].
+__device__ __noinline__ void sigma_update(int c, int D, int R, double Nc, const double* __restrict__ Tc,
+                             const double* __restrict__ Ccc, const double* __restrict__ S,
+                             double* __restrict__ Sigma, double* big, int* s_bad,
+                             int* __restrict__ status) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int l16 = lane & 15, q16 = lane >> 4, nt = blockDim.x;
+  double* Cb = big;          // [64][64] T_c Cc_c^T
+  double* Ms = big + 4096;   // [D][D] candidate
+  for (int t = wave; t < 16; t += nw) {
+    const int ta = t >> 2, tb = t & 3;
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < R; r0 += 16) {
+      acc = mma16_xyt(
+          [&](int i, int l) {
+            const int a = ta * 16 + i, r = r0 + l;
+            return (a < D && r < R) ? Tc[(int64_t)a * R + r] : 0.0;
+          },
+          [&](int j, int l) {
+            const int b = tb * 16 + j, r = r0 + l;
+            return (b < D && r < R) ? Ccc[(int64_t)b * R + r] : 0.0;
+          },
+          acc, 1.0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Cb[(ta * 16 + 4 * r + q16) * 64 + tb * 16 + l16] = acc[r];
+  }
+  __syncthreads();
+  const int Dp = D * (D + 1) / 2;
+  for (int e = tid; e < D * D; e += nt) {
+    const int a = e / D, b = e - a * D;
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    Ms[e] = (S[(int64_t)c * Dp + packed_idx(lo, hi, D)] - 0.5 * (Cb[a * 64 + b] + Cb[b * 64 + a])) / Nc;
+  }
+  __syncthreads();
+  double* Lc = Cb;  // Cholesky scratch, D x D
+  for (int e = tid; e < D * D; e += nt) Lc[e] = Ms[e];
+  if (tid == 0) *s_bad = 0;
+  __syncthreads();
+  for (int j = 0; j < D; ++j) {
+    const double djj = Lc[j * D + j];
+    if (!(djj > 0.0) || !isfinite(djj)) {
+      if (tid == 0) *s_bad = 1;
+      break;
+    }
+    const double ljj = sqrt(djj);
+    __syncthreads();
+    if (tid > j && tid < D) Lc[tid * D + j] /= ljj;
+    if (tid == j) Lc[j * D + j] = ljj;
+    __syncthreads();
+    if (tid > j && tid < D) {
+      const double lij = Lc[tid * D + j];
+      for (int k = j + 1; k <= tid; ++k) Lc[tid * D + k] -= lij * Lc[k * D + j];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (*s_bad) {
+    if (tid == 0) status[c] = 2;
+    return;
+  }
+  for (int e = tid; e < D * D; e += nt) Sigma[(int64_t)c * D * D + e] = Ms[e];
+  if (tid == 0) status[c] = 0;
+}
+
 // One workgroup per component: blocked FP64 Cholesky of A_c on MFMA
 // (chol_tp64), T_c^T = A_c^{-1} Cc_c^T with all D right-hand sides at once
 // (solve_tp64, in place in T_c), then Sigma_c = sym((S_c - T_c Cc_c^T) / N_c)
@@ -122,63 +190,226 @@ k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
     if (tid == 0) status[c] = 0;
     return;
   }
-  // ---- Sigma_c = sym((S_c - T_c Cc_c^T) / N_c), kept if positive definite
-  double* Cb = big;          // [64][64] T_c Cc_c^T
-  double* Ms = big + 4096;   // [D][D] candidate
-  for (int t = wave; t < 16; t += 4) {
-    const int ta = t >> 2, tb = t & 3;
-    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int r0 = 0; r0 < R; r0 += 16) {
-      acc = mma16_xyt(
-          [&](int i, int l) {
-            const int a = ta * 16 + i, r = r0 + l;
-            return (a < D && r < R) ? Tc[(int64_t)a * R + r] : 0.0;
-          },
-          [&](int j, int l) {
-            const int b = tb * 16 + j, r = r0 + l;
-            return (b < D && r < R) ? Ccc[(int64_t)b * R + r] : 0.0;
-          },
-          acc, 1.0);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Cb[(ta * 16 + 4 * r + q16) * 64 + tb * 16 + l16] = acc[r];
-  }
-  __syncthreads();
-  const int Dp = D * (D + 1) / 2;
-  for (int e = tid; e < D * D; e += 256) {
-    const int a = e / D, b = e - a * D;
-    const int lo = a < b ? a : b, hi = a < b ? b : a;
-    Ms[e] = (S[(int64_t)c * Dp + packed_idx(lo, hi, D)] - 0.5 * (Cb[a * 64 + b] + Cb[b * 64 + a])) / Nc;
-  }
-  __syncthreads();
-  double* Lc = Cb;  // Cholesky scratch, D x D
-  for (int e = tid; e < D * D; e += 256) Lc[e] = Ms[e];
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
-  for (int j = 0; j < D; ++j) {
-    const double djj = Lc[j * D + j];
-    if (!(djj > 0.0) || !isfinite(djj)) {
-      if (tid == 0) s_bad = 1;
-      break;
-    }
-    const double ljj = sqrt(djj);
-    __syncthreads();
-    if (tid > j && tid < D) Lc[tid * D + j] /= ljj;
-    if (tid == j) Lc[j * D + j] = ljj;
-    __syncthreads();
-    if (tid > j && tid < D) {
-      const double lij = Lc[tid * D + j];
-      for (int k = j + 1; k <= tid; ++k) Lc[tid * D + k] -= lij * Lc[k * D + j];
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  if (s_bad) {
-    if (tid == 0) status[c] = 2;
+  sigma_update(c, D, R, Nc, Tc, Ccc, S, Sigma, big, &s_bad, status);
+}
+
+// The same M-step with the right-hand sides held in registers, one
+// workgroup of 8 waves per component.  The 64 x R block of right-hand sides
+// B = Cc_c^T (D padded to 64) is split into 16 x 16 tiles; wave w keeps the
+// tiles of column block w % 4 and row blocks i = w / 4 + 2 s (s < 13) as
+// FP64 MFMA fragments.  Block column k of the Cholesky factor is formed
+// left-looking in LDS (A_ik - sum_{j<k} G_ij G_kj^T from the finished
+// columns in device memory), its diagonal tile factored and inverted, the
+// column written once, and the forward-solve step for block row k runs on
+// it while it is still in LDS: Z_k = G_kk^{-1} B_k, B_i -= G_ik Z_k (i > k).
+// The backward solve G^T X = Z then reads each tile of G once.  The
+// right-hand sides never leave the registers between the read of Cc_c and
+// the write of T_c.
+constexpr int MR_NW = 8;
+constexpr int MR_NS = 13;     // right-hand-side slots per wave (nb <= 26)
+constexpr int MR_MAXNB = 25;  // R <= 400
+constexpr size_t MR_LDS_DOUBLES = 2 * MR_MAXNB * 256 + 16 * 64 + 256;
+
+__global__ void __launch_bounds__(MR_NW * 64)
+k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
+           const double* __restrict__ Cc, const double* __restrict__ N,
+           const double* __restrict__ S, int update_sigma, double* __restrict__ T,
+           double* __restrict__ Sigma, int* __restrict__ status, int* __restrict__ err) {
+  extern __shared__ double sm[];
+  double* pan = sm;                     // [nb][256] block column k (tile it = row k + it)
+  double* Wd = sm + MR_MAXNB * 256;     // [nb][256] G_kk^{-1}, row-major
+  double* zb = Wd + MR_MAXNB * 256;     // [16][64] Z_k, then X_k
+  double* dg = zb + 16 * 64;            // [256]
+  __shared__ int s_bad;
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, q16 = lane >> 4;
+  const double Nc = N[c];
+  if (!(Nc >= kMinCount)) {  // no data: keep T_c, Sigma_c
+    if (tid == 0) status[c] = 1;
     return;
   }
-  for (int e = tid; e < D * D; e += 256) Sigma[(int64_t)c * D * D + e] = Ms[e];
-  if (tid == 0) status[c] = 0;
+  double* Ac = A + (int64_t)c * TP;
+  const double* Ccc = Cc + (int64_t)c * D * R;
+  // identity on the padded diagonal so the padding factors trivially
+  for (int d = R + tid; d < nb * 16; d += MR_NW * 64) Ac[tp_off(d >> 4, d >> 4) + (d & 15) * 17] = 1.0;
+  // right-hand sides: slot s = row block ib + 2 s, column block db;
+  // register r = B[16 i + 4 r + q16][16 db + l16] = Cc_c[16 db + l16][16 i + 4 r + q16]
+  const int ib = wave >> 2, db = wave & 3, dcol = 16 * db + l16;
+  doublex4 bt[MR_NS];
+#pragma unroll
+  for (int s = 0; s < MR_NS; ++s) {
+    const int i = ib + 2 * s;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * i + 4 * r + q16;
+      bt[s][r] = (i < nb && row < R && dcol < D) ? Ccc[(int64_t)dcol * R + row] : 0.0;
+    }
+  }
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+
+  const int eo = l16 * 16 + q16;  // element (l16, 4 q + q16) of a row-major tile is at eo + 4 q
+  for (int k = 0; k < nb; ++k) {
+    const int m1 = nb - k;  // tiles of block column k, the diagonal one first
+    // ---- block column k: A_(k+it),k - sum_{j<k} G_(k+it),j G_k,j^T, two
+    //      rows per wave with the next j's tiles requested before the MFMAs
+    for (int it0 = wave; it0 < m1; it0 += 2 * MR_NW) {
+      const int itA = it0, itB = it0 + MR_NW < m1 ? it0 + MR_NW : it0;
+      const double* At = Ac + tp_off(k + itA, k);
+      const double* Bt = Ac + tp_off(k + itB, k);
+      doublex4 accA, accB;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        accA[r] = At[(4 * r + q16) * 16 + l16];
+        accB[r] = Bt[(4 * r + q16) * 16 + l16];
+      }
+      double ck[4], ca[4], cb[4], nk[4], na[4], nb4[4];
+      auto load = [&](int j, double (&gk)[4], double (&ga)[4], double (&gb)[4]) {
+        const double* Gk = Ac + tp_off(k, j);
+        const double* Ga = Ac + tp_off(k + itA, j);
+        const double* Gb = Ac + tp_off(k + itB, j);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          gk[q] = Gk[eo + 4 * q];
+          ga[q] = Ga[eo + 4 * q];
+          gb[q] = Gb[eo + 4 * q];
+        }
+      };
+      if (k > 0) load(0, ck, ca, cb);
+      for (int j = 0; j < k; ++j) {
+        if (j + 1 < k) load(j + 1, nk, na, nb4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ca[q], ck[q], accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-cb[q], ck[q], accB, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ck[q] = nk[q];
+          ca[q] = na[q];
+          cb[q] = nb4[q];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        pan[itA * 256 + (4 * r + q16) * 16 + l16] = accA[r];
+        if (itB != itA) pan[itB * 256 + (4 * r + q16) * 16 + l16] = accB[r];
+      }
+    }
+    __syncthreads();
+    if (wave == 0) {
+      for (int e = lane; e < 256; e += 64) dg[e] = pan[e];
+      __builtin_amdgcn_wave_barrier();
+      diag_factor64(dg, Ac + tp_off(k, k), Wd + k * 256, k * 16, &s_bad);
+    }
+    __syncthreads();
+    if (s_bad) break;
+    const double* W = Wd + k * 256;
+    // ---- panel G_(k+it),k = pan_it W^T (to LDS and device memory), and
+    //      Z_k = W B_k by the owners of row block k
+    for (int it = 1 + wave; it < m1; it += MR_NW) {
+      double* Pt = pan + it * 256;
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16_xyt([&](int i, int l) { return Pt[i * 16 + l]; },
+                      [&](int j, int l) { return W[j * 16 + l]; }, acc, 1.0);
+      __builtin_amdgcn_wave_barrier();  // the tile is read whole before it is replaced
+      double* Gt = Ac + tp_off(k + it, k);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        Gt[(4 * r + q16) * 16 + l16] = acc[r];
+        Pt[(4 * r + q16) * 16 + l16] = acc[r];
+      }
+    }
+    if (ib == (k & 1)) {
+#pragma unroll
+      for (int s = 0; s < MR_NS; ++s) {
+        if (s == (k >> 1)) {
+          doublex4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            z = __builtin_amdgcn_mfma_f64_16x16x4f64(W[l16 * 16 + 4 * q + q16], bt[s][q], z, 0, 0, 0);
+          bt[s] = z;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) zb[(4 * r + q16) * 64 + dcol] = z[r];
+        }
+      }
+    }
+    __syncthreads();
+    // ---- B_i -= G_ik Z_k for i > k
+#pragma unroll
+    for (int s = 0; s < MR_NS; ++s) {
+      const int i = ib + 2 * s;
+      if (i > k && i < nb) {
+        const double* Gt = pan + (i - k) * 256;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          bt[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-Gt[eo + 4 * q], zb[(4 * q + q16) * 64 + dcol],
+                                                       bt[s], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  if (s_bad) {
+    if (tid == 0) {
+      status[c] = 3;
+      raise_error(err, IVX_ENOTPD, PK_MSTEP, c);
+    }
+    return;
+  }
+  // ---- backward solve G^T X = Z: X_k = W_k^T Z_k, then Z_i -= G_ki^T X_k (i < k)
+  for (int k = nb - 1; k >= 0; --k) {
+    const double* W = Wd + k * 256;
+    if (ib == (k & 1)) {
+#pragma unroll
+      for (int s = 0; s < MR_NS; ++s) {
+        if (s == (k >> 1)) {
+          doublex4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            x = __builtin_amdgcn_mfma_f64_16x16x4f64(W[(4 * q + q16) * 16 + l16], bt[s][q], x, 0, 0, 0);
+          bt[s] = x;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) zb[(4 * r + q16) * 64 + dcol] = x[r];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < MR_NS; ++s) {
+      const int i = ib + 2 * s;
+      if (i < k) {
+        const double* Gt = Ac + tp_off(k, i);
+        double g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = Gt[(4 * q + q16) * 16 + l16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          bt[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-g[q], zb[(4 * q + q16) * 64 + dcol], bt[s],
+                                                       0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // ---- T_c[d][r] = X[r][d]
+  double* Tc = T + (int64_t)c * D * R;
+  if (dcol < D) {
+#pragma unroll
+    for (int s = 0; s < MR_NS; ++s) {
+      const int i = ib + 2 * s;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * i + 4 * r + q16;
+        if (i < nb && row < R) Tc[(int64_t)dcol * R + row] = bt[s][r];
+      }
+    }
+  }
+  if (!update_sigma) {
+    if (tid == 0) status[c] = 0;
+    return;
+  }
+  __syncthreads();
+  sigma_update(c, D, R, Nc, Tc, Ccc, S, Sigma, sm, &s_bad, status);
 }
 
 // Minimum-divergence set-up, one workgroup of 256 threads:
@@ -396,7 +627,10 @@ size_t mstep_lds_bytes(int R, int D);
 bool mstep_set_attributes() {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mstep_solve),
                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)mstep_lds_bytes(480, 63)) == hipSuccess;
+                             (int)mstep_lds_bytes(480, 63)) == hipSuccess &&
+         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mstep_rr),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(MR_LDS_DOUBLES * sizeof(double))) == hipSuccess;
 }
 
 size_t mstep_lds_bytes(int R, int D) {
@@ -409,6 +643,12 @@ size_t mstep_lds_bytes(int R, int D) {
 void launch_mstep_solve(ivx_ctx* ctx, const ivx_accum* acc, const double* S, int update_sigma,
                         int* status, hipStream_t s) {
   const int nb = (ctx->R + 15) / 16;
+  if (!ctx->tune.mstep_global && nb <= MR_MAXNB) {
+    k_mstep_rr<<<ctx->C, MR_NW * 64, MR_LDS_DOUBLES * sizeof(double), s>>>(
+        ctx->C, ctx->D, ctx->R, nb, ctx->TP, acc->A, acc->Cc, acc->N, S, update_sigma, ctx->T,
+        ctx->Sigma, status, ctx->dev_err);
+    return;
+  }
   k_mstep_solve<<<ctx->C, 256, mstep_lds_bytes(ctx->R, ctx->D), s>>>(
       ctx->C, ctx->D, ctx->R, nb, ctx->TP, acc->A, acc->Cc, acc->N, S, update_sigma, ctx->T,
       ctx->Sigma, ctx->Winv, status, ctx->dev_err, ctx->tune.mstep_left);

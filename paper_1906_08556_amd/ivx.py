@@ -45,7 +45,8 @@ class SelectorDims(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("frame_ncb", ctypes.c_int32), ("frame_ncb_bf16", ctypes.c_int32),
                 ("b_split", ctypes.c_int32), ("frame_direct", ctypes.c_int32),
-                ("mstep_left", ctypes.c_int32)]
+                ("mstep_left", ctypes.c_int32),
+                ("estep_global", ctypes.c_int32), ("mstep_global", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

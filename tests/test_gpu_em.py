@@ -23,6 +23,7 @@ import torch
 import oracle
 import synth
 from _gpu_helpers import dev, make_ctx, packed_upper, unpack_tp, unpack_upper
+from paper_1906_08556_amd import ivx
 
 pytestmark = pytest.mark.gpu
 
@@ -131,6 +132,71 @@ def test_estep_matches_oracle_full_shape_subset():
     _check_estep(wl, n, f, tv)
 
 
+@pytest.mark.parametrize("estep_global", [0, 1])
+@pytest.mark.parametrize("R", [32, 45, 400])
+def test_estep_factorisations_match_oracle(R, estep_global):
+    """Both forms of the per-utterance factorisation (eqs. (3)-(4)): the
+    precision matrix held in the registers of one workgroup (estep_global 0)
+    and worked on tile by tile in device memory (1), for R a multiple of the
+    16-wide tile, a ragged R (padding tiles) and the full R = 400 with the
+    full model shape (D 60, C 2048)."""
+    if R == 400:
+        wl = synth.make(2, n_utts=6)
+    else:
+        wl = synth.make(1, R=R, U=24)
+    gamma, _ = oracle.posteriors(oracle.frame_loglik(wl.X, wl.w, wl.mu, wl.cov))
+    n, f, _ = oracle.bw_stats(wl.X, wl.utt_off, gamma, second_order=False)
+    tv = oracle.init_tv(wl.mu, wl.cov, wl.T_init)
+    n32, f32 = n.astype(np.float32), f.astype(np.float32)
+    ctx = _ctx_tv(wl, tv)
+    ctx.tuning_set(estep_global=estep_global)
+    phi, Phi, ll, info = _estep_gpu(ctx, n32, f32)
+    e = oracle.estep(n32.astype(np.float64), f32.astype(np.float64), *tv)
+    cos = cosines(phi, e["phi"])
+    rel = np.max(np.abs(phi - e["phi"]) / np.abs(e["phi"]).max(1, keepdims=True))
+    Phi_full = unpack_upper(Phi, R)
+    rphi = max(relfro(Phi_full[u], e["Phi"][u]) for u in range(len(phi)))
+    llrel = abs(ll - e["ll_u"].sum()) / abs(e["ll_u"].sum())
+    print(f"R={R} estep_global={estep_global}: min cos {cos.min():.9f} max rel {rel:.2e} "
+          f"Phi relfro {rphi:.2e} ll rel {llrel:.2e}")
+    assert np.all(info == 0)
+    assert cos.min() >= 0.9999
+    assert rel <= 2e-3
+    assert rphi <= 2e-3
+    assert llrel <= 1e-5
+    # extraction-only call (no covariance output) gives the same i-vectors
+    phi2, _, _, _ = _estep_gpu(ctx, n32, f32, want_cov=False)
+    np.testing.assert_array_equal(phi2, phi)
+
+
+@pytest.mark.parametrize("estep_global", [0, 1])
+def test_estep_reports_a_precision_that_is_not_positive_definite(cfg1, estep_global):
+    """Negative occupancies make I + sum_c n_c U_c indefinite: the utterance's
+    info holds the 1-based index of the failing pivot, its i-vector is NaN and
+    the call reports IVX_ENOTPD; the other utterances are unaffected."""
+    wl, n, f, S, tv = cfg1
+    ctx = _ctx_tv(wl, tv)
+    ctx.tuning_set(estep_global=estep_global)
+    n32 = n[:4].astype(np.float32).copy()
+    f32 = f[:4].astype(np.float32)
+    n32[2] = -50.0 * np.abs(n32[2]) - 50.0
+    U, R = 4, wl.shape.R
+    phi = torch.empty((U, R), dtype=torch.float32, device="cuda")
+    info = torch.empty(U, dtype=torch.int32, device="cuda")
+    ctx.tv_estep(dev(n32), dev(f32), phi, info=info)
+    with pytest.raises(ivx.IvxError) as ei:
+        ctx.sync_status()
+    assert ei.value.status == -3
+    inf = info.cpu().numpy()
+    ph = phi.cpu().numpy()
+    assert inf[2] >= 1 and inf[2] <= R
+    assert np.all(np.isnan(ph[2]))
+    ok = [0, 1, 3]
+    assert np.all(inf[ok] == 0)
+    e = oracle.estep(n32[ok].astype(np.float64), f32[ok].astype(np.float64), *tv)
+    assert cosines(ph[ok], e["phi"]).min() >= 0.9999
+
+
 def test_estep_empty_utterance_gives_the_prior(cfg1):
     wl, n, f, S, tv = cfg1
     ctx = _ctx_tv(wl, tv)
@@ -199,11 +265,16 @@ def _accum_from_oracle(ctx, ref):
     return acc
 
 
-@pytest.mark.parametrize("left", [0, 1], ids=["right-looking", "left-looking"])
-def test_mstep_solve_and_objective_match_oracle(cfg1, left):
+MSTEP_FORMS = {"registers": dict(mstep_global=0),
+               "right-looking": dict(mstep_global=1, mstep_left=0),
+               "left-looking": dict(mstep_global=1, mstep_left=1)}
+
+
+@pytest.mark.parametrize("form", list(MSTEP_FORMS))
+def test_mstep_solve_and_objective_match_oracle(cfg1, form):
     wl, n, f, S, tv = cfg1
     ctx = _ctx_tv(wl, tv)
-    ctx.tuning_set(mstep_left=left)
+    ctx.tuning_set(**MSTEP_FORMS[form])
     e = oracle.estep(n, f, *tv)
     ref = oracle.accumulate(n, f, e["phi"], e["Phi"])
     acc = _accum_from_oracle(ctx, ref)
@@ -222,6 +293,66 @@ def test_mstep_solve_and_objective_match_oracle(cfg1, left):
     assert relfro(Sg, S1) <= 1e-9
     obj_ref = oracle.objective(ref["N"], S, tv[1], e["ll_u"].sum())
     assert abs(obj.item() - obj_ref) <= 1e-9 * abs(obj_ref)
+
+
+@pytest.mark.parametrize("form", list(MSTEP_FORMS))
+@pytest.mark.parametrize("R", [45, 400])
+def test_mstep_solve_forms_match_oracle_at_larger_R(R, form):
+    """The M-step solve T_c = Cc_c A_c^{-1} and the Sigma_c update (FP64 on
+    both sides, same accumulators) for a ragged R (3 block steps) and the full
+    R = 400 (25 block steps), in every form."""
+    wl = synth.make(1, R=R, U=24)
+    gamma, _ = oracle.posteriors(oracle.frame_loglik(wl.X, wl.w, wl.mu, wl.cov))
+    n, f, S = oracle.bw_stats(wl.X, wl.utt_off, gamma)
+    tv = oracle.init_tv(wl.mu, wl.cov, wl.T_init)
+    ctx = _ctx_tv(wl, tv)
+    ctx.tuning_set(**MSTEP_FORMS[form])
+    e = oracle.estep(n, f, *tv)
+    ref = oracle.accumulate(n, f, e["phi"], e["Phi"])
+    acc = _accum_from_oracle(ctx, ref)
+    status = torch.empty(wl.shape.C, dtype=torch.int32, device="cuda")
+    ctx.tv_mstep_solve(acc, dev(packed_upper(S)), update_sigma=True, status=status)
+    ctx.sync_status()
+    T1, S1, info = oracle.mstep(ref, S, tv[0], tv[1], update_sigma=True)
+    Tg, Sg, _, _ = [t.cpu().numpy() for t in ctx.get_tv()]
+    st = status.cpu().numpy()
+    print(f"R={R} {form}: T relfro {relfro(Tg, T1):.2e} Sigma relfro {relfro(Sg, S1):.2e} "
+          f"skipped {info['skipped']} not PD {info['notpd']}")
+    assert sorted(np.nonzero(st == 1)[0].tolist()) == info["skipped"]
+    assert sorted(np.nonzero(st == 2)[0].tolist()) == info["notpd"]
+    assert relfro(Tg, T1) <= 1e-9
+    assert relfro(Sg, S1) <= 1e-9
+
+
+@pytest.mark.parametrize("form", list(MSTEP_FORMS))
+def test_mstep_reports_an_accumulator_that_is_not_positive_definite(cfg1, form):
+    """A_c made indefinite for one component: that component keeps T_c and
+    Sigma_c (status 3) and the call reports IVX_ENOTPD; the others match the
+    oracle."""
+    wl, n, f, S, tv = cfg1
+    ctx = _ctx_tv(wl, tv)
+    ctx.tuning_set(**MSTEP_FORMS[form])
+    e = oracle.estep(n, f, *tv)
+    ref = oracle.accumulate(n, f, e["phi"], e["Phi"])
+    bad = 5
+    A_ok = ref["A"]
+    ref = dict(ref, A=A_ok.copy())
+    ref["A"][bad] = -A_ok[bad]
+    acc = _accum_from_oracle(ctx, ref)
+    status = torch.empty(wl.shape.C, dtype=torch.int32, device="cuda")
+    ctx.tv_mstep_solve(acc, dev(packed_upper(S)), update_sigma=True, status=status)
+    with pytest.raises(ivx.IvxError) as ei:
+        ctx.sync_status()
+    assert ei.value.status == -3
+    st = status.cpu().numpy()
+    assert st[bad] == 3
+    Tg, Sg, _, _ = [t.cpu().numpy() for t in ctx.get_tv()]
+    np.testing.assert_array_equal(Tg[bad], tv[0][bad])
+    np.testing.assert_array_equal(Sg[bad], tv[1][bad])
+    good = np.ones(wl.shape.C, bool)
+    good[bad] = False
+    T1, S1, info = oracle.mstep(dict(ref, A=A_ok), S, tv[0], tv[1], update_sigma=True)
+    assert relfro(Tg[good], T1[good]) <= 1e-9
 
 
 def test_mindiv_matches_oracle(cfg1):
@@ -439,10 +570,12 @@ def test_em_iteration_full_shape_matches_oracle(full_shape):
 
 
 @pytest.mark.timeout(900)
-def test_em_iteration_full_shape_left_looking_mstep(full_shape):
-    """The M-step with the left-looking Cholesky of A_c (tuning field
-    mstep_left) meets the same bounds at the full model shape."""
-    e = _full_shape_iteration(*full_shape, prec=0, mstep_left=1)
+def test_em_iteration_full_shape_device_memory_factorisations(full_shape):
+    """The factorisations that work on their matrices in device memory (the
+    per-utterance E-step tile by tile, the M-step with the left-looking
+    Cholesky of A_c and the right-hand sides in device memory) meet the same
+    bounds at the full model shape."""
+    e = _full_shape_iteration(*full_shape, prec=0, estep_global=1, mstep_global=1, mstep_left=1)
     assert e["cos"] >= 0.9999
     assert e["obj"] <= 1e-6
     assert e["t_max"] <= 1e-3
