@@ -146,10 +146,9 @@ ivx_status estep_impl(ivx_ctx* ctx, const float* n, const float* f, int64_t U, i
   prof_end(ctx, slot, s);
   {
     ProfScope ps(ctx, PK_ESTEP_CHOL, s);
-    launch_estep_chol(ctx, U, ctx->Lbuf, ctx->Wbuf, ctx->bvec, phi, ctx->llu, info, Phi != nullptr, s);
+    launch_estep_chol(ctx, U, ctx->Lbuf, ctx->Wbuf, ctx->bvec, phi, ctx->llu, info, Phi, s);
   }
   if (ll_acc) launch_sum_f64(ctx, ctx->llu, U, ll_acc, s);
-  if (Phi) launch_tp_to_packed(ctx, ctx->Lbuf, U, Phi, s);
   return after_launch("tv_estep");
 }
 

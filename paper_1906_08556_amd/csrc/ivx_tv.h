@@ -10,13 +10,15 @@ void launch_tv_prep(ivx_ctx* ctx, hipStream_t s);
 void launch_add_identity(ivx_ctx* ctx, float* L, int64_t U, hipStream_t s);
 void launch_reduce_b(ivx_ctx* ctx, const float* part, int nsplit, int64_t sstride, int64_t U,
                      float* b, hipStream_t s);
+// Phi (packed upper, may be null: no covariance wanted) is written here
+// whichever form runs.
 void launch_estep_chol(ivx_ctx* ctx, int64_t U, float* Lb, float* Wb, const float* b, float* phi,
-                       double* llu, int* info, bool want_cov, hipStream_t s);
+                       double* llu, int* info, float* Phi, hipStream_t s);
 // k_estep_rr.hip: the same operation with the matrix held in registers
 bool estep_rr_fits(int R);
 bool estep_rr_setup();
-void launch_estep_rr(ivx_ctx* ctx, int64_t U, float* Lb, const float* b, float* phi, double* llu,
-                     int* info, bool want_cov, hipStream_t s);
+void launch_estep_rr(ivx_ctx* ctx, int64_t U, const float* Lb, const float* b, float* phi,
+                     double* llu, int* info, float* Phi_packed, hipStream_t s);
 void launch_tp_to_packed(ivx_ctx* ctx, const float* Ptp, int64_t U, float* out, hipStream_t s);
 void launch_packed_to_psi(ivx_ctx* ctx, const float* Phi, const float* phi, int64_t U, double* Psi,
                           hipStream_t s);

@@ -2,11 +2,13 @@
 //
 // One workgroup of 8 waves per utterance.  The lower 16 x 16 tiles of the
 // tile-packed precision matrix L(u) (R <= 400: at most 325 tiles, 333 KB in
-// FP32) are distributed over the register files of the 8 waves: tile t
+// FP32; read, not modified) are distributed over the register files of the
+// 8 waves: tile t
 // (t = bi (bi + 1) / 2 + bj) lives in slot t / 8 of wave t % 8, as the
 // accumulator fragment of v_mfma_f32_16x16x4_f32 (lane l holds rows
 // 4 (l / 16) .. 4 (l / 16) + 3 of column l % 16).  L(u) is read once and
-// Phi(u) written once; every intermediate stays in registers, and block rows or
+// Phi(u) written once, straight into the packed upper triangle of the
+// caller's output; every intermediate stays in registers, and block rows or
 // columns that other waves need are exchanged through LDS:
 //
 //   1. blocked Cholesky L = G G^T, right-looking: the diagonal tile of the
@@ -18,7 +20,7 @@
 //   3. Phi = W^T W, one block row of W at a time: Phi_ij += W_ki^T W_kj;
 //   4. phi = Phi b (per-tile partial products summed in a fixed order),
 //      log|L(u)| from the diagonal of G, the utterance's objective share,
-//      and Phi written back over L(u).
+//      and Phi (when wanted) in the packed upper layout.
 //
 // The tile layout in registers changes between phases: in phase 1 a slot
 // holds the fragment of the transposed tile (which lets the panel product
@@ -169,9 +171,9 @@ __device__ __forceinline__ int first_slot(int w, int T) {
 }
 
 __global__ void __launch_bounds__(RR_NW * 64)
-k_estep_rr(int R, int nb, int64_t TP, float* __restrict__ Lb, const float* __restrict__ bvec,
+k_estep_rr(int R, int nb, int64_t TP, const float* __restrict__ Lb, const float* __restrict__ bvec,
            const double* __restrict__ p, float* __restrict__ phi, double* __restrict__ llu,
-           int* __restrict__ info, int want_cov, int* __restrict__ err) {
+           int* __restrict__ info, float* __restrict__ Phi_out, int* __restrict__ err) {
   extern __shared__ float sm[];
   float* dinv = sm + RR_OFF_DINV;
   float* buf = sm + RR_OFF_BUF;
@@ -183,7 +185,7 @@ k_estep_rr(int R, int nb, int64_t TP, float* __restrict__ Lb, const float* __res
   const int l16 = lane & 15, q16 = lane >> 4;
   float* scr = sm + RR_OFF_SCR + wave * 272;
   const int64_t u = blockIdx.x;
-  float* L = Lb + u * TP;
+  const float* L = Lb + u * TP;
   // fragment offsets: "row l16, columns 4 q16 .. 4 q16 + 3" of a swizzled tile
   const int frag = swz(l16, 4 * q16);
 
@@ -413,7 +415,18 @@ _Pragma("unroll")
           for (int r = 0; r < 4; ++r) part[t * 32 + 16 + 4 * q16 + r] = c[r];
         }
       }
-      if (want_cov) st4(L + tile_off(ti, tj) + l16 * 16 + 4 * q16, v);
+      if (Phi_out) {
+        // element (a, c) of the lower tile is (c, a) of the packed upper
+        // triangle, row c at c R - c (c - 1) / 2; lanes along a write
+        // consecutive words of one packed row
+        const int a = 16 * ti + l16;
+        float* out = Phi_out + u * ((int64_t)R * (R + 1) / 2);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = 16 * tj + 4 * q16 + r;
+          if (a < R && c <= a) out[(int64_t)c * R - (int64_t)c * (c - 1) / 2 + (a - c)] = v[r];
+        }
+      }
     }
   }
   __syncthreads();
@@ -451,12 +464,12 @@ bool estep_rr_setup() {
                              (int)RR_LDS_BYTES) == hipSuccess;
 }
 
-void launch_estep_rr(ivx_ctx* ctx, int64_t U, float* Lb, const float* b, float* phi, double* llu,
-                     int* info, bool want_cov, hipStream_t s) {
+void launch_estep_rr(ivx_ctx* ctx, int64_t U, const float* Lb, const float* b, float* phi,
+                     double* llu, int* info, float* Phi_packed, hipStream_t s) {
   if (U <= 0) return;
   const int nb = (ctx->R + 15) / 16;
   k_estep_rr<<<(unsigned)U, RR_NW * 64, RR_LDS_BYTES, s>>>(ctx->R, nb, ctx->TP, Lb, b, ctx->p, phi,
-                                                          llu, info, want_cov ? 1 : 0, ctx->dev_err);
+                                                          llu, info, Phi_packed, ctx->dev_err);
 }
 
 }  // namespace ivx

@@ -570,15 +570,16 @@ void launch_reduce_b(ivx_ctx* ctx, const float* part, int nsplit, int64_t sstrid
 }
 
 void launch_estep_chol(ivx_ctx* ctx, int64_t U, float* Lb, float* Wb, const float* b, float* phi,
-                       double* llu, int* info, bool want_cov, hipStream_t s) {
+                       double* llu, int* info, float* Phi, hipStream_t s) {
   if (U <= 0) return;
   if (!ctx->tune.estep_global && estep_rr_fits(ctx->R)) {
-    launch_estep_rr(ctx, U, Lb, b, phi, llu, info, want_cov, s);
+    launch_estep_rr(ctx, U, Lb, b, phi, llu, info, Phi, s);
     return;
   }
   const int nb = (ctx->R + 15) / 16;
   k_estep_chol<<<(unsigned)U, 256, 0, s>>>(ctx->R, nb, ctx->TP, Lb, Wb, b, ctx->p, phi, llu, info,
-                                           want_cov ? 1 : 0, ctx->dev_err);
+                                           Phi != nullptr ? 1 : 0, ctx->dev_err);
+  if (Phi) launch_tp_to_packed(ctx, Lb, U, Phi, s);
 }
 
 void launch_tp_to_packed(ivx_ctx* ctx, const float* Ptp, int64_t U, float* out, hipStream_t s) {
