@@ -208,7 +208,7 @@ k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
 constexpr int MR_NW = 8;
 constexpr int MR_NS = 13;     // right-hand-side slots per wave (nb <= 26)
 constexpr int MR_MAXNB = 25;  // R <= 400
-constexpr size_t MR_LDS_DOUBLES = 2 * MR_MAXNB * 256 + 16 * 64 + 256;
+constexpr size_t MR_LDS_DOUBLES = 2 * MR_MAXNB * 256 + 16 * 64 + 256 + (MR_MAXNB - 1) * 256;
 
 __global__ void __launch_bounds__(MR_NW * 64)
 k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
@@ -220,6 +220,7 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
   double* Wd = sm + MR_MAXNB * 256;     // [nb][256] G_kk^{-1}, row-major
   double* zb = Wd + MR_MAXNB * 256;     // [16][64] Z_k, then X_k
   double* dg = zb + 16 * 64;            // [256]
+  double* rowk = dg + 256;              // [nb - 1][256] block row k of G
   __shared__ int s_bad;
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -252,8 +253,19 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
   const int eo = l16 * 16 + q16;  // element (l16, 4 q + q16) of a row-major tile is at eo + 4 q
   for (int k = 0; k < nb; ++k) {
     const int m1 = nb - k;  // tiles of block column k, the diagonal one first
-    // ---- block column k: A_(k+it),k - sum_{j<k} G_(k+it),j G_k,j^T, two
-    //      rows per wave with the next j's tiles requested before the MFMAs
+    // ---- block column k: A_(k+it),k - sum_{j<k} G_(k+it),j G_k,j^T.  Block
+    //      row k of G (shared by every row's sum) is staged in LDS first; each
+    //      wave takes two rows and keeps the tiles of the next three j in
+    //      flight while it multiplies the current one (contraction index
+    //      4 q16 + q: lane (l16, q16) reads four consecutive doubles of row
+    //      l16 of a tile)
+    for (int e = tid; e < k * 128; e += MR_NW * 64) {
+      const int j = e >> 7, w = e & 127;
+      reinterpret_cast<double2*>(rowk + j * 256)[w] =
+          reinterpret_cast<const double2*>(Ac + tp_off(k, j))[w];
+    }
+    __syncthreads();
+    const int ro = l16 * 16 + 4 * q16;
     for (int it0 = wave; it0 < m1; it0 += 2 * MR_NW) {
       const int itA = it0, itB = it0 + MR_NW < m1 ? it0 + MR_NW : it0;
       const double* At = Ac + tp_off(k + itA, k);
@@ -264,31 +276,40 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
         accA[r] = At[(4 * r + q16) * 16 + l16];
         accB[r] = Bt[(4 * r + q16) * 16 + l16];
       }
-      double ck[4], ca[4], cb[4], nk[4], na[4], nb4[4];
-      auto load = [&](int j, double (&gk)[4], double (&ga)[4], double (&gb)[4]) {
-        const double* Gk = Ac + tp_off(k, j);
-        const double* Ga = Ac + tp_off(k + itA, j);
-        const double* Gb = Ac + tp_off(k + itB, j);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          gk[q] = Gk[eo + 4 * q];
-          ga[q] = Ga[eo + 4 * q];
-          gb[q] = Gb[eo + 4 * q];
-        }
+      double2 a0[2], b0[2], a1[2], b1[2], a2[2], b2[2];
+      auto load = [&](int j, double2 (&ga)[2], double2 (&gb)[2]) {
+        const double2* Ga = reinterpret_cast<const double2*>(Ac + tp_off(k + itA, j) + ro);
+        const double2* Gb = reinterpret_cast<const double2*>(Ac + tp_off(k + itB, j) + ro);
+        ga[0] = Ga[0];
+        ga[1] = Ga[1];
+        gb[0] = Gb[0];
+        gb[1] = Gb[1];
       };
-      if (k > 0) load(0, ck, ca, cb);
-      for (int j = 0; j < k; ++j) {
-        if (j + 1 < k) load(j + 1, nk, na, nb4);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ca[q], ck[q], accA, 0, 0, 0);
-          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-cb[q], ck[q], accB, 0, 0, 0);
+      auto step = [&](int j, const double2 (&ga)[2], const double2 (&gb)[2]) {
+        const double2* Kr = reinterpret_cast<const double2*>(rowk + j * 256 + ro);
+        const double2 k0 = Kr[0], k1 = Kr[1];
+        accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[0].x, k0.x, accA, 0, 0, 0);
+        accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[0].x, k0.x, accB, 0, 0, 0);
+        accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[0].y, k0.y, accA, 0, 0, 0);
+        accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[0].y, k0.y, accB, 0, 0, 0);
+        accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[1].x, k1.x, accA, 0, 0, 0);
+        accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[1].x, k1.x, accB, 0, 0, 0);
+        accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[1].y, k1.y, accA, 0, 0, 0);
+        accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[1].y, k1.y, accB, 0, 0, 0);
+      };
+      if (k > 0) load(0, a0, b0);
+      if (k > 1) load(1, a1, b1);
+      if (k > 2) load(2, a2, b2);
+      for (int j = 0; j < k; j += 3) {
+        step(j, a0, b0);
+        if (j + 3 < k) load(j + 3, a0, b0);
+        if (j + 1 < k) {
+          step(j + 1, a1, b1);
+          if (j + 4 < k) load(j + 4, a1, b1);
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          ck[q] = nk[q];
-          ca[q] = na[q];
-          cb[q] = nb4[q];
+        if (j + 2 < k) {
+          step(j + 2, a2, b2);
+          if (j + 5 < k) load(j + 5, a2, b2);
         }
       }
 #pragma unroll
