@@ -153,52 +153,97 @@ __device__ inline int chol_tp64(double* __restrict__ A, int nb, double* __restri
   return 0;
 }
 
-// Factors the diagonal tile held in dg [256] (lower part used) by wave 0:
-// G_kk to dg and to Akk, W_kk = G_kk^{-1} (row-major, upper part zero) to W.
-// Sets *s_bad to 1 + the first row whose pivot was not positive.
-__device__ inline void diag_factor64(double* dg, double* __restrict__ Akk,
+// Lane-crossing moves of one FP64 value (two 32-bit halves each).
+__device__ inline double lane_read64(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// value of lane `src` (byte address 4 src)
+__device__ inline double lane_perm64(int src4, double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src4, (int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src4, (int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// value of lane J of the lane's own 16-lane row (DPP row_newbcast:J)
+template <int J>
+__device__ inline double row_bcast64(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x150 + J, 0xf, 0xf, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x150 + J, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Factors the diagonal tile held in dg [256] (lower part used) in the
+// registers of one wave: G_kk (upper part zero) to Akk and W_kk = G_kk^{-1}
+// (row-major, upper part zero) to W.  Lane (c, q) = (lane % 16, lane / 16)
+// holds rows 4 r + q (r < 4) of column c of the symmetric trailing matrix
+// and of X, the right-hand side of G W = I being reduced alongside.  Step j
+// of the right-looking elimination takes the pivot with a lane read,
+// 1 / G_jj = rsqrt(pivot) by two Newton steps from the hardware estimate,
+// the column-j entries of the lane's own rows with a broadcast inside each
+// 16-lane row, and row j (of the trailing matrix and of X) with a permute
+// from the row group that holds it; row j of W is then final and stored.
+// Rows above the step hold values that are never read again.  Sets *s_bad
+// to 1 + the first row whose pivot was not positive.
+__device__ inline void diag_factor64(const double* dg, double* __restrict__ Akk,
                                      double* __restrict__ W, int row0, int* s_bad) {
   // the lane-dependent selects below stay inside the call (hoisting them out
   // of a caller's step loop would hold dozens of scalar masks live)
   int lane = threadIdx.x & 63;
   asm volatile("" : "+v"(lane));
-  for (int j = 0; j < 16; ++j) {
-    const double piv = dg[j * 16 + j];
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      if (lane == 0) *s_bad = row0 + j + 1;
-      break;  // piv is the same in every lane: uniform exit
-    }
-    const double ljj = sqrt(piv);
-    __builtin_amdgcn_wave_barrier();
-    if (lane > j && lane < 16) dg[lane * 16 + j] /= ljj;
-    if (lane == j) dg[j * 16 + j] = ljj;
-    __builtin_amdgcn_wave_barrier();
-    for (int e = lane; e < 256; e += 64) {
-      const int i = e >> 4, c = e & 15;
-      if (c > j && i >= c) dg[e] -= dg[i * 16 + j] * dg[c * 16 + j];
-    }
-    __builtin_amdgcn_wave_barrier();
+  const int c = lane & 15, q = lane >> 4;
+  double a[4], x[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = 4 * r + q;
+    a[r] = dg[c <= i ? i * 16 + c : c * 16 + i];
+    x[r] = i == c ? 1.0 : 0.0;
   }
-  for (int e = lane; e < 256; e += 64) {
-    const int i = e >> 4, c = e & 15;
-    const double v = (c <= i) ? dg[e] : 0.0;
-    dg[e] = v;
-    Akk[e] = v;
+  double my_rinv = 0.0;  // 1 / G_cc
+  int bad = 0;
+#define IVX_DF64_STEP(j)                                                            \
+  {                                                                                 \
+    const double piv = lane_read64(a[(j) >> 2], 16 * ((j) & 3) + (j));              \
+    if (!(piv > 0.0) || !isfinite(piv)) {                                           \
+      bad = (j) + 1;                                                                \
+      goto done;                                                                    \
+    }                                                                               \
+    double ri = __builtin_amdgcn_rsq(piv);                                          \
+    ri = fma(0.5 * ri, fma(-piv * ri, ri, 1.0), ri);                                \
+    ri = fma(0.5 * ri, fma(-piv * ri, ri, 1.0), ri);                                \
+    const double ri2 = ri * ri;                                                     \
+    my_rinv = c == (j) ? ri : my_rinv;                                              \
+    const int src4 = (16 * ((j) & 3) + c) * 4;                                      \
+    const double ajc = lane_perm64(src4, a[(j) >> 2]);                              \
+    const double xjc = lane_perm64(src4, x[(j) >> 2]);                              \
+    if (q == ((j) & 3)) W[(j) * 16 + c] = x[(j) >> 2] * ri;                         \
+    const double t = c > (j) ? ajc * ri2 : 0.0;                                     \
+    const double u = xjc * ri2;                                                     \
+    _Pragma("unroll") for (int r = 0; r < 4; ++r) {                                 \
+      const double d = row_bcast64<(j)>(a[r]);                                      \
+      a[r] = fma(-d, t, a[r]);                                                      \
+      x[r] = fma(-d, u, x[r]);                                                      \
+    }                                                                               \
   }
-  __builtin_amdgcn_wave_barrier();
-  if (lane < 16 && *s_bad == 0) {
-    const int j = lane;
-    double w[16];
+  IVX_DF64_STEP(0) IVX_DF64_STEP(1) IVX_DF64_STEP(2) IVX_DF64_STEP(3)
+  IVX_DF64_STEP(4) IVX_DF64_STEP(5) IVX_DF64_STEP(6) IVX_DF64_STEP(7)
+  IVX_DF64_STEP(8) IVX_DF64_STEP(9) IVX_DF64_STEP(10) IVX_DF64_STEP(11)
+  IVX_DF64_STEP(12) IVX_DF64_STEP(13) IVX_DF64_STEP(14) IVX_DF64_STEP(15)
+#undef IVX_DF64_STEP
+done:
+  if (bad) {
+    if (lane == 0) *s_bad = row0 + bad;
+    return;
+  }
+  // column c of the trailing matrix at step c is G_ic G_cc for i >= c
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      double s = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-      for (int l = 0; l < i; ++l) s -= dg[i * 16 + l] * w[l];
-      w[i] = (i >= j) ? s / dg[i * 16 + i] : 0.0;
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) W[i * 16 + j] = w[i];
+  for (int r = 0; r < 4; ++r) {
+    const int i = 4 * r + q;
+    Akk[i * 16 + c] = i >= c ? a[r] * my_rinv : 0.0;
   }
 }
 

@@ -208,7 +208,7 @@ k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
 constexpr int MR_NW = 8;
 constexpr int MR_NS = 13;     // right-hand-side slots per wave (nb <= 26)
 constexpr int MR_MAXNB = 25;  // R <= 400
-constexpr size_t MR_LDS_DOUBLES = 2 * MR_MAXNB * 256 + 16 * 64 + 256 + (MR_MAXNB - 1) * 256;
+constexpr size_t MR_LDS_DOUBLES = 2 * MR_MAXNB * 256 + 16 * 64 + (MR_MAXNB - 1) * 256;
 
 __global__ void __launch_bounds__(MR_NW * 64)
 k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
@@ -219,8 +219,7 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
   double* pan = sm;                     // [nb][256] block column k (tile it = row k + it)
   double* Wd = sm + MR_MAXNB * 256;     // [nb][256] G_kk^{-1}, row-major
   double* zb = Wd + MR_MAXNB * 256;     // [16][64] Z_k, then X_k
-  double* dg = zb + 16 * 64;            // [256]
-  double* rowk = dg + 256;              // [nb - 1][256] block row k of G
+  double* rowk = zb + 16 * 64;          // [nb - 1][256] block row k of G
   __shared__ int s_bad;
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -319,11 +318,7 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
       }
     }
     __syncthreads();
-    if (wave == 0) {
-      for (int e = lane; e < 256; e += 64) dg[e] = pan[e];
-      __builtin_amdgcn_wave_barrier();
-      diag_factor64(dg, Ac + tp_off(k, k), Wd + k * 256, k * 16, &s_bad);
-    }
+    if (wave == 0) diag_factor64(pan, Ac + tp_off(k, k), Wd + k * 256, k * 16, &s_bad);
     __syncthreads();
     if (s_bad) break;
     const double* W = Wd + k * 256;

@@ -265,6 +265,31 @@ def _accum_from_oracle(ctx, ref):
     return acc
 
 
+def _check_sigma(st, Sg, S1, Sold, S, T1, ref, info, tol=1e-9, singular=1e-12):
+    """Sigma_c after the M-step against the oracle.  The new Sigma_c is kept
+    only if it is positive definite (status 2 otherwise), and both sides must
+    decide alike, except where the candidate (S_c - T_c Cc_c^T) / N_c is
+    singular at rounding level (|smallest eigenvalue| <= 1e-12 of the
+    largest: a component with fewer effective frames than dimensions gives a
+    candidate that is singular in exact arithmetic, so FP64 rounding in T_c
+    decides).  There either decision is valid, and the Sigma_c left must be
+    the one that decision implies."""
+    C = len(st)
+    notpd_o = np.zeros(C, bool)
+    notpd_o[info["notpd"]] = True
+    notpd_g = st == 2
+    same = np.ones(C, bool)
+    for c in np.nonzero(notpd_o != notpd_g)[0]:
+        M = (S[c] - T1[c] @ ref["Cc"][c].T) / ref["N"][c]
+        M = 0.5 * (M + M.T)
+        lam = np.linalg.eigvalsh(M)
+        assert abs(lam[0]) <= singular * lam[-1], (c, lam[0], lam[-1])
+        assert relfro(Sg[c], Sold[c] if notpd_g[c] else M) <= tol
+        same[c] = False
+    assert relfro(Sg[same], S1[same]) <= tol
+    return np.nonzero(~same)[0].tolist()
+
+
 MSTEP_FORMS = {"registers": dict(mstep_global=0),
                "right-looking": dict(mstep_global=1, mstep_left=0),
                "left-looking": dict(mstep_global=1, mstep_left=1)}
@@ -288,9 +313,8 @@ def test_mstep_solve_and_objective_match_oracle(cfg1, form):
     Tg, Sg, pg, mug = [t.cpu().numpy() for t in ctx.get_tv()]
     st = status.cpu().numpy()
     assert sorted(np.nonzero(st == 1)[0].tolist()) == info["skipped"]
-    assert sorted(np.nonzero(st == 2)[0].tolist()) == info["notpd"]
     assert relfro(Tg, T1) <= 1e-9
-    assert relfro(Sg, S1) <= 1e-9
+    _check_sigma(st, Sg, S1, tv[1], S, T1, ref, info)
     obj_ref = oracle.objective(ref["N"], S, tv[1], e["ll_u"].sum())
     assert abs(obj.item() - obj_ref) <= 1e-9 * abs(obj_ref)
 
@@ -316,12 +340,12 @@ def test_mstep_solve_forms_match_oracle_at_larger_R(R, form):
     T1, S1, info = oracle.mstep(ref, S, tv[0], tv[1], update_sigma=True)
     Tg, Sg, _, _ = [t.cpu().numpy() for t in ctx.get_tv()]
     st = status.cpu().numpy()
-    print(f"R={R} {form}: T relfro {relfro(Tg, T1):.2e} Sigma relfro {relfro(Sg, S1):.2e} "
-          f"skipped {info['skipped']} not PD {info['notpd']}")
     assert sorted(np.nonzero(st == 1)[0].tolist()) == info["skipped"]
-    assert sorted(np.nonzero(st == 2)[0].tolist()) == info["notpd"]
     assert relfro(Tg, T1) <= 1e-9
-    assert relfro(Sg, S1) <= 1e-9
+    split = _check_sigma(st, Sg, S1, tv[1], S, T1, ref, info)
+    print(f"R={R} {form}: T relfro {relfro(Tg, T1):.2e} skipped {info['skipped']} not PD "
+          f"{info['notpd']} (GPU {np.nonzero(st == 2)[0].tolist()}; singular candidates "
+          f"decided differently {split})")
 
 
 @pytest.mark.parametrize("form", list(MSTEP_FORMS))
