@@ -76,56 +76,80 @@ __device__ __forceinline__ floatx4 mfma4(floatx4 a, floatx4 b, floatx4 c) {
   return c;
 }
 
-// Factors one symmetric 16 x 16 tile held in scr (16 x 17, row-major) in one
-// wave: C = G G^T, writes G^{-1} to dk (swizzled row-major), stores
-// sum log G_ii in *ld and returns the first non-positive pivot (1-based), 0
-// if none.  Lanes l and l + 16 m hold the same row l % 16 during the
-// factorisation; the inverse is formed column by column (lane l: column l).
-__device__ __forceinline__ int rr_factor_diag(float* scr, float* dk, double* ld) {
+// value of lane J of the lane's own 16-lane row (DPP row_newbcast:J)
+template <int J>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + J, 0xf, 0xf, false));
+}
+// value of lane src4 / 4
+__device__ __forceinline__ float lane_perm(int src4, float v) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(v)));
+}
+
+// Factors one symmetric 16 x 16 tile held in scr (16 x 17, row-major, lower
+// part used) in the registers of one wave: C = G G^T, writes G^{-1} to dk
+// (swizzled row-major), stores sum log G_ii in *ld and returns the first
+// non-positive pivot (1-based), 0 if none.  Lane (c, q) = (lane % 16,
+// lane / 16) holds rows 4 r + q (r < 4) of column c of the symmetric
+// trailing matrix and of X, the right-hand side of G W = I reduced
+// alongside.  Step j takes the pivot with a lane read, the column-j entries
+// of the lane's own rows with a broadcast inside each 16-lane row, and row j
+// (of the trailing matrix and of X) with a permute from the row group that
+// holds it; row j of G^{-1} is then final and stored.  Rows above the step
+// hold values that are never read again.
+__device__ __forceinline__ int rr_factor_diag(const float* scr, float* dk, double* ld) {
   int lane = threadIdx.x & 63;
   asm volatile("" : "+v"(lane));  // lane-dependent selects stay inside the call
-  const int l16 = lane & 15;
+  const int c = lane & 15, q = lane >> 4;
+  float a[4], x[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = 4 * r + q;
+    a[r] = scr[c <= i ? i * 17 + c : c * 17 + i];
+    x[r] = i == c ? 1.0f : 0.0f;
+  }
   int bad = 0;
   double prod = 1.0;  // product of the pivots G_jj^2 (each in FP32 range: no overflow)
-  {
-    float x[16];  // row l16 of the tile; entries right of the diagonal are not used
 #pragma unroll
-    for (int c = 0; c < 16; ++c) x[c] = scr[l16 * 17 + c];
+  for (int j = 0; j < 16; ++j) {
+    float piv = rl(a[j >> 2], 16 * (j & 3) + j);
+    if (!(piv > 0.0f) || !isfinite(piv)) {
+      if (bad == 0) bad = j + 1;
+      piv = 1.0f;
+    }
+    prod *= (double)piv;
+    const float ri = __builtin_amdgcn_rsqf(piv);  // 1 / G_jj
+    const float ri2 = ri * ri;
+    const int src4 = (16 * (j & 3) + c) * 4;
+    const float ajc = lane_perm(src4, a[j >> 2]);
+    const float xjc = lane_perm(src4, x[j >> 2]);
+    if (q == (j & 3)) dk[swz(j, c)] = x[j >> 2] * ri;
+    const float t = c > j ? ajc * ri2 : 0.0f;
+    const float u = xjc * ri2;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      float piv = rl(x[j], j);
-      if (!(piv > 0.0f) || !isfinite(piv)) {
-        if (bad == 0) bad = j + 1;
-        piv = 1.0f;
+    for (int r = 0; r < 4; ++r) {
+      float d;
+      switch (j) {  // the DPP control is an immediate
+        case 0: d = row_bcast<0>(a[r]); break;
+        case 1: d = row_bcast<1>(a[r]); break;
+        case 2: d = row_bcast<2>(a[r]); break;
+        case 3: d = row_bcast<3>(a[r]); break;
+        case 4: d = row_bcast<4>(a[r]); break;
+        case 5: d = row_bcast<5>(a[r]); break;
+        case 6: d = row_bcast<6>(a[r]); break;
+        case 7: d = row_bcast<7>(a[r]); break;
+        case 8: d = row_bcast<8>(a[r]); break;
+        case 9: d = row_bcast<9>(a[r]); break;
+        case 10: d = row_bcast<10>(a[r]); break;
+        case 11: d = row_bcast<11>(a[r]); break;
+        case 12: d = row_bcast<12>(a[r]); break;
+        case 13: d = row_bcast<13>(a[r]); break;
+        case 14: d = row_bcast<14>(a[r]); break;
+        default: d = row_bcast<15>(a[r]); break;
       }
-      prod *= (double)piv;
-      const float inv = __builtin_amdgcn_rsqf(piv);  // 1 / G_jj
-      x[j] *= inv;                                   // G_ij for lanes i > j
-      if (lane == 0) scr[j * 17 + 16] = inv;
-#pragma unroll
-      for (int c = j + 1; c < 16; ++c) x[c] = fmaf(-x[j], rl(x[j], c), x[c]);
+      a[r] = fmaf(-d, t, a[r]);
+      x[r] = fmaf(-d, u, x[r]);
     }
-    __builtin_amdgcn_wave_barrier();
-    if (lane < 16) {
-#pragma unroll
-      for (int c = 0; c < 16; ++c) scr[l16 * 17 + c] = x[c];
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  }
-  // column l16 of G^{-1}: y_i = (delta_i,l16 - sum_{m<i} G_im y_m) / G_ii, with
-  // G_im and 1 / G_ii read from LDS (every lane reads the same word)
-  float y[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    float t = (l16 == i) ? 1.0f : 0.0f;
-#pragma unroll
-    for (int m = 0; m < i; ++m) t = fmaf(-scr[i * 17 + m], y[m], t);
-    y[i] = t * scr[i * 17 + 16];
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) dk[swz(i, l16)] = y[i];
   }
   *ld = 0.5 * log(prod);  // sum log G_jj
   return bad;
