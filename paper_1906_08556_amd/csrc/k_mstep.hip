@@ -113,24 +113,49 @@ __device__ __noinline__ void sigma_update(int c, int D, int R, double Nc, const 
     Ms[e] = (S[(int64_t)c * Dp + packed_idx(lo, hi, D)] - 0.5 * (Cb[a * 64 + b] + Cb[b * 64 + a])) / Nc;
   }
   __syncthreads();
-  double* Lc = Cb;  // Cholesky scratch, D x D
-  for (int e = tid; e < D * D; e += nt) Lc[e] = Ms[e];
+  // positive definiteness: blocked Cholesky of Ms on 16 x 16 tiles in LDS
+  // (lower tiles, tile-packed, padded with the identity), the diagonal tiles
+  // factored in one wave's registers, panels and updates on MFMA
+  const int nbD = (D + 15) >> 4;  // <= 4
+  double* Pt = Cb;                // [10][256]
+  double* Wk = Cb + 10 * 256;     // [256] G_kk^{-1}
+  double* Lk = Wk + 256;          // [256] G_kk (not needed further)
+  for (int e = tid; e < nbD * (nbD + 1) / 2 * 256; e += nt) {
+    const int t = e >> 8, w = e & 255;
+    const int bi = t >= 6 ? 3 : t >= 3 ? 2 : t >= 1 ? 1 : 0, bj = t - bi * (bi + 1) / 2;
+    const int i = bi * 16 + (w >> 4), j = bj * 16 + (w & 15);
+    Pt[e] = (i < D && j < D) ? Ms[i * D + j] : (i == j ? 1.0 : 0.0);
+  }
   if (tid == 0) *s_bad = 0;
   __syncthreads();
-  for (int j = 0; j < D; ++j) {
-    const double djj = Lc[j * D + j];
-    if (!(djj > 0.0) || !isfinite(djj)) {
-      if (tid == 0) *s_bad = 1;
-      break;
+  for (int k = 0; k < nbD; ++k) {
+    if (wave == 0) diag_factor64(Pt + tp_off(k, k), Lk, Wk, 16 * k, s_bad);
+    __syncthreads();
+    if (*s_bad) break;
+    for (int it = k + 1 + wave; it < nbD; it += nw) {
+      double* At = Pt + tp_off(it, k);
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16_xyt([&](int i, int l) { return At[i * 16 + l]; },
+                      [&](int j, int l) { return Wk[j * 16 + l]; }, acc, 1.0);
+      __builtin_amdgcn_wave_barrier();  // the tile is read whole before it is replaced
+#pragma unroll
+      for (int r = 0; r < 4; ++r) At[(4 * r + q16) * 16 + l16] = acc[r];
     }
-    const double ljj = sqrt(djj);
     __syncthreads();
-    if (tid > j && tid < D) Lc[tid * D + j] /= ljj;
-    if (tid == j) Lc[j * D + j] = ljj;
-    __syncthreads();
-    if (tid > j && tid < D) {
-      const double lij = Lc[tid * D + j];
-      for (int k = j + 1; k <= tid; ++k) Lc[tid * D + k] -= lij * Lc[k * D + j];
+    const int m = nbD - k - 1;
+    for (int t = wave; t < m * (m + 1) / 2; t += nw) {
+      int ii, jj;
+      tri_decode(t, ii, jj);
+      double* Ct = Pt + tp_off(k + 1 + ii, k + 1 + jj);
+      const double* Pi = Pt + tp_off(k + 1 + ii, k);
+      const double* Pj = Pt + tp_off(k + 1 + jj, k);
+      doublex4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = Ct[(4 * r + q16) * 16 + l16];
+      acc = mma16_xyt([&](int i, int l) { return Pi[i * 16 + l]; },
+                      [&](int j, int l) { return Pj[j * 16 + l]; }, acc, -1.0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Ct[(4 * r + q16) * 16 + l16] = acc[r];
     }
     __syncthreads();
   }
