@@ -75,37 +75,18 @@ k_objective_finish(const double* __restrict__ part, int C, const double* __restr
   if (threadIdx.x == 0) out[0] = s + (ll_sum ? ll_sum[0] : 0.0);
 }
 
-// Sigma_c = sym((S_c - T_c Cc_c^T) / N_c), stored only if it is positive
-// definite (status 0; else status 2 and Sigma_c unchanged).  T_c Cc_c^T runs
-// on MFMA; called by all threads of the workgroup (any multiple of 64, at
-// least D), after T_c has been written.  LDS: big [4096 + D * D].
-__device__ __noinline__ void sigma_update(int c, int D, int R, double Nc, const double* __restrict__ Tc,
-                             const double* __restrict__ Ccc, const double* __restrict__ S,
-                             double* __restrict__ Sigma, double* big, int* s_bad,
-                             int* __restrict__ status) {
+// Sigma_c = sym((S_c - P) / N_c) with P = T_c Cc_c^T given in big[0..4096)
+// ([64][64], row-major), stored only if it is positive definite (status 0;
+// else status 2 and Sigma_c unchanged).  Called by all threads of the
+// workgroup (any multiple of 64, at least D) after P is complete.  LDS: big
+// [4096 + D * D].
+__device__ __noinline__ void sigma_finish(int c, int D, double Nc, const double* __restrict__ S,
+                                          double* __restrict__ Sigma, double* big, int* s_bad,
+                                          int* __restrict__ status) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int l16 = lane & 15, q16 = lane >> 4, nt = blockDim.x;
   double* Cb = big;          // [64][64] T_c Cc_c^T
   double* Ms = big + 4096;   // [D][D] candidate
-  for (int t = wave; t < 16; t += nw) {
-    const int ta = t >> 2, tb = t & 3;
-    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int r0 = 0; r0 < R; r0 += 16) {
-      acc = mma16_xyt(
-          [&](int i, int l) {
-            const int a = ta * 16 + i, r = r0 + l;
-            return (a < D && r < R) ? Tc[(int64_t)a * R + r] : 0.0;
-          },
-          [&](int j, int l) {
-            const int b = tb * 16 + j, r = r0 + l;
-            return (b < D && r < R) ? Ccc[(int64_t)b * R + r] : 0.0;
-          },
-          acc, 1.0);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Cb[(ta * 16 + 4 * r + q16) * 64 + tb * 16 + l16] = acc[r];
-  }
-  __syncthreads();
   const int Dp = D * (D + 1) / 2;
   for (int e = tid; e < D * D; e += nt) {
     const int a = e / D, b = e - a * D;
@@ -167,6 +148,38 @@ __device__ __noinline__ void sigma_update(int c, int D, int R, double Nc, const 
   for (int e = tid; e < D * D; e += nt) Sigma[(int64_t)c * D * D + e] = Ms[e];
   if (tid == 0) status[c] = 0;
 }
+
+// The Sigma_c update after T_c has been written to device memory:
+// T_c Cc_c^T on MFMA into big[0..4096), then sigma_finish.
+__device__ __noinline__ void sigma_update(int c, int D, int R, double Nc, const double* __restrict__ Tc,
+                             const double* __restrict__ Ccc, const double* __restrict__ S,
+                             double* __restrict__ Sigma, double* big, int* s_bad,
+                             int* __restrict__ status) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int l16 = lane & 15, q16 = lane >> 4;
+  double* Cb = big;          // [64][64] T_c Cc_c^T
+  for (int t = wave; t < 16; t += nw) {
+    const int ta = t >> 2, tb = t & 3;
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < R; r0 += 16) {
+      acc = mma16_xyt(
+          [&](int i, int l) {
+            const int a = ta * 16 + i, r = r0 + l;
+            return (a < D && r < R) ? Tc[(int64_t)a * R + r] : 0.0;
+          },
+          [&](int j, int l) {
+            const int b = tb * 16 + j, r = r0 + l;
+            return (b < D && r < R) ? Ccc[(int64_t)b * R + r] : 0.0;
+          },
+          acc, 1.0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Cb[(ta * 16 + 4 * r + q16) * 64 + tb * 16 + l16] = acc[r];
+  }
+  __syncthreads();
+  sigma_finish(c, D, Nc, S, Sigma, big, s_bad, status);
+}
+
 
 // One workgroup per component: blocked FP64 Cholesky of A_c on MFMA
 // (chol_tp64), T_c^T = A_c^{-1} Cc_c^T with all D right-hand sides at once
@@ -449,8 +462,43 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
     if (tid == 0) status[c] = 0;
     return;
   }
+  // ---- T_c Cc_c^T from the X fragments: wave (ib, db) sums over its row
+  //      blocks for the output tiles (db, tb), tb < 4 (A operand: the slot's
+  //      fragment as it stands, B operand: Cc_c^T read from device memory);
+  //      the halves ib = 0 and 1 are added in LDS in a fixed order.  pan and
+  //      Wd are free after the backward solve.
+  doublex4 pc[4];
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb) pc[tb] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < MR_NS; ++s) {
+    const int i = ib + 2 * s;
+    if (i < nb) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * i + 4 * r + q16;
+        double cv[4];
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb) {
+          const int b = 16 * tb + l16;
+          cv[tb] = (row < R && b < D) ? Ccc[(int64_t)b * R + row] : 0.0;
+        }
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb)
+          pc[tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bt[s][r], cv[tb], pc[tb], 0, 0, 0);
+      }
+    }
+  }
+  double* Pb = sm + (ib ? 8192 : 0);
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Pb[(16 * db + 4 * r + q16) * 64 + 16 * tb + l16] = pc[tb][r];
+  }
   __syncthreads();
-  sigma_update(c, D, R, Nc, Tc, Ccc, S, Sigma, sm, &s_bad, status);
+  for (int e = tid; e < 4096; e += MR_NW * 64) sm[e] += sm[8192 + e];
+  __syncthreads();
+  sigma_finish(c, D, Nc, S, Sigma, sm, &s_bad, status);
 }
 
 // Minimum-divergence set-up, one workgroup of 256 threads:
