@@ -303,56 +303,109 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
     }
     __syncthreads();
     const int ro = l16 * 16 + 4 * q16;
-    for (int it0 = wave; it0 < m1; it0 += 2 * MR_NW) {
-      const int itA = it0, itB = it0 + MR_NW < m1 ? it0 + MR_NW : it0;
-      const double* At = Ac + tp_off(k + itA, k);
-      const double* Bt = Ac + tp_off(k + itB, k);
-      doublex4 accA, accB;
+    if (m1 > MR_NW) {
+      // two rows per wave, independent accumulators (a wave with one row
+      // computes it twice and stores it once)
+      for (int it0 = wave; it0 < m1; it0 += 2 * MR_NW) {
+        const int itA = it0, itB = it0 + MR_NW < m1 ? it0 + MR_NW : it0;
+        const double* At = Ac + tp_off(k + itA, k);
+        const double* Bt = Ac + tp_off(k + itB, k);
+        doublex4 accA, accB;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        accA[r] = At[(4 * r + q16) * 16 + l16];
-        accB[r] = Bt[(4 * r + q16) * 16 + l16];
+        for (int r = 0; r < 4; ++r) {
+          accA[r] = At[(4 * r + q16) * 16 + l16];
+          accB[r] = Bt[(4 * r + q16) * 16 + l16];
+        }
+        double2 a0[2], b0[2], a1[2], b1[2], a2[2], b2[2];
+        auto load = [&](int j, double2 (&ga)[2], double2 (&gb)[2]) {
+          const double2* Ga = reinterpret_cast<const double2*>(Ac + tp_off(k + itA, j) + ro);
+          const double2* Gb = reinterpret_cast<const double2*>(Ac + tp_off(k + itB, j) + ro);
+          ga[0] = Ga[0];
+          ga[1] = Ga[1];
+          gb[0] = Gb[0];
+          gb[1] = Gb[1];
+        };
+        auto step = [&](int j, const double2 (&ga)[2], const double2 (&gb)[2]) {
+          const double2* Kr = reinterpret_cast<const double2*>(rowk + j * 256 + ro);
+          const double2 k0 = Kr[0], k1 = Kr[1];
+          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[0].x, k0.x, accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[0].x, k0.x, accB, 0, 0, 0);
+          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[0].y, k0.y, accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[0].y, k0.y, accB, 0, 0, 0);
+          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[1].x, k1.x, accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[1].x, k1.x, accB, 0, 0, 0);
+          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[1].y, k1.y, accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[1].y, k1.y, accB, 0, 0, 0);
+        };
+        if (k > 0) load(0, a0, b0);
+        if (k > 1) load(1, a1, b1);
+        if (k > 2) load(2, a2, b2);
+        for (int j = 0; j < k; j += 3) {
+          step(j, a0, b0);
+          if (j + 3 < k) load(j + 3, a0, b0);
+          if (j + 1 < k) {
+            step(j + 1, a1, b1);
+            if (j + 4 < k) load(j + 4, a1, b1);
+          }
+          if (j + 2 < k) {
+            step(j + 2, a2, b2);
+            if (j + 5 < k) load(j + 5, a2, b2);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          pan[itA * 256 + (4 * r + q16) * 16 + l16] = accA[r];
+          if (itB != itA) pan[itB * 256 + (4 * r + q16) * 16 + l16] = accB[r];
+        }
       }
-      double2 a0[2], b0[2], a1[2], b1[2], a2[2], b2[2];
-      auto load = [&](int j, double2 (&ga)[2], double2 (&gb)[2]) {
-        const double2* Ga = reinterpret_cast<const double2*>(Ac + tp_off(k + itA, j) + ro);
-        const double2* Gb = reinterpret_cast<const double2*>(Ac + tp_off(k + itB, j) + ro);
-        ga[0] = Ga[0];
-        ga[1] = Ga[1];
-        gb[0] = Gb[0];
-        gb[1] = Gb[1];
+    } else {
+      // at most one row per wave: the waves of row it = w % m1 split its
+      // sum over j into equal ranges; the partial sums of the waves w >= m1
+      // go to the free panel slots MR_NW + w and are added in a fixed order
+      const int it = wave % m1, p = wave / m1, P = (MR_NW - 1 - it) / m1 + 1;
+      const int j0 = p * k / P, j1 = (p + 1) * k / P;
+      const double* At = Ac + tp_off(k + it, k);
+      doublex4 acc0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc0[r] = p == 0 ? At[(4 * r + q16) * 16 + l16] : 0.0;
+      double2 g0[2], g1[2], g2[2];
+      auto load1 = [&](int j, double2 (&g)[2]) {
+        const double2* G = reinterpret_cast<const double2*>(Ac + tp_off(k + it, j) + ro);
+        g[0] = G[0];
+        g[1] = G[1];
       };
-      auto step = [&](int j, const double2 (&ga)[2], const double2 (&gb)[2]) {
+      auto step1 = [&](int j, const double2 (&g)[2], doublex4& acc) {
         const double2* Kr = reinterpret_cast<const double2*>(rowk + j * 256 + ro);
         const double2 k0 = Kr[0], k1 = Kr[1];
-        accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[0].x, k0.x, accA, 0, 0, 0);
-        accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[0].x, k0.x, accB, 0, 0, 0);
-        accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[0].y, k0.y, accA, 0, 0, 0);
-        accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[0].y, k0.y, accB, 0, 0, 0);
-        accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[1].x, k1.x, accA, 0, 0, 0);
-        accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[1].x, k1.x, accB, 0, 0, 0);
-        accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[1].y, k1.y, accA, 0, 0, 0);
-        accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[1].y, k1.y, accB, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-g[0].x, k0.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-g[0].y, k0.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-g[1].x, k1.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-g[1].y, k1.y, acc, 0, 0, 0);
       };
-      if (k > 0) load(0, a0, b0);
-      if (k > 1) load(1, a1, b1);
-      if (k > 2) load(2, a2, b2);
-      for (int j = 0; j < k; j += 3) {
-        step(j, a0, b0);
-        if (j + 3 < k) load(j + 3, a0, b0);
-        if (j + 1 < k) {
-          step(j + 1, a1, b1);
-          if (j + 4 < k) load(j + 4, a1, b1);
+      if (j0 < j1) load1(j0, g0);
+      if (j0 + 1 < j1) load1(j0 + 1, g1);
+      if (j0 + 2 < j1) load1(j0 + 2, g2);
+      for (int j = j0; j < j1; j += 3) {
+        step1(j, g0, acc0);
+        if (j + 3 < j1) load1(j + 3, g0);
+        if (j + 1 < j1) {
+          step1(j + 1, g1, acc0);
+          if (j + 4 < j1) load1(j + 4, g1);
         }
-        if (j + 2 < k) {
-          step(j + 2, a2, b2);
-          if (j + 5 < k) load(j + 5, a2, b2);
+        if (j + 2 < j1) {
+          step1(j + 2, g2, acc0);
+          if (j + 5 < j1) load1(j + 5, g2);
         }
       }
+      double* dst = pan + (p == 0 ? it : MR_NW + wave) * 256;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        pan[itA * 256 + (4 * r + q16) * 16 + l16] = accA[r];
-        if (itB != itA) pan[itB * 256 + (4 * r + q16) * 16 + l16] = accB[r];
+      for (int r = 0; r < 4; ++r) dst[(4 * r + q16) * 16 + l16] = acc0[r];
+      __syncthreads();
+      for (int e = tid; e < m1 * 256; e += MR_NW * 64) {
+        const int t = e >> 8, np = (MR_NW - 1 - t) / m1 + 1;
+        double v = pan[e];
+        for (int q = 1; q < np; ++q) v += pan[(MR_NW + t + q * m1) * 256 + (e & 255)];
+        pan[e] = v;
       }
     }
     __syncthreads();
