@@ -246,7 +246,7 @@ k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
 constexpr int MR_NW = 8;
 constexpr int MR_NS = 13;     // right-hand-side slots per wave (nb <= 26)
 constexpr int MR_MAXNB = 25;  // R <= 400
-constexpr size_t MR_LDS_DOUBLES = 2 * MR_MAXNB * 256 + 16 * 64 + (MR_MAXNB - 1) * 256;
+constexpr size_t MR_LDS_DOUBLES = 2 * MR_MAXNB * 256 + 16 * 64 + (MR_MAXNB - 1) * 256 + 256;
 
 __global__ void __launch_bounds__(MR_NW * 64)
 k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
@@ -255,9 +255,11 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
            double* __restrict__ Sigma, int* __restrict__ status, int* __restrict__ err) {
   extern __shared__ double sm[];
   double* pan = sm;                     // [nb][256] block column k (tile it = row k + it)
-  double* Wd = sm + MR_MAXNB * 256;     // [nb][256] G_kk^{-1}, row-major
-  double* zb = Wd + MR_MAXNB * 256;     // [16][64] Z_k, then X_k
+  double* pan2 = sm + MR_MAXNB * 256;   // [nb][256] G_(k+it),k for the forward update; the
+                                        // inverse W_j of every finished step j < k in tile nb-1-j
+  double* zb = pan2 + MR_MAXNB * 256;   // [16][64] Z_k, then X_k
   double* rowk = zb + 16 * 64;          // [nb - 1][256] block row k of G
+  double* wk = rowk + (MR_MAXNB - 1) * 256;  // [256] W_k = G_kk^{-1}, row-major
   __shared__ int s_bad;
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -301,7 +303,10 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
       reinterpret_cast<double2*>(rowk + j * 256)[w] =
           reinterpret_cast<const double2*>(Ac + tp_off(k, j))[w];
     }
-    __syncthreads();
+    __syncthreads();  // also: every wave is past the forward update of step k - 1
+    if (k > 0) {
+      for (int e = tid; e < 256; e += MR_NW * 64) pan2[(nb - k) * 256 + e] = wk[e];
+    }
     const int ro = l16 * 16 + 4 * q16;
     if (m1 > MR_NW) {
       // two rows per wave, independent accumulators (a wave with one row
@@ -409,23 +414,22 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
       }
     }
     __syncthreads();
-    if (wave == 0) diag_factor64(pan, Ac + tp_off(k, k), Wd + k * 256, k * 16, &s_bad);
+    if (wave == 0) diag_factor64(pan, Ac + tp_off(k, k), wk, k * 16, &s_bad);
     __syncthreads();
     if (s_bad) break;
-    const double* W = Wd + k * 256;
-    // ---- panel G_(k+it),k = pan_it W^T (to LDS and device memory), and
+    const double* W = wk;
+    // ---- panel G_(k+it),k = pan_it W^T (to pan2 and device memory), and
     //      Z_k = W B_k by the owners of row block k
     for (int it = 1 + wave; it < m1; it += MR_NW) {
-      double* Pt = pan + it * 256;
+      const double* Pt = pan + it * 256;
       doublex4 acc = {0.0, 0.0, 0.0, 0.0};
       acc = mma16_xyt([&](int i, int l) { return Pt[i * 16 + l]; },
                       [&](int j, int l) { return W[j * 16 + l]; }, acc, 1.0);
-      __builtin_amdgcn_wave_barrier();  // the tile is read whole before it is replaced
       double* Gt = Ac + tp_off(k + it, k);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         Gt[(4 * r + q16) * 16 + l16] = acc[r];
-        Pt[(4 * r + q16) * 16 + l16] = acc[r];
+        pan2[it * 256 + (4 * r + q16) * 16 + l16] = acc[r];
       }
     }
     if (ib == (k & 1)) {
@@ -443,20 +447,24 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
       }
     }
     __syncthreads();
-    // ---- B_i -= G_ik Z_k for i > k
+    // ---- B_i -= G_ik Z_k for i > k.  No barrier after it: the next step
+    //      writes pan and rowk, not pan2 or zb, until its first barrier.
 #pragma unroll
     for (int s = 0; s < MR_NS; ++s) {
       const int i = ib + 2 * s;
       if (i > k && i < nb) {
-        const double* Gt = pan + (i - k) * 256;
+        const double* Gt = pan2 + (i - k) * 256;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           bt[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-Gt[eo + 4 * q], zb[(4 * q + q16) * 64 + dcol],
                                                        bt[s], 0, 0, 0);
       }
     }
-    __syncthreads();
   }
+  if (!s_bad) {
+    for (int e = tid; e < 256; e += MR_NW * 64) pan2[e] = wk[e];  // W_(nb-1) to tile 0
+  }
+  __syncthreads();
   if (s_bad) {
     if (tid == 0) {
       status[c] = 3;
@@ -466,7 +474,7 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
   }
   // ---- backward solve G^T X = Z: X_k = W_k^T Z_k, then Z_i -= G_ki^T X_k (i < k)
   for (int k = nb - 1; k >= 0; --k) {
-    const double* W = Wd + k * 256;
+    const double* W = pan2 + (nb - 1 - k) * 256;
     if (ib == (k & 1)) {
 #pragma unroll
       for (int s = 0; s < MR_NS; ++s) {
@@ -519,7 +527,7 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
   //      blocks for the output tiles (db, tb), tb < 4 (A operand: the slot's
   //      fragment as it stands, B operand: Cc_c^T read from device memory);
   //      the halves ib = 0 and 1 are added in LDS in a fixed order.  pan and
-  //      Wd are free after the backward solve.
+  //      pan2 are free after the backward solve.
   doublex4 pc[4];
 #pragma unroll
   for (int tb = 0; tb < 4; ++tb) pc[tb] = doublex4{0.0, 0.0, 0.0, 0.0};
