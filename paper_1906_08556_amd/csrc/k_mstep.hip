@@ -246,7 +246,7 @@ k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
 constexpr int MR_NW = 8;
 constexpr int MR_NS = 13;     // right-hand-side slots per wave (nb <= 26)
 constexpr int MR_MAXNB = 25;  // R <= 400
-constexpr size_t MR_LDS_DOUBLES = 2 * MR_MAXNB * 256 + 16 * 64 + (MR_MAXNB - 1) * 256 + 256;
+constexpr size_t MR_LDS_DOUBLES = 2 * MR_MAXNB * 256 + 16 * 64 + (MR_MAXNB - 1) * 256;
 
 __global__ void __launch_bounds__(MR_NW * 64)
 k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
@@ -255,11 +255,11 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
            double* __restrict__ Sigma, int* __restrict__ status, int* __restrict__ err) {
   extern __shared__ double sm[];
   double* pan = sm;                     // [nb][256] block column k (tile it = row k + it)
-  double* pan2 = sm + MR_MAXNB * 256;   // [nb][256] G_(k+it),k for the forward update; the
-                                        // inverse W_j of every finished step j < k in tile nb-1-j
+  double* pan2 = sm + MR_MAXNB * 256;   // [nb][256] G_(k+it),k (tiles 1 .. nb-k-1) for the
+                                        // forward update, and W_j = G_jj^{-1} (row-major) of
+                                        // every step j <= k in tile wtile(j)
   double* zb = pan2 + MR_MAXNB * 256;   // [16][64] Z_k, then X_k
   double* rowk = zb + 16 * 64;          // [nb - 1][256] block row k of G
-  double* wk = rowk + (MR_MAXNB - 1) * 256;  // [256] W_k = G_kk^{-1}, row-major
   __shared__ int s_bad;
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -290,23 +290,19 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
   __syncthreads();
 
   const int eo = l16 * 16 + q16;  // element (l16, 4 q + q16) of a row-major tile is at eo + 4 q
+  // pan2 tile of W_k: tile 0 for k = 0, else nb - k (the panel tiles of step
+  // k are 1 .. nb - k - 1, and W_k is written after step k - 1's last use
+  // of tile nb - k)
+  const auto wtile = [nb](int k) { return k == 0 ? 0 : nb - k; };
   for (int k = 0; k < nb; ++k) {
     const int m1 = nb - k;  // tiles of block column k, the diagonal one first
-    // ---- block column k: A_(k+it),k - sum_{j<k} G_(k+it),j G_k,j^T.  Block
-    //      row k of G (shared by every row's sum) is staged in LDS first; each
-    //      wave takes two rows and keeps the tiles of the next three j in
-    //      flight while it multiplies the current one (contraction index
-    //      4 q16 + q: lane (l16, q16) reads four consecutive doubles of row
-    //      l16 of a tile)
-    for (int e = tid; e < k * 128; e += MR_NW * 64) {
-      const int j = e >> 7, w = e & 127;
-      reinterpret_cast<double2*>(rowk + j * 256)[w] =
-          reinterpret_cast<const double2*>(Ac + tp_off(k, j))[w];
-    }
-    __syncthreads();  // also: every wave is past the forward update of step k - 1
-    if (k > 0) {
-      for (int e = tid; e < 256; e += MR_NW * 64) pan2[(nb - k) * 256 + e] = wk[e];
-    }
+    // ---- block column k: A_(k+it),k - sum_{j<k} G_(k+it),j G_k,j^T, with
+    //      block row k of G (shared by every row's sum) already in rowk; each
+    //      wave keeps the tiles of the next three j in flight while it
+    //      multiplies the current one (contraction index 4 q16 + q: lane
+    //      (l16, q16) reads four consecutive doubles of row l16 of a tile).
+    //      No barrier before it: it writes pan only, and the previous step's
+    //      forward update reads pan2 and zb.
     const int ro = l16 * 16 + 4 * q16;
     if (m1 > MR_NW) {
       // two rows per wave, independent accumulators (a wave with one row
@@ -414,11 +410,23 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
       }
     }
     __syncthreads();
-    if (wave == 0) diag_factor64(pan, Ac + tp_off(k, k), wk, k * 16, &s_bad);
+    // W_k to pan2 tile wtile(k), which no panel tile of this or a later
+    // step uses; the other waves stage block row k + 1 of G (the tiles of
+    // the finished columns; tile k comes from the panel below)
+    if (wave == 0) {
+      diag_factor64(pan, Ac + tp_off(k, k), pan2 + wtile(k) * 256, k * 16, &s_bad);
+    } else if (k + 1 < nb) {
+      for (int e = tid - 64; e < k * 128; e += (MR_NW - 1) * 64) {
+        const int j = e >> 7, w = e & 127;
+        reinterpret_cast<double2*>(rowk + j * 256)[w] =
+            reinterpret_cast<const double2*>(Ac + tp_off(k + 1, j))[w];
+      }
+    }
     __syncthreads();
     if (s_bad) break;
-    const double* W = wk;
-    // ---- panel G_(k+it),k = pan_it W^T (to pan2 and device memory), and
+    const double* W = pan2 + wtile(k) * 256;
+    // ---- panel G_(k+it),k = pan_it W^T (to pan2 and device memory; tile 1
+    //      also to rowk as the last tile of the next block row), and
     //      Z_k = W B_k by the owners of row block k
     for (int it = 1 + wave; it < m1; it += MR_NW) {
       const double* Pt = pan + it * 256;
@@ -430,6 +438,7 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
       for (int r = 0; r < 4; ++r) {
         Gt[(4 * r + q16) * 16 + l16] = acc[r];
         pan2[it * 256 + (4 * r + q16) * 16 + l16] = acc[r];
+        if (it == 1) rowk[k * 256 + (4 * r + q16) * 16 + l16] = acc[r];
       }
     }
     if (ib == (k & 1)) {
@@ -448,7 +457,7 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
     }
     __syncthreads();
     // ---- B_i -= G_ik Z_k for i > k.  No barrier after it: the next step
-    //      writes pan and rowk, not pan2 or zb, until its first barrier.
+    //      writes only pan until its first barrier.
 #pragma unroll
     for (int s = 0; s < MR_NS; ++s) {
       const int i = ib + 2 * s;
@@ -461,9 +470,6 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
       }
     }
   }
-  if (!s_bad) {
-    for (int e = tid; e < 256; e += MR_NW * 64) pan2[e] = wk[e];  // W_(nb-1) to tile 0
-  }
   __syncthreads();
   if (s_bad) {
     if (tid == 0) {
@@ -474,7 +480,7 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
   }
   // ---- backward solve G^T X = Z: X_k = W_k^T Z_k, then Z_i -= G_ki^T X_k (i < k)
   for (int k = nb - 1; k >= 0; --k) {
-    const double* W = pan2 + (nb - 1 - k) * 256;
+    const double* W = pan2 + wtile(k) * 256;
     if (ib == (k & 1)) {
 #pragma unroll
       for (int s = 0; s < MR_NS; ++s) {
