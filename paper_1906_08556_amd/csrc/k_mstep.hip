@@ -237,12 +237,15 @@ k_mstep_solve(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
 // tiles of column block w % 4 and row blocks i = w / 4 + 2 s (s < 13) as
 // FP64 MFMA fragments.  Block column k of the Cholesky factor is formed
 // left-looking in LDS (A_ik - sum_{j<k} G_ij G_kj^T from the finished
-// columns in device memory), its diagonal tile factored and inverted, the
-// column written once, and the forward-solve step for block row k runs on
-// it while it is still in LDS: Z_k = G_kk^{-1} B_k, B_i -= G_ik Z_k (i > k).
+// columns in device memory, block row k of G staged in LDS), its diagonal
+// tile factored and inverted in one wave's registers while the other waves
+// stage block row k + 1, the column written once, and the forward-solve step
+// for block row k runs on it while it is still in LDS: Z_k = G_kk^{-1} B_k,
+// then B_i -= G_ik Z_k (i > k), which overlaps the next column's formation.
 // The backward solve G^T X = Z then reads each tile of G once.  The
 // right-hand sides never leave the registers between the read of Cc_c and
-// the write of T_c.
+// the write of T_c, and T_c Cc_c^T for the Sigma update is formed from them
+// there.
 constexpr int MR_NW = 8;
 constexpr int MR_NS = 13;     // right-hand-side slots per wave (nb <= 26)
 constexpr int MR_MAXNB = 25;  // R <= 400
