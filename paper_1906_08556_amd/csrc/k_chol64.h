@@ -188,9 +188,13 @@ __device__ inline double row_bcast64(double v) {
 // 16-lane row, and row j (of the trailing matrix and of X) with a permute
 // from the row group that holds it; row j of W is then final and stored.
 // Rows above the step hold values that are never read again.  Sets *s_bad
-// to 1 + the first row whose pivot was not positive.
+// to 1 + the first row whose pivot was not positive.  CM: dg and W are
+// stored column-major (element (r, c) at 16 c + r), else row-major; Akk is
+// row-major.
+template <bool CM = false>
 __device__ inline void diag_factor64(const double* dg, double* __restrict__ Akk,
                                      double* __restrict__ W, int row0, int* s_bad) {
+  auto ix = [](int r, int cc) { return CM ? cc * 16 + r : r * 16 + cc; };
   // the lane-dependent selects below stay inside the call (hoisting them out
   // of a caller's step loop would hold dozens of scalar masks live)
   int lane = threadIdx.x & 63;
@@ -200,7 +204,7 @@ __device__ inline void diag_factor64(const double* dg, double* __restrict__ Akk,
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = 4 * r + q;
-    a[r] = dg[c <= i ? i * 16 + c : c * 16 + i];
+    a[r] = dg[c <= i ? ix(i, c) : ix(c, i)];
     x[r] = i == c ? 1.0 : 0.0;
   }
   double my_rinv = 0.0;  // 1 / G_cc
@@ -220,7 +224,7 @@ __device__ inline void diag_factor64(const double* dg, double* __restrict__ Akk,
     const int src4 = (16 * ((j) & 3) + c) * 4;                                      \
     const double ajc = lane_perm64(src4, a[(j) >> 2]);                              \
     const double xjc = lane_perm64(src4, x[(j) >> 2]);                              \
-    if (q == ((j) & 3)) W[(j) * 16 + c] = x[(j) >> 2] * ri;                         \
+    if (q == ((j) & 3)) W[ix((j), c)] = x[(j) >> 2] * ri;                           \
     const double t = c > (j) ? ajc * ri2 : 0.0;                                     \
     const double u = xjc * ri2;                                                     \
     _Pragma("unroll") for (int r = 0; r < 4; ++r) {                                 \

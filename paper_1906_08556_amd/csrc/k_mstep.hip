@@ -292,7 +292,10 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
   if (tid == 0) s_bad = 0;
   __syncthreads();
 
-  const int eo = l16 * 16 + q16;  // element (l16, 4 q + q16) of a row-major tile is at eo + 4 q
+  // The LDS tiles (pan, pan2, rowk) are stored column-major (element (r, c)
+  // at 16 c + r), so that the reads of an MFMA operand fragment (row l16 of
+  // the tile in lane l16) fall in consecutive words; tiles in device memory
+  // are row-major.
   // pan2 tile of W_k: tile 0 for k = 0, else nb - k (the panel tiles of step
   // k are 1 .. nb - k - 1, and W_k is written after step k - 1's last use
   // of tile nb - k)
@@ -330,16 +333,16 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
           gb[1] = Gb[1];
         };
         auto step = [&](int j, const double2 (&ga)[2], const double2 (&gb)[2]) {
-          const double2* Kr = reinterpret_cast<const double2*>(rowk + j * 256 + ro);
-          const double2 k0 = Kr[0], k1 = Kr[1];
-          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[0].x, k0.x, accA, 0, 0, 0);
-          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[0].x, k0.x, accB, 0, 0, 0);
-          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[0].y, k0.y, accA, 0, 0, 0);
-          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[0].y, k0.y, accB, 0, 0, 0);
-          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[1].x, k1.x, accA, 0, 0, 0);
-          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[1].x, k1.x, accB, 0, 0, 0);
-          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[1].y, k1.y, accA, 0, 0, 0);
-          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[1].y, k1.y, accB, 0, 0, 0);
+          const double* Kr = rowk + j * 256 + 64 * q16 + l16;  // G_kj[l16][4 q16 + n] at Kr[16 n]
+          const double k0 = Kr[0], k1 = Kr[16], k2 = Kr[32], k3 = Kr[48];
+          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[0].x, k0, accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[0].x, k0, accB, 0, 0, 0);
+          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[0].y, k1, accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[0].y, k1, accB, 0, 0, 0);
+          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[1].x, k2, accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[1].x, k2, accB, 0, 0, 0);
+          accA = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[1].y, k3, accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f64_16x16x4f64(-gb[1].y, k3, accB, 0, 0, 0);
         };
         if (k > 0) load(0, a0, b0);
         if (k > 1) load(1, a1, b1);
@@ -358,8 +361,8 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          pan[itA * 256 + (4 * r + q16) * 16 + l16] = accA[r];
-          if (itB != itA) pan[itB * 256 + (4 * r + q16) * 16 + l16] = accB[r];
+          pan[itA * 256 + l16 * 16 + 4 * r + q16] = accA[r];
+          if (itB != itA) pan[itB * 256 + l16 * 16 + 4 * r + q16] = accB[r];
         }
       }
     } else {
@@ -379,12 +382,12 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
         g[1] = G[1];
       };
       auto step1 = [&](int j, const double2 (&g)[2], doublex4& acc) {
-        const double2* Kr = reinterpret_cast<const double2*>(rowk + j * 256 + ro);
-        const double2 k0 = Kr[0], k1 = Kr[1];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-g[0].x, k0.x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-g[0].y, k0.y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-g[1].x, k1.x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-g[1].y, k1.y, acc, 0, 0, 0);
+        const double* Kr = rowk + j * 256 + 64 * q16 + l16;  // G_kj[l16][4 q16 + n] at Kr[16 n]
+        const double k0 = Kr[0], k1 = Kr[16], k2 = Kr[32], k3 = Kr[48];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-g[0].x, k0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-g[0].y, k1, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-g[1].x, k2, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-g[1].y, k3, acc, 0, 0, 0);
       };
       if (j0 < j1) load1(j0, g0);
       if (j0 + 1 < j1) load1(j0 + 1, g1);
@@ -403,7 +406,7 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
       }
       double* dst = pan + (p == 0 ? it : MR_NW + wave) * 256;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dst[(4 * r + q16) * 16 + l16] = acc0[r];
+      for (int r = 0; r < 4; ++r) dst[l16 * 16 + 4 * r + q16] = acc0[r];
       __syncthreads();
       for (int e = tid; e < m1 * 256; e += MR_NW * 64) {
         const int t = e >> 8, np = (MR_NW - 1 - t) / m1 + 1;
@@ -417,12 +420,14 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
     // step uses; the other waves stage block row k + 1 of G (the tiles of
     // the finished columns; tile k comes from the panel below)
     if (wave == 0) {
-      diag_factor64(pan, Ac + tp_off(k, k), pan2 + wtile(k) * 256, k * 16, &s_bad);
+      diag_factor64<true>(pan, Ac + tp_off(k, k), pan2 + wtile(k) * 256, k * 16, &s_bad);
     } else if (k + 1 < nb) {
       for (int e = tid - 64; e < k * 128; e += (MR_NW - 1) * 64) {
         const int j = e >> 7, w = e & 127;
-        reinterpret_cast<double2*>(rowk + j * 256)[w] =
-            reinterpret_cast<const double2*>(Ac + tp_off(k + 1, j))[w];
+        const double2 v = reinterpret_cast<const double2*>(Ac + tp_off(k + 1, j))[w];
+        const int r = w >> 3, cc = 2 * (w & 7);  // elements (r, cc), (r, cc + 1)
+        rowk[j * 256 + cc * 16 + r] = v.x;
+        rowk[j * 256 + cc * 16 + 16 + r] = v.y;
       }
     }
     __syncthreads();
@@ -434,14 +439,14 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
     for (int it = 1 + wave; it < m1; it += MR_NW) {
       const double* Pt = pan + it * 256;
       doublex4 acc = {0.0, 0.0, 0.0, 0.0};
-      acc = mma16_xyt([&](int i, int l) { return Pt[i * 16 + l]; },
-                      [&](int j, int l) { return W[j * 16 + l]; }, acc, 1.0);
+      acc = mma16_xyt([&](int i, int l) { return Pt[l * 16 + i]; },
+                      [&](int j, int l) { return W[l * 16 + j]; }, acc, 1.0);
       double* Gt = Ac + tp_off(k + it, k);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         Gt[(4 * r + q16) * 16 + l16] = acc[r];
-        pan2[it * 256 + (4 * r + q16) * 16 + l16] = acc[r];
-        if (it == 1) rowk[k * 256 + (4 * r + q16) * 16 + l16] = acc[r];
+        pan2[it * 256 + l16 * 16 + 4 * r + q16] = acc[r];
+        if (it == 1) rowk[k * 256 + l16 * 16 + 4 * r + q16] = acc[r];
       }
     }
     if (ib == (k & 1)) {
@@ -451,7 +456,7 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
           doublex4 z = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int q = 0; q < 4; ++q)
-            z = __builtin_amdgcn_mfma_f64_16x16x4f64(W[l16 * 16 + 4 * q + q16], bt[s][q], z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f64_16x16x4f64(W[(4 * q + q16) * 16 + l16], bt[s][q], z, 0, 0, 0);
           bt[s] = z;
 #pragma unroll
           for (int r = 0; r < 4; ++r) zb[(4 * r + q16) * 64 + dcol] = z[r];
@@ -468,7 +473,7 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
         const double* Gt = pan2 + (i - k) * 256;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          bt[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-Gt[eo + 4 * q], zb[(4 * q + q16) * 64 + dcol],
+          bt[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-Gt[(4 * q + q16) * 16 + l16], zb[(4 * q + q16) * 64 + dcol],
                                                        bt[s], 0, 0, 0);
       }
     }
@@ -491,7 +496,7 @@ k_mstep_rr(int C, int D, int R, int nb, int64_t TP, double* __restrict__ A,
           doublex4 x = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int q = 0; q < 4; ++q)
-            x = __builtin_amdgcn_mfma_f64_16x16x4f64(W[(4 * q + q16) * 16 + l16], bt[s][q], x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f64_16x16x4f64(W[l16 * 16 + 4 * q + q16], bt[s][q], x, 0, 0, 0);
           bt[s] = x;
 #pragma unroll
           for (int r = 0; r < 4; ++r) zb[(4 * r + q16) * 64 + dcol] = x[r];
