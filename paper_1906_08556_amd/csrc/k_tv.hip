@@ -32,11 +32,12 @@ k_tv_prep(const double* __restrict__ T, const double* __restrict__ Sigma, int D,
           double* __restrict__ logdet, int* __restrict__ err) {
   extern __shared__ double sm[];
   double* A = sm;           // Sigma -> L, later P
-  double* Li = sm + D * D;  // L^{-1}
+  double* Li = sm + D * D;  // L^{-1}, then 64 zeros
   __shared__ int bad;
   __shared__ double ld;
   const int c = blockIdx.x, t = threadIdx.x;
   for (int i = t; i < D * D; i += 256) A[i] = Sigma[(size_t)c * D * D + i];
+  if (t < 64) Li[D * D + t] = 0.0;
   if (t == 0) bad = 0;
   __syncthreads();
   for (int j = 0; j < D; ++j) {
@@ -92,7 +93,10 @@ k_tv_prep(const double* __restrict__ T, const double* __restrict__ Sigma, int D,
   for (int e = t; e < D * D; e += 256) Psig[(size_t)c * D * D + e] = A[e];
   // Y = L^{-1} T_c, V = P T_c: thread t holds column r of T_c in registers
   // (D <= 63) and forms all D rows of that column from the LDS copies of
-  // L^{-1} and P (same summation order over k as a plain loop)
+  // L^{-1} and P (same summation order over k as a plain loop).  The k loop
+  // has no test: tk[k] = 0 for k >= D and L^{-1} is zero above the diagonal,
+  // so the extra terms add exact zeros (the reads past row d stay inside the
+  // two matrices and the 64 zeros after them).
   const double* Tc = T + (size_t)c * D * R;
   for (int r = t; r < R; r += 256) {
     double tk[64];
@@ -100,12 +104,12 @@ k_tv_prep(const double* __restrict__ T, const double* __restrict__ Sigma, int D,
     for (int k = 0; k < 64; ++k) tk[k] = (k < D) ? Tc[(size_t)k * R + r] : 0.0;
     for (int d = 0; d < D; ++d) {
       double y = 0.0, v = 0.0;
+      const double* Lr = Li + d * D;
+      const double* Pr = A + d * D;
 #pragma unroll
       for (int k = 0; k < 64; ++k) {
-        if (k < D) {
-          if (k <= d) y += Li[d * D + k] * tk[k];
-          v += A[d * D + k] * tk[k];
-        }
+        y += Lr[k] * tk[k];
+        v += Pr[k] * tk[k];
       }
       Y32[((size_t)c * D + d) * R + r] = (float)y;
       V32[((size_t)c * D + d) * R + r] = (float)v;
@@ -550,7 +554,7 @@ __global__ void k_colsums_fin(const double* __restrict__ part, int64_t U, int C,
 }  // namespace
 
 void launch_tv_prep(ivx_ctx* ctx, hipStream_t s) {
-  const size_t lds = 2 * sizeof(double) * ctx->D * ctx->D;
+  const size_t lds = sizeof(double) * (2 * ctx->D * ctx->D + 64);
   k_tv_prep<<<ctx->C, 256, lds, s>>>(ctx->T, ctx->Sigma, ctx->D, ctx->R, ctx->Y32, ctx->V32,
                                      ctx->Psig, ctx->sig_logdet, ctx->dev_err);
 }
