@@ -210,3 +210,20 @@ def test_bf16_forward_is_close_to_the_exact_network_and_exact_on_representable_v
     np.testing.assert_array_equal(h1, e1)
     np.testing.assert_array_equal(h2, e2)
     np.testing.assert_array_equal(z16, e2 @ W3.T + b[2])
+
+
+def test_feature_stats_and_standardise_on_a_hand_example():
+    """Population (not sample) standard deviation, per feature column; the
+    standardised columns have mean 0 and population variance 1."""
+    X = np.array([[1.0, 2.0, -4.0], [3.0, 6.0, -4.0 + 1e-3], [5.0, 10.0, -4.0 - 1e-3]])
+    mean, std = oracle.feature_stats(X)
+    np.testing.assert_allclose(mean, [3.0, 6.0, -4.0], rtol=0, atol=1e-15)
+    # column 1: deviations -2, 0, 2 -> population variance 8/3 (the sample
+    # variance would be 4); column 2 is column 1 doubled; column 3: 0, +-1e-3
+    np.testing.assert_allclose(std, [np.sqrt(8.0 / 3.0), 2.0 * np.sqrt(8.0 / 3.0),
+                                     np.sqrt(2e-6 / 3.0)], rtol=1e-9)
+    Z = oracle.standardise(X, mean, std)
+    np.testing.assert_allclose(Z[:, 0], [-np.sqrt(1.5), 0.0, np.sqrt(1.5)], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(Z[:, 0], Z[:, 1], rtol=1e-12, atol=1e-15)  # scale-free
+    np.testing.assert_allclose(Z.mean(axis=0), 0.0, atol=1e-12)
+    np.testing.assert_allclose((Z ** 2).mean(axis=0), 1.0, rtol=1e-9)
